@@ -1,0 +1,132 @@
+"""Oracle for the multi-camera depth path (TEST INFRASTRUCTURE ONLY).
+
+Only ``tests/``, the smoke check and the bench's CPU-baseline leg may import
+this package.  It is a plain FP64 brute-force reference written from the
+paper (Sec. 3.2.2, Algorithm 1; sensor model in Sec. 1, Sec. 4.1 and Table
+6) and shares no code with the GPU renderer.  The C part is built by
+``oracle/build.py`` (gcc, OpenMP) into ``oracle/liboracle.so``.
+"""
+import ctypes
+import os
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+FLAG_EDGE, FLAG_FAR, FLAG_TIE = 1, 2, 4
+POST_NOISE, POST_DROPOUT, POST_LATENCY = 1, 2, 4
+
+
+class PostParams(ctypes.Structure):
+    _fields_ = [("seed", ctypes.c_uint64),
+                ("sigma_abs", ctypes.c_float), ("sigma_rel", ctypes.c_float),
+                ("p_drop", ctypes.c_float), ("near", ctypes.c_float),
+                ("far", ctypes.c_float), ("fill", ctypes.c_float),
+                ("lat_min", ctypes.c_int32), ("lat_max", ctypes.c_int32),
+                ("flags", ctypes.c_uint32)]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            from . import build
+            build.build()
+        _lib = ctypes.CDLL(_LIB_PATH)
+        _lib.oracle_render.restype = ctypes.c_int
+        _lib.oracle_post.restype = ctypes.c_int
+        _lib.oracle_latency.restype = ctypes.c_int
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
+
+
+def _f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def render(terrain, link_tri, link_off, link_pos, link_quat, cam_pos, cam_quat, intr,
+           W, H, far, depth_mode=0, rays=None, K=8):
+    """Brute-force FP64 render.
+
+    terrain [T,3,3]; link_tri [LT,3,3] with link_off [B+1]; link_pos [E,B,3];
+    link_quat [E,B,4]; cam_pos [E,C,3]; cam_quat [E,C,4]; intr [E,C,4].
+    rays: optional int64 linear pixel ids into [E,C,H,W].
+    Returns dict(depth f64, inst i32, tri i32, flags i32, cand i32 [n,K,2],
+    cand_depth f64 [n,K]); flat over ``rays`` (or all pixels).
+    """
+    terrain = _f32(terrain).reshape(-1, 9)
+    link_tri = _f32(link_tri).reshape(-1, 9)
+    link_off = np.ascontiguousarray(link_off, dtype=np.int64)
+    B = int(link_off.shape[0] - 1)
+    cam_pos = _f32(cam_pos)
+    E, C = cam_pos.shape[0], cam_pos.shape[1]
+    link_pos = _f32(link_pos).reshape(E, B, 3)
+    link_quat = _f32(link_quat).reshape(E, B, 4)
+    cam_quat = _f32(cam_quat).reshape(E, C, 4)
+    intr = _f32(intr).reshape(E, C, 4)
+    if rays is not None:
+        rays = np.ascontiguousarray(rays, dtype=np.int64)
+        n = rays.shape[0]
+    else:
+        n = E * C * H * W
+    depth = np.empty(n, np.float64)
+    inst = np.empty(n, np.int32)
+    tri = np.empty(n, np.int32)
+    flags = np.empty(n, np.int32)
+    cand = np.empty((n, K, 2), np.int32)
+    cand_d = np.empty((n, K), np.float64)
+    rc = lib().oracle_render(
+        _p(terrain), ctypes.c_int64(terrain.shape[0]), _p(link_tri), _p(link_off), ctypes.c_int(B),
+        _p(link_pos), _p(link_quat), _p(cam_pos), _p(cam_quat), _p(intr),
+        ctypes.c_int(E), ctypes.c_int(C), ctypes.c_int(W), ctypes.c_int(H),
+        ctypes.c_double(far), ctypes.c_int(depth_mode),
+        _p(rays), ctypes.c_int64(n),
+        _p(depth), _p(inst), _p(tri), _p(flags), _p(cand), _p(cand_d), ctypes.c_int(K))
+    if rc != 0:
+        raise ValueError("oracle_render: bad arguments")
+    return dict(depth=depth, inst=inst, tri=tri, flags=flags, cand=cand, cand_depth=cand_d)
+
+
+def philox(ctr, key):
+    """Philox4x32-10 of one 4-word counter and 2-word key -> 4 uint32 words."""
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros(4, np.uint32)
+    lib().oracle_philox4x32_10(_p(c), _p(k), _p(out))
+    return out
+
+
+def make_params(seed=0, sigma_abs=0.0, sigma_rel=0.0, p_drop=0.0, near=0.05, far=3.0,
+                fill=0.0, lat_min=0, lat_max=0, flags=None):
+    if flags is None:
+        flags = (POST_NOISE if (sigma_abs or sigma_rel) else 0) | \
+                (POST_DROPOUT if p_drop else 0) | (POST_LATENCY if lat_max else 0)
+    return PostParams(seed, sigma_abs, sigma_rel, p_drop, near, far, fill, lat_min, lat_max, flags)
+
+
+def latency(params, cam_uid, step):
+    return lib().oracle_latency(ctypes.byref(params), ctypes.c_uint32(cam_uid), ctypes.c_uint64(step))
+
+
+def post(depth, inst, params, s0=0, cam_uid=None):
+    """Sensor model over frames depth/inst [S,E,C,H,W] starting at step s0.
+
+    Returns (out f64 [S,E,C,H,W], drop u8 [S,E,C,H,W], lat u8 [S,E,C]).
+    """
+    depth = _f32(depth)
+    inst = np.ascontiguousarray(inst, dtype=np.int32)
+    S, E, C, H, W = depth.shape
+    out = np.empty(depth.shape, np.float64)
+    drop = np.empty(depth.shape, np.uint8)
+    lat = np.empty((S, E, C), np.uint8)
+    uid = None if cam_uid is None else np.ascontiguousarray(cam_uid, dtype=np.uint32)
+    rc = lib().oracle_post(_p(depth), _p(inst), ctypes.c_int(E), ctypes.c_int(C), ctypes.c_int(H),
+                           ctypes.c_int(W), ctypes.c_int(S), ctypes.c_uint64(s0), _p(uid),
+                           ctypes.byref(params), _p(out), _p(drop), _p(lat))
+    if rc != 0:
+        raise ValueError("oracle_post: bad arguments")
+    return out, drop, lat

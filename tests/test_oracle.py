@@ -1,0 +1,372 @@
+"""Pins for the FP64 oracle against facts fixed outside the oracle itself.
+
+Closed-form depths of the terrain profile (plane, 20 degree slope, treads,
+risers), the published Philox known-answer vectors, PyTorch's independent
+Philox source, SciPy rotations for the body transform, convex-solid
+watertightness, permutation invariance and sensor-model statistics.
+"""
+import math
+import os
+import subprocess
+import numpy as np
+import pytest
+from scipy.spatial.transform import Rotation
+
+import oracle
+import scenegen as sg
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------------------
+# helpers
+# ---------------------------------------------------------------------------
+
+def look_quat(direction, up=(0.0, 0.0, 1.0)):
+    """Quaternion (x,y,z,w) of a camera whose optical z is ``direction``."""
+    z = np.asarray(direction, float)
+    z = z / np.linalg.norm(z)
+    up = np.asarray(up, float)
+    if abs(np.dot(up, z)) > 0.99:
+        up = np.array([1.0, 0.0, 0.0])
+    x = np.cross(z, up)
+    x /= np.linalg.norm(x)
+    y = np.cross(z, x)
+    return Rotation.from_matrix(np.stack([x, y, z], 1)).as_quat()
+
+
+def render_points(tris, cams, far=10.0, link=None):
+    """One 1x1 camera per env at cams[i] = (pos, dir): the ray goes along dir."""
+    E = len(cams)
+    pos = np.array([[c[0]] for c in cams], np.float32)
+    quat = np.array([[look_quat(c[1])] for c in cams], np.float32)
+    intr = np.tile(np.array([1.0, 1.0, 0.5, 0.5], np.float32), (E, 1, 1))
+    if link is None:
+        lt, lo = np.zeros((0, 3, 3), np.float32), np.zeros(1, np.int64)
+        lp, lq = np.zeros((E, 0, 3), np.float32), np.zeros((E, 0, 4), np.float32)
+    else:
+        lt, lo, lp, lq = link
+    return oracle.render(tris, lt, lo, lp, lq, pos, quat, intr, 1, 1, far)
+
+
+def profile_closed_form(w):
+    """Independent closed-form depth for every pixel of the small plain case.
+
+    The ray is built from the optical axes stated for this camera (1 m above
+    the ground, pitched 45 degrees down), not from its quaternion.
+    Returns (depth, piece index, near_boundary flag).
+    """
+    terr = w["terrain_obj"]
+    K = w["intr"][0, 0].astype(np.float64)
+    s2 = 1.0 / math.sqrt(2.0)
+    ax = np.array([0.0, -1.0, 0.0])
+    ay = np.array([-s2, 0.0, -s2])
+    az = np.array([s2, 0.0, -s2])
+    o = np.array([0.0, 0.0, 1.0])
+    H, W = w["H"], w["W"]
+    depth = np.full((H, W), w["far"])
+    piece = np.full((H, W), -1)
+    nearb = np.zeros((H, W), bool)
+    for y in range(H):
+        for x in range(W):
+            a = (x + 0.5 - K[2]) / K[0]
+            b = (y + 0.5 - K[3]) / K[1]
+            d = az + a * ax + b * ay
+            best = math.inf
+            for k, (xa, za, xb, zb, yh) in enumerate(terr.pieces()):
+                n = np.array([-(zb - za), 0.0, xb - xa])
+                den = n @ d
+                if den == 0.0:
+                    continue
+                lam = n @ (np.array([xa, 0.0, za]) - o) / den
+                if not (lam > 0):
+                    continue
+                P = o + lam * d
+                L2 = (xb - xa) ** 2 + (zb - za) ** 2
+                s = ((P[0] - xa) * (xb - xa) + (P[2] - za) * (zb - za)) / L2
+                L = math.sqrt(L2)
+                if -1e-12 <= s <= 1 + 1e-12 and abs(P[1]) <= yh and lam < best:
+                    best = lam
+                    piece[y, x] = k
+                    nearb[y, x] = min(s * L, (1 - s) * L, yh - abs(P[1])) < 1e-6
+            if best <= w["far"]:
+                depth[y, x] = best
+    return depth, piece, nearb
+
+
+# ---------------------------------------------------------------------------
+# ray generation, intersection and depth semantics
+# ---------------------------------------------------------------------------
+
+def small_render(depth_mode=0):
+    w = sg.small_plain_case()
+    r = oracle.render(w["terrain"], w["link_tri"], w["link_off"], w["link_pos"][0],
+                      w["link_quat"][0], w["cam_pos"], w["cam_quat"], w["intr"],
+                      w["W"], w["H"], w["far"], depth_mode=depth_mode)
+    return w, r
+
+
+def test_plane_closed_form_rows():
+    """Ground z = 0 seen from h = 1 m at 45 deg: depth(y) = sqrt(2) h / (1 + b)."""
+    w, r = small_render()
+    d = r["depth"].reshape(w["H"], w["W"])
+    fy, cy = float(w["intr"][0, 0, 1]), float(w["intr"][0, 0, 3])
+    checked = 0
+    for y in range(w["H"]):
+        b = (y + 0.5 - cy) / fy
+        lam = math.sqrt(2.0) / (1.0 + b)
+        xhit = lam * (1.0 / math.sqrt(2.0) - b / math.sqrt(2.0))  # along +x
+        if xhit < 0.79:
+            assert np.all(np.abs(d[y] - lam) <= 1e-6), (y, d[y] - lam)
+            checked += 1
+    assert checked >= 6
+
+
+def test_profile_closed_form_all_pixels():
+    w, r = small_render()
+    d = r["depth"].reshape(w["H"], w["W"])
+    cf, piece, nearb = profile_closed_form(w)
+    ok = ~nearb
+    assert np.max(np.abs(d - cf)[ok]) <= 1e-6
+    # the image must see the plane, the slope, a riser and a tread
+    seen = set(np.unique(piece[ok]).tolist())
+    assert {0, 1}.issubset(seen)            # ground and 20 degree slope
+    assert seen & {3, 5, 7}                  # a riser
+    assert seen & {4, 6, 8}                  # a tread or the top landing
+    assert np.all(r["inst"] == 0)            # terrain is inst B = 0 with no robot
+
+
+def test_range_mode_scales_planar_depth():
+    w, rp = small_render(0)
+    _, rr = small_render(1)
+    K = w["intr"][0, 0].astype(np.float64)
+    y, x = np.divmod(np.arange(w["H"] * w["W"]), w["W"])
+    a = (x + 0.5 - K[2]) / K[0]
+    b = (y + 0.5 - K[3]) / K[1]
+    norm = np.sqrt(1 + a * a + b * b)
+    hit = rr["depth"] < w["far"] - 1e-9
+    np.testing.assert_allclose(rr["depth"][hit], rp["depth"][hit] * norm[hit], rtol=1e-12)
+
+
+def test_single_triangle_and_far_plane():
+    tri = np.array([[[-1, -1, 0], [3, -1, 0], [-1, 3, 0]]], np.float32)
+    r = render_points(tri, [((0, 0, 2), (0, 0, -1)), ((0, 0, 5), (0, 0, -1))], far=3.0)
+    assert r["depth"][0] == pytest.approx(2.0, abs=1e-12) and r["inst"][0] == 0 and r["tri"][0] == 0
+    assert r["depth"][1] == 3.0 and r["inst"][1] == -1 and r["tri"][1] == -1
+    # a hit exactly behind the origin does not count (lambda > 0)
+    r = render_points(tri, [((0, 0, -1), (0, 0, -1))], far=3.0)
+    assert r["inst"][0] == -1
+
+
+def test_tie_rules():
+    A = [[-1, -1, 0], [3, -1, 0], [-1, 3, 0]]
+    tri = np.array([A, A], np.float32)
+    r = render_points(tri, [((0, 0, 2), (0, 0, -1))])
+    assert r["tri"][0] == 0
+    # the same triangle as link 0 (identity pose) and as terrain: the link wins
+    link = (np.array([A], np.float32), np.array([0, 1], np.int64),
+            np.zeros((1, 1, 3), np.float32), np.array([[[0, 0, 0, 1]]], np.float32))
+    r = render_points(np.array([A], np.float32), [((0, 0, 2), (0, 0, -1))], link=link)
+    assert r["inst"][0] == 0 and r["tri"][0] == 0
+    assert r["flags"][0] & oracle.FLAG_TIE
+
+
+def random_scene(seed, n_tri=40, E=2, C=2, W=9, H=7):
+    rng = np.random.default_rng(seed)
+    c = rng.uniform(-1, 1, (n_tri, 1, 3)) * [2, 2, 0.3] + [2.0, 0, 0]
+    terr = (c + rng.normal(0, 0.4, (n_tri, 3, 3))).astype(np.float32)
+    V, T = sg.octasphere(3)
+    link = (V[T] * 0.35).astype(np.float32)
+    lp = rng.uniform(-0.3, 0.3, (E, 1, 3)).astype(np.float32) + np.float32([1.2, 0, 0.3])
+    lq = rng.normal(size=(E, 1, 4)).astype(np.float32)
+    cp = np.zeros((E, C, 3), np.float32) + np.float32([0, 0, 1.0])
+    cq = np.array([[look_quat((1.0, rng.uniform(-.3, .3), -0.6)) for _ in range(C)] for _ in range(E)],
+                  np.float32)
+    intr = np.tile(np.float32([6, 6, W / 2, H / 2]), (E, C, 1))
+    return terr, link, lp, lq, cp, cq, intr, W, H
+
+
+def test_permutation_invariance():
+    terr, link, lp, lq, cp, cq, intr, W, H = random_scene(1)
+    off = np.array([0, link.shape[0]], np.int64)
+    r0 = oracle.render(terr, link, off, lp, lq, cp, cq, intr, W, H, 5.0)
+    perm = np.random.default_rng(2).permutation(terr.shape[0])
+    r1 = oracle.render(terr[perm], link, off, lp, lq, cp, cq, intr, W, H, 5.0)
+    assert np.array_equal(r0["depth"], r1["depth"])
+    assert np.array_equal(r0["inst"], r1["inst"])
+    terr_hit = r0["inst"] == 1
+    assert terr_hit.sum() > 10 and (r0["inst"] == 0).sum() > 5
+    assert np.array_equal(r0["tri"][terr_hit], perm[r1["tri"][terr_hit]])
+
+
+def test_body_transform_matches_world_placement():
+    """A posed link equals its triangles placed in the world by SciPy's rotation."""
+    terr, link, lp, lq, cp, cq, intr, W, H = random_scene(3, n_tri=1)
+    E = lp.shape[0]
+    empty = np.zeros((0, 3, 3), np.float32)
+    off = np.array([0, link.shape[0]], np.int64)
+    r_link = oracle.render(empty, link, off, lp, lq, cp, cq, intr, W, H, 5.0)
+    for e in range(E):
+        R = Rotation.from_quat(lq[e, 0].astype(np.float64)).as_matrix()
+        world = (link.astype(np.float64) @ R.T + lp[e, 0]).astype(np.float64)
+        sl = slice(e * 2 * W * H, (e + 1) * 2 * W * H)
+        r_w = oracle.render(world, np.zeros((0, 3, 3), np.float32), np.zeros(1, np.int64),
+                            np.zeros((1, 0, 3)), np.zeros((1, 0, 4)), cp[e:e + 1], cq[e:e + 1],
+                            intr[e:e + 1], W, H, 5.0)
+        hit = r_w["inst"] >= 0
+        assert hit.sum() > 5
+        # world vertices were rounded to float32, so allow that rounding only
+        assert np.max(np.abs(r_w["depth"] - r_link["depth"][sl])) < 2e-6
+        same = (r_w["flags"] == 0) & (r_link["flags"][sl] == 0)
+        assert np.array_equal(r_w["tri"][same], r_link["tri"][sl][same])
+
+
+def test_quaternion_sign_invariance():
+    terr, link, lp, lq, cp, cq, intr, W, H = random_scene(4)
+    off = np.array([0, link.shape[0]], np.int64)
+    a = oracle.render(terr, link, off, lp, lq, cp, cq, intr, W, H, 5.0)
+    b = oracle.render(terr, link, off, lp, -lq, cp, -cq, intr, W, H, 5.0)
+    assert np.array_equal(a["inst"], b["inst"]) and np.array_equal(a["tri"], b["tri"])
+    assert np.max(np.abs(a["depth"] - b["depth"])) < 1e-12
+
+
+def test_watertight_closed_convex_mesh():
+    """Rays aimed at every vertex and edge midpoint of a convex closed mesh hit it
+    at the aimed point (the solid is convex, so that point is the first hit)."""
+    V, T = sg.octasphere(3)
+    tris = V[T].astype(np.float32)
+    Vf = tris.reshape(-1, 3).astype(np.float64)
+    targets = {tuple(v) for v in Vf}
+    for t in tris.astype(np.float64):
+        for i in range(3):
+            targets.add(tuple(0.5 * (t[i] + t[(i + 1) % 3])))
+    targets = np.array(sorted(targets))
+    cams = [(3.0 * p / np.linalg.norm(p), -p) for p in targets]
+    r = render_points(tris, cams, far=10.0)
+    assert np.all(r["inst"] == 0)
+    expect = np.array([np.linalg.norm(3.0 * p / np.linalg.norm(p) - p) for p in targets])
+    assert np.max(np.abs(r["depth"] - expect)) < 1e-5
+    assert np.mean((r["flags"] & oracle.FLAG_EDGE) > 0) > 0.99
+
+
+# ---------------------------------------------------------------------------
+# counter-based generator
+# ---------------------------------------------------------------------------
+
+def test_philox_known_answers():
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "philox4x32_10_kat.txt"))
+            if l.strip() and not l.startswith("#")]
+    assert len(rows) == 3
+    for row in rows:
+        v = [int(x, 16) for x in row]
+        assert oracle.philox(v[0:4], v[4:6]).tolist() == v[6:10]
+
+
+TORCH_PHILOX_PROBE = r"""
+#include <ATen/core/PhiloxRNGEngine.h>
+#include <cstdio>
+#include <cstdlib>
+int main(int argc, char** argv) {
+  for (int i = 1; i + 2 < argc; i += 3) {
+    unsigned long long seed = strtoull(argv[i], 0, 0), sub = strtoull(argv[i+1], 0, 0),
+                       off = strtoull(argv[i+2], 0, 0);
+    at::Philox4_32 eng(seed, sub, off);
+    unsigned a = eng(), b = eng(), c = eng(), d = eng();
+    printf("%u %u %u %u\n", a, b, c, d);
+  }
+}
+"""
+
+
+def test_philox_matches_pytorch_source(tmp_path):
+    """PyTorch ships an independent Philox4x32-10 (header source); compare words.
+
+    at::Philox4_32(seed, subsequence, offset) encrypts the counter
+    (offset_lo, offset_hi, subsequence_lo, subsequence_hi) with key (seed_lo, seed_hi).
+    """
+    import torch
+    inc = os.path.join(os.path.dirname(torch.__file__), "include")
+    src = tmp_path / "probe.cpp"
+    exe = tmp_path / "probe"
+    src.write_text(TORCH_PHILOX_PROBE)
+    subprocess.check_call(["g++", "-O1", "-std=c++17", f"-I{inc}", str(src), "-o", str(exe)])
+    rng = np.random.default_rng(7)
+    cases = [(int(rng.integers(0, 2**63)), int(rng.integers(0, 2**63)), int(rng.integers(0, 2**63)))
+             for _ in range(20)]
+    args = [str(x) for c in cases for x in c]
+    out = subprocess.check_output([str(exe)] + args).decode().split("\n")
+    for (seed, sub, off), line in zip(cases, out):
+        ctr = [off & 0xFFFFFFFF, off >> 32, sub & 0xFFFFFFFF, sub >> 32]
+        key = [seed & 0xFFFFFFFF, seed >> 32]
+        assert oracle.philox(ctr, key).tolist() == [int(x) for x in line.split()]
+
+
+# ---------------------------------------------------------------------------
+# sensor model
+# ---------------------------------------------------------------------------
+
+def test_post_identity_when_everything_off():
+    depth, inst = sg.synthetic_frames(2, 2, 5, 7, 3)
+    p = oracle.make_params(seed=5, near=0.05, far=3.0)
+    out, drop, lat = oracle.post(depth, inst, p)
+    near, far = float(np.float32(0.05)), float(np.float32(3.0))  # parameters are FP32
+    expect = np.where(inst >= 0, np.clip(depth.astype(np.float64), near, far), far)
+    assert np.array_equal(out, expect)
+    assert not drop.any() and not lat.any()
+
+
+def test_post_dropout_rate_and_fill():
+    depth, inst = sg.synthetic_frames(4, 2, 48, 64, 4)
+    p = oracle.make_params(seed=11, p_drop=0.02, fill=-1.0)
+    out, drop, _ = oracle.post(depth, inst, p)
+    n = drop.size
+    rate = drop.mean()
+    assert abs(rate - 0.02) < 5 * math.sqrt(0.02 * 0.98 / n)
+    assert np.all(out[drop == 1] == -1.0)
+    p0 = oracle.make_params(seed=11, p_drop=0.0, flags=oracle.POST_DROPOUT)
+    assert not oracle.post(depth, inst, p0)[1].any()
+    p1 = oracle.make_params(seed=11, p_drop=1.0)
+    assert oracle.post(depth, inst, p1)[1].all()
+
+
+def test_post_noise_statistics():
+    S, E, C, H, W = 2, 4, 2, 48, 64
+    depth = np.full((S, E, C, H, W), 1.5, np.float32)
+    inst = np.zeros((S, E, C, H, W), np.int32)
+    p = oracle.make_params(seed=3, sigma_abs=0.01, near=0.05, far=3.0)
+    out, _, _ = oracle.post(depth, inst, p)
+    g = (out - 1.5) / 0.01
+    n = g.size
+    assert abs(g.mean()) < 5 / math.sqrt(n)
+    assert abs(g.var() - 1.0) < 5 * math.sqrt(2.0 / n)
+    # kurtosis of a Gaussian is 3
+    assert abs(np.mean(g ** 4) / g.var() ** 2 - 3.0) < 0.1
+    # relative noise scales with depth
+    p2 = oracle.make_params(seed=3, sigma_rel=0.1, near=0.0, far=100.0)
+    out2, _, _ = oracle.post(depth, inst, p2)
+    assert abs(np.std(out2 - 1.5) / 0.15 - 1.0) < 0.02
+    # misses get no noise
+    inst[:] = -1
+    out3, _, _ = oracle.post(depth, inst, p)
+    assert np.all(out3 == 3.0)
+
+
+def test_post_latency_semantics_and_histogram():
+    S, E, C, H, W = 12, 3, 2, 2, 3
+    vals = 0.5 + 0.1 * np.arange(S)
+    depth = np.broadcast_to(vals[:, None, None, None, None], (S, E, C, H, W)).astype(np.float32).copy()
+    inst = np.zeros((S, E, C, H, W), np.int32)
+    s0 = 40
+    p = oracle.make_params(seed=9, lat_min=1, lat_max=3)
+    out, _, lat = oracle.post(depth, inst, p, s0=s0)
+    for si in range(S):
+        for ec in range(E * C):
+            k = int(lat[si].ravel()[ec])
+            assert 1 <= k <= 3
+            src = max(si - k, 0)
+            assert np.all(out[si].reshape(E * C, -1)[ec] == np.float64(np.float32(vals[src])))
+    ks = np.array([oracle.latency(p, u, s) for u in range(200) for s in range(30)])
+    counts = np.bincount(ks, minlength=4)[1:]
+    expect = ks.size / 3
+    chi2 = np.sum((counts - expect) ** 2 / expect)
+    assert chi2 < 13.8  # chi-square, 2 dof, p = 0.001
