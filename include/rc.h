@@ -1,0 +1,224 @@
+/*
+ * rc.h - multi-camera depth ray casting for massively parallel robot
+ * environments on AMD Instinct MI355X (gfx950).
+ *
+ * The operation (paper Sec. 3.2.2 and Algorithm 1, "Multi-Depth Ray Casting
+ * Kernel"): for every environment e, camera c and pixel (x, y), cast the
+ * camera ray against the environment's posed robot link meshes and one
+ * shared static terrain mesh and report the closest hit clipped by a far
+ * plane; then apply the sensor model the paper names (latency, noise and
+ * dropout: Sec. 1, Sec. 4.1, Table 6).
+ *
+ * Conventions shared by every call:
+ *  - Pointers named in a struct or argument as "device" must point to device
+ *    memory of the current HIP device; "host" pointers to host memory.  All
+ *    arrays are C-contiguous, little endian, with the shapes given.
+ *  - The library never allocates device memory.  Every call that needs
+ *    device storage takes a caller-owned workspace whose size the matching
+ *    rc_*_size query returns; the workspace must be 256-byte aligned.
+ *  - Calls are asynchronous on the given stream (a hipStream_t passed as
+ *    void*, NULL = the null stream) unless stated otherwise.  Inputs must stay
+ *    valid until the stream reaches the call; outputs are valid after it.
+ *  - Every call validates its arguments on the host before it enqueues
+ *    anything; an error leaves outputs untouched.  No C++ exception crosses
+ *    this interface.  rc_last_error() gives the text of the last error of
+ *    the calling thread.
+ *  - Frames: quaternions are (x, y, z, w) and rotate local vectors to world;
+ *    they are normalised before use.  A camera's optical frame has x right,
+ *    y down, z forward.  Intrinsics are (fx, fy, cx, cy) in pixels; pixel
+ *    (x, y) looks through (x + 0.5, y + 0.5).
+ *  - Ids: inst = b in [0, n_links) for link b, inst = n_links for the
+ *    terrain, -1 for a miss; tri is the triangle's index in the mesh it came
+ *    from (link-local index for links, input index for the terrain), -1 for
+ *    a miss.  A miss reports depth = far plane.
+ */
+#ifndef RC_H
+#define RC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t rc_status;
+#define RC_OK 0
+#define RC_ERR_INVALID_ARG (-1)  /* bad argument, nothing enqueued */
+#define RC_ERR_WORKSPACE (-2)    /* workspace too small or misaligned */
+#define RC_ERR_DEVICE (-3)       /* a HIP call failed; see rc_last_error() */
+#define RC_ERR_STATE (-4)        /* call out of order (e.g. a skipped step) */
+#define RC_ERR_UNSUPPORTED (-5)  /* valid input the library cannot handle */
+
+typedef void* rc_stream; /* hipStream_t */
+typedef struct rc_scene rc_scene;
+typedef struct rc_post rc_post;
+
+/* Library version as 10000 * major + 100 * minor + patch. */
+int32_t rc_version(void);
+/* Static text for a status code. */
+const char* rc_status_string(rc_status st);
+/* Text of the last error on the calling thread ("" if none). */
+const char* rc_last_error(void);
+
+/* ---------------------------------------------------------------------
+ * Static terrain (Algorithm 1's M_terrain, shared by all environments).
+ * ------------------------------------------------------------------- */
+
+/* Workspace bytes rc_scene_create needs for n_tri >= 1 terrain triangles. */
+rc_status rc_scene_size(int64_t n_tri, size_t* ws_bytes);
+
+/* Build the terrain's bounding volume hierarchy (a linear BVH over 63-bit
+ * Morton codes, LDS radix sort, bottom-up boxes) into `ws`, and create the
+ * scene handle (host memory, owned by the caller until rc_scene_destroy).
+ *   tri  device float [n_tri][3][3]: world-frame vertices (m).  Not kept:
+ *        it may be freed once `stream` has passed this call.
+ *   ws   device, ws_bytes >= rc_scene_size(n_tri); must outlive the scene.
+ * Synchronises `stream` once (to check the hierarchy depth).  Errors:
+ * INVALID_ARG (n_tri < 1 or > 2^31 - 2, NULL pointers), WORKSPACE,
+ * UNSUPPORTED (a hierarchy deeper than 64 levels), DEVICE. */
+rc_status rc_scene_create(const float* tri, int64_t n_tri, void* ws, size_t ws_bytes,
+                          rc_stream stream, rc_scene** out);
+
+/* Release the handle (not the caller's workspaces). NULL is a no-op. */
+rc_status rc_scene_destroy(rc_scene* scene);
+
+/* ---------------------------------------------------------------------
+ * Robot body meshes ({M_b}, kept canonical in their local frames, Sec. 3.2.2).
+ * ------------------------------------------------------------------- */
+
+/* Workspace bytes for n_links meshes; tri_offset host int64 [n_links + 1],
+ * tri_offset[0] = 0, non-decreasing, each mesh >= 1 triangle. */
+rc_status rc_robot_size(const int64_t* tri_offset, int32_t n_links, size_t* ws_bytes);
+
+/* Build one hierarchy per link in its local frame into `ws` and attach them
+ * to the scene (replacing any earlier set).  The meshes are shared by every
+ * environment; only poses are per environment.
+ *   link_tri   device float [tri_offset[n_links]][3][3], link-local (m)
+ *   tri_offset host int64 [n_links + 1]
+ * 0 <= n_links <= 64 (0 detaches the robot).  Synchronises `stream` once. */
+rc_status rc_robot_meshes(rc_scene* scene, const float* link_tri, const int64_t* tri_offset,
+                          int32_t n_links, void* ws, size_t ws_bytes, rc_stream stream);
+
+/* ---------------------------------------------------------------------
+ * Rendering (Algorithm 1).
+ * ------------------------------------------------------------------- */
+
+#define RC_DEPTH_PLANAR 0 /* optical-z depth (what depth cameras report) */
+#define RC_DEPTH_RANGE 1  /* distance along the ray */
+
+typedef struct {
+    int32_t n_env, n_cam, width, height;
+    const float* link_pos;  /* device [n_env][n_links][3]: t_b per env (world, m) */
+    const float* link_quat; /* device [n_env][n_links][4]: q_b per env */
+    const float* cam_pos;   /* device [n_env][n_cam][3]: camera centre p_c (world) */
+    const float* cam_quat;  /* device [n_env][n_cam][4]: optical -> world */
+    const float* intr;      /* device [n_env][n_cam][4]: fx, fy, cx, cy (batched K) */
+    float far_plane;        /* d_max (m), > 0 */
+    int32_t depth_mode;     /* RC_DEPTH_PLANAR or RC_DEPTH_RANGE */
+    float* depth;           /* device out [n_env][n_cam][height][width] (m) */
+    int32_t* inst;          /* device out, same shape, or NULL */
+    int32_t* tri;           /* device out, same shape, or NULL */
+} rc_render_args;
+
+/* Workspace bytes of rc_render for n_env environments (the per-environment
+ * top-level hierarchies over the link instances, rebuilt on every call). */
+rc_status rc_render_size(const rc_scene* scene, int32_t n_env, size_t* ws_bytes);
+
+/* Rebuild every environment's top-level hierarchy from its link poses, then
+ * cast one ray per (env, cam, pixel): link hits first, then the terrain under
+ * the shrunken bound, closest hit kept (ties: lower inst, then lower tri).
+ * A hit counts when 0 < depth <= far_plane.  Errors: INVALID_ARG (sizes < 1,
+ * width or height > 65535, NULL required pointers, bad mode), WORKSPACE,
+ * STATE (no terrain), DEVICE. */
+rc_status rc_render(const rc_scene* scene, const rc_render_args* args, void* ws,
+                    size_t ws_bytes, rc_stream stream);
+
+/* ---------------------------------------------------------------------
+ * Sensor model: latency, noise, dropout (Sec. 1, Sec. 4.1, Table 6).
+ * ------------------------------------------------------------------- */
+
+#define RC_POST_NOISE 1u
+#define RC_POST_DROPOUT 2u
+#define RC_POST_LATENCY 4u
+
+typedef struct {
+    uint64_t seed;       /* Philox4x32-10 key (low word, high word) */
+    float sigma_abs;     /* noise std = sigma_abs + sigma_rel * depth (m) */
+    float sigma_rel;
+    float p_drop;        /* per-pixel dropout probability in [0, 1] */
+    float near_plane;    /* output clamp [near_plane, far_plane] (m) */
+    float far_plane;
+    float fill;          /* value written for a dropped pixel */
+    int32_t lat_min;     /* latency in frames, uniform in [lat_min, lat_max] */
+    int32_t lat_max;
+    uint32_t flags;      /* RC_POST_NOISE | RC_POST_DROPOUT | RC_POST_LATENCY */
+} rc_post_params;
+
+/* Workspace bytes of a sensor-model state for frames [n_env][n_cam][height]
+ * [width] with latencies up to max_latency frames (a device ring of
+ * max_latency + 1 frames). */
+rc_status rc_post_size(int32_t n_env, int32_t n_cam, int32_t height, int32_t width,
+                       int32_t max_latency, size_t* ws_bytes);
+
+/* Create the state (host handle; the ring lives in the caller's `ws`). */
+rc_status rc_post_create(int32_t n_env, int32_t n_cam, int32_t height, int32_t width,
+                         int32_t max_latency, void* ws, size_t ws_bytes, rc_post** out);
+
+/* Forget captured frames: the next rc_postprocess call starts a new sequence. */
+rc_status rc_post_reset(rc_post* post);
+
+/* Apply the sensor model to the frame rendered at `step` and emit the frame
+ * the sensor shows at that step.  For capture step s, pixel p (row-major
+ * index within its image) and camera uid u, Philox4x32-10 with key = seed
+ * encrypts the counter (p, u, s mod 2^32, ((s >> 32) mod 2^16) << 16):
+ * word 0 decides dropout (w0 < floor(p_drop * 2^32)), words 1-2 give a
+ * Box-Muller normal g from u1 = ((w1 >> 8) + 1) 2^-24, u2 = (w2 >> 8) 2^-24.
+ * A hit becomes clamp(z + (sigma_abs + sigma_rel z) g, near, far), a miss
+ * becomes far, a dropped pixel becomes fill; the result enters the ring.
+ * The latency of camera u at step s is k = lat_min + ((w0 * (lat_max -
+ * lat_min + 1)) >> 32) with w from the counter (0xFFFFFFFF, u, s mod 2^32,
+ * (((s >> 32) mod 2^16) << 16) | 1); the output is the capture of step
+ * max(s - k, s0), s0 = the first step of the sequence.
+ *   depth_in  device float [n_env][n_cam][height][width] (rc_render output)
+ *   inst_in   device int32, same shape (hit <=> inst >= 0), or NULL (hit <=>
+ *             depth < far_plane)
+ *   cam_uid   device uint32 [n_env * n_cam] or NULL (uid = e * n_cam + c)
+ *   depth_out device float, same shape; drop_out device uint8, same shape,
+ *             dropout mask of the capture shown, or NULL; lat_out device
+ *             uint8 [n_env][n_cam] or NULL.
+ * Steps must be consecutive within a sequence (else STATE); s < 2^48. */
+rc_status rc_postprocess(rc_post* post, const float* depth_in, const int32_t* inst_in,
+                         const rc_post_params* params, uint64_t step, const uint32_t* cam_uid,
+                         float* depth_out, uint8_t* drop_out, uint8_t* lat_out,
+                         rc_stream stream);
+
+/* Release the handle (not the workspace). NULL is a no-op. */
+rc_status rc_post_destroy(rc_post* post);
+
+/* ---------------------------------------------------------------------
+ * Inspection of built hierarchies (for tests; no compute).
+ * ------------------------------------------------------------------- */
+
+typedef struct {
+    int64_t n_prim;        /* leaves (triangles or instances) */
+    int64_t n_nodes;       /* internal node records (>= 1) */
+    int64_t node_offset;   /* byte offset in the workspace: node records, 64 B each */
+    int64_t tri_offset;    /* byte offset: float [n_prim][9] triangles in leaf order */
+    int64_t tri_id_offset; /* byte offset: int32 [n_prim] input index of each leaf */
+    int64_t key_offset;    /* byte offset: uint64 [n_prim] sorted Morton keys */
+    int32_t max_depth;     /* deepest internal node (root = 0) */
+    int32_t reserved;
+} rc_bvh_layout;
+
+/* Layout of the terrain hierarchy (which = -1) or of link `which` inside the
+ * workspace given to rc_scene_create / rc_robot_meshes.  Node record:
+ * float box0[6] = (lo.x, hi.x, lo.y, hi.y, lo.z, hi.z), float box1[6],
+ * int32 child0, child1, parent, sibling; child >= 0 is an internal node,
+ * child < 0 is leaf ~child; boxes are padded outwards for FP32 traversal. */
+rc_status rc_bvh_layout_of(const rc_scene* scene, int32_t which, rc_bvh_layout* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RC_H */

@@ -1,0 +1,443 @@
+// C-ABI of librc: argument validation, workspace layout and kernel launches.
+// Every entry point validates on the host before it enqueues anything and
+// turns HIP failures into RC_ERR_DEVICE with a message for rc_last_error().
+#include "rc_internal.h"
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+struct rc_scene {
+    char* ws = nullptr;
+    rc::BvhLayout terrain;
+    int32_t terrain_depth = 0;
+    // robot
+    char* robot_ws = nullptr;
+    int32_t n_links = 0;
+    size_t meta_off = 0;
+    std::vector<rc::BvhLayout> links;
+    std::vector<int32_t> link_depth;
+};
+
+struct rc_post {
+    int32_t n_env, n_cam, height, width, max_latency;
+    int64_t n_pix;
+    float* ring;
+    bool started;
+    uint64_t s0, last;
+};
+
+namespace rc {
+
+static thread_local std::string g_error;
+
+void set_error(const std::string& msg) { g_error = msg; }
+
+namespace {
+
+rc_status fail(rc_status st, const std::string& msg) {
+    set_error(msg);
+    return st;
+}
+
+rc_status hip_fail(hipError_t e, const char* what) {
+    return fail(RC_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+bool aligned(const void* p, size_t a = 256) { return ((uintptr_t)p % a) == 0; }
+
+// Robot workspace: link directory, its upload table, then one hierarchy per link.
+size_t robot_layout(const int64_t* off, int32_t n, std::vector<BvhLayout>* out, size_t* meta_off,
+                    size_t* table_off) {
+    size_t o = 0;
+    *meta_off = o;
+    o = align_up(o + (size_t)kMaxLinks * sizeof(LinkMeta));
+    *table_off = o;
+    o = align_up(o + (size_t)kMaxLinks * 4 * sizeof(int64_t));
+    if (out) out->clear();
+    for (int32_t b = 0; b < n; ++b) {
+        BvhLayout L = bvh_layout(off[b + 1] - off[b], o);
+        if (out) out->push_back(L);
+        o = L.end;
+    }
+    return o;
+}
+
+__global__ void k_link_meta(const char* base, LinkMeta* meta, const int64_t* table, int n) {
+    // table[b] = {node byte offset, tri byte offset, id byte offset, n_tri}, from `base`
+    int b = threadIdx.x;
+    if (b >= n) return;
+    const int64_t* t = table + 4 * b;
+    LinkMeta M;
+    M.node_base = (int32_t)(t[0] / (int64_t)sizeof(Node));
+    M.tri_base = (int32_t)(t[1] / 4);
+    M.id_base = (int32_t)(t[2] / 4);
+    M.n_tri = (int32_t)t[3];
+    const Node* root = reinterpret_cast<const Node*>(base + t[0]);
+    for (int a = 0; a < 3; ++a) {
+        float lo = root->b0[2 * a], hi = root->b0[2 * a + 1];
+        if (M.n_tri > 1) {
+            lo = fminf(lo, root->b1[2 * a]);
+            hi = fmaxf(hi, root->b1[2 * a + 1]);
+        }
+        M.root[2 * a] = lo;
+        M.root[2 * a + 1] = hi;
+    }
+    for (int k = 0; k < 6; ++k) M.pad1[k] = 0;
+    meta[b] = M;
+}
+
+}  // namespace
+}  // namespace rc
+
+using namespace rc;
+
+extern "C" {
+
+int32_t rc_version(void) { return 10000; }
+
+const char* rc_status_string(rc_status st) {
+    switch (st) {
+        case RC_OK: return "ok";
+        case RC_ERR_INVALID_ARG: return "invalid argument";
+        case RC_ERR_WORKSPACE: return "workspace too small or misaligned";
+        case RC_ERR_DEVICE: return "device error";
+        case RC_ERR_STATE: return "call out of order";
+        case RC_ERR_UNSUPPORTED: return "unsupported input";
+        default: return "unknown status";
+    }
+}
+
+const char* rc_last_error(void) { return g_error.c_str(); }
+
+rc_status rc_scene_size(int64_t n_tri, size_t* ws_bytes) {
+    if (!ws_bytes) return fail(RC_ERR_INVALID_ARG, "rc_scene_size: ws_bytes is NULL");
+    if (n_tri < 1 || n_tri > (int64_t)0x7FFFFFFE)
+        return fail(RC_ERR_INVALID_ARG, "rc_scene_size: n_tri must be in [1, 2^31 - 2]");
+    *ws_bytes = bvh_layout(n_tri, 0).end;
+    return RC_OK;
+}
+
+rc_status rc_scene_create(const float* tri, int64_t n_tri, void* ws, size_t ws_bytes,
+                          rc_stream stream, rc_scene** out) {
+    if (!out) return fail(RC_ERR_INVALID_ARG, "rc_scene_create: out is NULL");
+    if (!tri || !ws) return fail(RC_ERR_INVALID_ARG, "rc_scene_create: NULL pointer");
+    if (n_tri < 1 || n_tri > (int64_t)0x7FFFFFFE)
+        return fail(RC_ERR_INVALID_ARG, "rc_scene_create: n_tri must be in [1, 2^31 - 2]");
+    BvhLayout L = bvh_layout(n_tri, 0);
+    if (ws_bytes < L.end || !aligned(ws))
+        return fail(RC_ERR_WORKSPACE, "rc_scene_create: workspace needs " + std::to_string(L.end) +
+                                          " bytes, 256-byte aligned");
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = launch_blas_build(tri, n_tri, (char*)ws, L, s);
+    if (e != hipSuccess) return hip_fail(e, "rc_scene_create: build");
+    int32_t depth = 0;
+    e = hipMemcpyAsync(&depth, (char*)ws + L.depth, 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "rc_scene_create: depth check");
+    if (depth > kMaxDepth)
+        return fail(RC_ERR_UNSUPPORTED, "rc_scene_create: hierarchy depth " + std::to_string(depth) +
+                                            " exceeds 64");
+    rc_scene* sc = new (std::nothrow) rc_scene();
+    if (!sc) return fail(RC_ERR_DEVICE, "rc_scene_create: out of host memory");
+    sc->ws = (char*)ws;
+    sc->terrain = L;
+    sc->terrain_depth = depth;
+    *out = sc;
+    return RC_OK;
+}
+
+rc_status rc_scene_destroy(rc_scene* scene) {
+    delete scene;
+    return RC_OK;
+}
+
+static rc_status check_offsets(const int64_t* off, int32_t n, const char* who) {
+    if (n < 0 || n > kMaxLinks)
+        return fail(RC_ERR_INVALID_ARG, std::string(who) + ": n_links must be in [0, 64]");
+    if (n == 0) return RC_OK;
+    if (!off) return fail(RC_ERR_INVALID_ARG, std::string(who) + ": tri_offset is NULL");
+    if (off[0] != 0) return fail(RC_ERR_INVALID_ARG, std::string(who) + ": tri_offset[0] != 0");
+    for (int32_t b = 0; b < n; ++b) {
+        if (off[b + 1] - off[b] < 1)
+            return fail(RC_ERR_INVALID_ARG, std::string(who) + ": every link needs >= 1 triangle");
+        if (off[b + 1] - off[b] > (int64_t)0x7FFFFFFE)
+            return fail(RC_ERR_INVALID_ARG, std::string(who) + ": link mesh too large");
+    }
+    return RC_OK;
+}
+
+rc_status rc_robot_size(const int64_t* tri_offset, int32_t n_links, size_t* ws_bytes) {
+    if (!ws_bytes) return fail(RC_ERR_INVALID_ARG, "rc_robot_size: ws_bytes is NULL");
+    rc_status st = check_offsets(tri_offset, n_links, "rc_robot_size");
+    if (st != RC_OK) return st;
+    size_t meta_off, table_off;
+    *ws_bytes = robot_layout(tri_offset, n_links, nullptr, &meta_off, &table_off);
+    return RC_OK;
+}
+
+rc_status rc_robot_meshes(rc_scene* scene, const float* link_tri, const int64_t* tri_offset,
+                          int32_t n_links, void* ws, size_t ws_bytes, rc_stream stream) {
+    if (!scene) return fail(RC_ERR_INVALID_ARG, "rc_robot_meshes: scene is NULL");
+    rc_status st = check_offsets(tri_offset, n_links, "rc_robot_meshes");
+    if (st != RC_OK) return st;
+    if (n_links == 0) {
+        scene->n_links = 0;
+        scene->robot_ws = nullptr;
+        scene->links.clear();
+        scene->link_depth.clear();
+        return RC_OK;
+    }
+    if (!link_tri || !ws) return fail(RC_ERR_INVALID_ARG, "rc_robot_meshes: NULL pointer");
+    std::vector<BvhLayout> Ls;
+    size_t meta_off, table_off;
+    size_t need = robot_layout(tri_offset, n_links, &Ls, &meta_off, &table_off);
+    if (ws_bytes < need || !aligned(ws))
+        return fail(RC_ERR_WORKSPACE, "rc_robot_meshes: workspace needs " + std::to_string(need) +
+                                          " bytes, 256-byte aligned");
+    if (need > (size_t)0x7FFFFFFF)
+        return fail(RC_ERR_UNSUPPORTED, "rc_robot_meshes: link meshes too large");
+    hipStream_t s = (hipStream_t)stream;
+    char* base = (char*)ws;
+    hipError_t e = hipSuccess;
+    for (int32_t b = 0; b < n_links && e == hipSuccess; ++b)
+        e = launch_blas_build(link_tri + 9 * tri_offset[b], Ls[b].n_prim, base, Ls[b], s);
+    if (e != hipSuccess) return hip_fail(e, "rc_robot_meshes: build");
+    // directory: offsets relative to the start of the robot workspace
+    std::vector<int64_t> table(4 * (size_t)n_links);
+    for (int32_t b = 0; b < n_links; ++b) {
+        table[4 * b + 0] = (int64_t)Ls[b].nodes;
+        table[4 * b + 1] = (int64_t)Ls[b].tris;
+        table[4 * b + 2] = (int64_t)Ls[b].tri_id;
+        table[4 * b + 3] = Ls[b].n_prim;
+    }
+    int64_t* dtable = (int64_t*)(base + table_off);
+    e = hipMemcpyAsync(dtable, table.data(), table.size() * sizeof(int64_t), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_link_meta, dim3(1), dim3(kMaxLinks), 0, s, (const char*)base,
+                           (LinkMeta*)(base + meta_off), (const int64_t*)dtable, n_links);
+        e = hipGetLastError();
+    }
+    std::vector<int32_t> depth(n_links);
+    for (int32_t b = 0; b < n_links && e == hipSuccess; ++b)
+        e = hipMemcpyAsync(&depth[b], base + Ls[b].depth, 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "rc_robot_meshes: directory");
+    for (int32_t b = 0; b < n_links; ++b)
+        if (depth[b] > kMaxDepth)
+            return fail(RC_ERR_UNSUPPORTED, "rc_robot_meshes: link hierarchy deeper than 64");
+    scene->robot_ws = base;
+    scene->n_links = n_links;
+    scene->meta_off = meta_off;
+    scene->links = Ls;
+    scene->link_depth = depth;
+    return RC_OK;
+}
+
+static size_t render_layout(int32_t n_env, int32_t n_links, size_t* xf_off) {
+    if (n_links <= 0) { *xf_off = 0; return 256; }
+    const int64_t n_rec = n_links > 1 ? n_links - 1 : 1;
+    size_t o = align_up((size_t)n_env * n_rec * sizeof(Node));
+    *xf_off = o;
+    o = align_up(o + (size_t)n_env * n_links * sizeof(InstXform));
+    return o;
+}
+
+rc_status rc_render_size(const rc_scene* scene, int32_t n_env, size_t* ws_bytes) {
+    if (!scene || !ws_bytes) return fail(RC_ERR_INVALID_ARG, "rc_render_size: NULL pointer");
+    if (n_env < 1) return fail(RC_ERR_INVALID_ARG, "rc_render_size: n_env must be >= 1");
+    size_t xo;
+    *ws_bytes = render_layout(n_env, scene->n_links, &xo);
+    return RC_OK;
+}
+
+rc_status rc_render(const rc_scene* scene, const rc_render_args* a, void* ws, size_t ws_bytes,
+                    rc_stream stream) {
+    if (!scene || !a) return fail(RC_ERR_INVALID_ARG, "rc_render: NULL scene or args");
+    if (!scene->ws) return fail(RC_ERR_STATE, "rc_render: scene has no terrain");
+    if (a->n_env < 1 || a->n_cam < 1 || a->width < 1 || a->height < 1 || a->width > 65535 ||
+        a->height > 65535)
+        return fail(RC_ERR_INVALID_ARG, "rc_render: sizes must be >= 1 (width, height <= 65535)");
+    const int64_t n_img = (int64_t)a->n_env * a->n_cam;
+    const int64_t tiles = n_img * ((a->width + 7) / 8) * ((a->height + 7) / 8);
+    if (tiles > (int64_t)0x7FFFFFFF / 2)
+        return fail(RC_ERR_UNSUPPORTED, "rc_render: too many pixels for one launch");
+    if (!a->cam_pos || !a->cam_quat || !a->intr || !a->depth)
+        return fail(RC_ERR_INVALID_ARG, "rc_render: cam_pos, cam_quat, intr and depth are required");
+    if (scene->n_links > 0 && (!a->link_pos || !a->link_quat))
+        return fail(RC_ERR_INVALID_ARG, "rc_render: link_pos and link_quat are required with links");
+    if (!(a->far_plane > 0.0f) || !std::isfinite(a->far_plane))
+        return fail(RC_ERR_INVALID_ARG, "rc_render: far_plane must be finite and > 0");
+    if (a->depth_mode != RC_DEPTH_PLANAR && a->depth_mode != RC_DEPTH_RANGE)
+        return fail(RC_ERR_INVALID_ARG, "rc_render: unknown depth_mode");
+    size_t xf_off;
+    size_t need = render_layout(a->n_env, scene->n_links, &xf_off);
+    if (scene->n_links > 0 && (!ws || ws_bytes < need || !aligned(ws)))
+        return fail(RC_ERR_WORKSPACE, "rc_render: workspace needs " + std::to_string(need) +
+                                          " bytes, 256-byte aligned");
+    hipStream_t s = (hipStream_t)stream;
+    RenderLaunch L;
+    L.terrain_nodes = (const Node*)(scene->ws + scene->terrain.nodes);
+    L.terrain_tris = (const float*)(scene->ws + scene->terrain.tris);
+    L.terrain_tri_id = (const int32_t*)(scene->ws + scene->terrain.tri_id);
+    L.link_nodes = (const Node*)scene->robot_ws;
+    L.link_tris = (const float*)scene->robot_ws;
+    L.link_tri_id = (const int32_t*)scene->robot_ws;
+    L.link_meta = scene->robot_ws ? (const LinkMeta*)(scene->robot_ws + scene->meta_off) : nullptr;
+    L.tlas = scene->n_links > 0 ? (const Node*)ws : nullptr;
+    L.xf = scene->n_links > 0 ? (const InstXform*)((char*)ws + xf_off) : nullptr;
+    L.link_pos = a->link_pos;
+    L.link_quat = a->link_quat;
+    L.cam_pos = a->cam_pos;
+    L.cam_quat = a->cam_quat;
+    L.intr = a->intr;
+    L.depth = a->depth;
+    L.inst = a->inst;
+    L.tri = a->tri;
+    L.n_env = a->n_env;
+    L.n_cam = a->n_cam;
+    L.width = a->width;
+    L.height = a->height;
+    L.n_links = scene->n_links;
+    L.depth_mode = a->depth_mode;
+    L.n_terrain = (int)scene->terrain.n_prim;
+    L.far_plane = a->far_plane;
+    hipError_t e = hipSuccess;
+    if (scene->n_links > 0)
+        e = launch_tlas_build(a->link_pos, a->link_quat, a->n_env, scene->n_links, L.link_meta,
+                              (Node*)ws, (InstXform*)((char*)ws + xf_off), s);
+    if (e == hipSuccess) e = launch_render(L, s);
+    if (e != hipSuccess) return hip_fail(e, "rc_render: launch");
+    return RC_OK;
+}
+
+static rc_status post_dims(int32_t n_env, int32_t n_cam, int32_t height, int32_t width,
+                           int32_t max_latency, const char* who) {
+    if (n_env < 1 || n_cam < 1 || height < 1 || width < 1)
+        return fail(RC_ERR_INVALID_ARG, std::string(who) + ": sizes must be >= 1");
+    if (max_latency < 0 || max_latency > 255)
+        return fail(RC_ERR_INVALID_ARG, std::string(who) + ": max_latency must be in [0, 255]");
+    const int64_t hw = (int64_t)height * width;
+    if (hw > (int64_t)0xFFFFFFFF)
+        return fail(RC_ERR_INVALID_ARG, std::string(who) + ": image too large");
+    return RC_OK;
+}
+
+rc_status rc_post_size(int32_t n_env, int32_t n_cam, int32_t height, int32_t width,
+                       int32_t max_latency, size_t* ws_bytes) {
+    if (!ws_bytes) return fail(RC_ERR_INVALID_ARG, "rc_post_size: ws_bytes is NULL");
+    rc_status st = post_dims(n_env, n_cam, height, width, max_latency, "rc_post_size");
+    if (st != RC_OK) return st;
+    const int64_t n_pix = (int64_t)n_env * n_cam * height * width;
+    *ws_bytes = align_up((size_t)n_pix * 4 * (size_t)(max_latency + 1));
+    return RC_OK;
+}
+
+rc_status rc_post_create(int32_t n_env, int32_t n_cam, int32_t height, int32_t width,
+                         int32_t max_latency, void* ws, size_t ws_bytes, rc_post** out) {
+    if (!out || !ws) return fail(RC_ERR_INVALID_ARG, "rc_post_create: NULL pointer");
+    size_t need;
+    rc_status st = rc_post_size(n_env, n_cam, height, width, max_latency, &need);
+    if (st != RC_OK) return st;
+    if (ws_bytes < need || !aligned(ws))
+        return fail(RC_ERR_WORKSPACE, "rc_post_create: workspace needs " + std::to_string(need) +
+                                          " bytes, 256-byte aligned");
+    rc_post* p = new (std::nothrow) rc_post();
+    if (!p) return fail(RC_ERR_DEVICE, "rc_post_create: out of host memory");
+    p->n_env = n_env; p->n_cam = n_cam; p->height = height; p->width = width;
+    p->max_latency = max_latency;
+    p->n_pix = (int64_t)n_env * n_cam * height * width;
+    p->ring = (float*)ws;
+    p->started = false;
+    p->s0 = p->last = 0;
+    *out = p;
+    return RC_OK;
+}
+
+rc_status rc_post_reset(rc_post* post) {
+    if (!post) return fail(RC_ERR_INVALID_ARG, "rc_post_reset: NULL handle");
+    post->started = false;
+    return RC_OK;
+}
+
+rc_status rc_postprocess(rc_post* post, const float* depth_in, const int32_t* inst_in,
+                         const rc_post_params* pp, uint64_t step, const uint32_t* cam_uid,
+                         float* depth_out, uint8_t* drop_out, uint8_t* lat_out, rc_stream stream) {
+    if (!post || !pp || !depth_in || !depth_out)
+        return fail(RC_ERR_INVALID_ARG, "rc_postprocess: NULL required pointer");
+    if (step >= (1ull << 48)) return fail(RC_ERR_INVALID_ARG, "rc_postprocess: step >= 2^48");
+    if (!(pp->p_drop >= 0.0f && pp->p_drop <= 1.0f))
+        return fail(RC_ERR_INVALID_ARG, "rc_postprocess: p_drop must be in [0, 1]");
+    if (!(pp->near_plane <= pp->far_plane) || !std::isfinite(pp->near_plane) ||
+        !std::isfinite(pp->far_plane))
+        return fail(RC_ERR_INVALID_ARG, "rc_postprocess: need finite near_plane <= far_plane");
+    if (!std::isfinite(pp->sigma_abs) || !std::isfinite(pp->sigma_rel) || !std::isfinite(pp->fill))
+        return fail(RC_ERR_INVALID_ARG, "rc_postprocess: non-finite noise or fill parameter");
+    if (pp->flags & ~(RC_POST_NOISE | RC_POST_DROPOUT | RC_POST_LATENCY))
+        return fail(RC_ERR_INVALID_ARG, "rc_postprocess: unknown flag");
+    if (pp->flags & RC_POST_LATENCY) {
+        if (pp->lat_min < 0 || pp->lat_max < pp->lat_min)
+            return fail(RC_ERR_INVALID_ARG, "rc_postprocess: need 0 <= lat_min <= lat_max");
+        if (pp->lat_max > post->max_latency)
+            return fail(RC_ERR_INVALID_ARG, "rc_postprocess: lat_max exceeds the ring's max_latency");
+    }
+    if (post->started && step != post->last + 1)
+        return fail(RC_ERR_STATE, "rc_postprocess: steps must be consecutive (call rc_post_reset)");
+    PostLaunch L;
+    L.depth_in = depth_in;
+    L.inst_in = inst_in;
+    L.cam_uid = cam_uid;
+    L.ring = post->ring;
+    L.depth_out = depth_out;
+    L.drop_out = drop_out;
+    L.lat_out = lat_out;
+    L.n_pix = post->n_pix;
+    L.n_env = post->n_env; L.n_cam = post->n_cam; L.height = post->height; L.width = post->width;
+    L.ring_len = post->max_latency + 1;
+    L.step = step;
+    L.s0 = post->started ? post->s0 : step;
+    L.seed = pp->seed;
+    double t = std::floor((double)pp->p_drop * 4294967296.0);
+    L.drop_thr = t > 0.0 ? (uint64_t)t : 0ull;
+    L.sigma_abs = pp->sigma_abs; L.sigma_rel = pp->sigma_rel;
+    L.near_plane = pp->near_plane; L.far_plane = pp->far_plane; L.fill = pp->fill;
+    L.lat_min = pp->lat_min; L.lat_max = pp->lat_max;
+    L.flags = pp->flags;
+    hipError_t e = launch_post(L, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "rc_postprocess: launch");
+    if (!post->started) { post->started = true; post->s0 = step; }
+    post->last = step;
+    return RC_OK;
+}
+
+rc_status rc_post_destroy(rc_post* post) {
+    delete post;
+    return RC_OK;
+}
+
+rc_status rc_bvh_layout_of(const rc_scene* scene, int32_t which, rc_bvh_layout* out) {
+    if (!scene || !out) return fail(RC_ERR_INVALID_ARG, "rc_bvh_layout_of: NULL pointer");
+    const BvhLayout* L;
+    int32_t depth;
+    if (which == -1) {
+        L = &scene->terrain;
+        depth = scene->terrain_depth;
+    } else if (which >= 0 && which < scene->n_links) {
+        L = &scene->links[which];
+        depth = scene->link_depth[which];
+    } else {
+        return fail(RC_ERR_INVALID_ARG, "rc_bvh_layout_of: no such hierarchy");
+    }
+    out->n_prim = L->n_prim;
+    out->n_nodes = L->n_nodes;
+    out->node_offset = (int64_t)L->nodes;
+    out->tri_offset = (int64_t)L->tris;
+    out->tri_id_offset = (int64_t)L->tri_id;
+    out->key_offset = (int64_t)L->keys;
+    out->max_depth = depth;
+    out->reserved = 0;
+    return RC_OK;
+}
+
+}  // extern "C"

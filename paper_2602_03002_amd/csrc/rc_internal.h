@@ -1,0 +1,117 @@
+// Internal declarations shared by the HIP sources of librc (not installed).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+#include <string>
+
+#include "../../include/rc.h"
+
+namespace rc {
+
+// Node record, 64 bytes: two child boxes (lo.x, hi.x, lo.y, hi.y, lo.z, hi.z),
+// then child0, child1, parent, sibling.  child >= 0: internal node; child < 0:
+// leaf ~child.  A BVH over n >= 2 leaves has n - 1 records (root = 0); over one
+// leaf it has one record whose second box is a point at (1e30, 1e30, 1e30),
+// beyond any far plane.
+struct alignas(16) Node {
+    float b0[6];
+    float b1[6];
+    int32_t c0, c1, parent, sibling;
+};
+static_assert(sizeof(Node) == 64, "node record is one 64-byte line");
+
+// Per-link hierarchy directory entry (device), 64 bytes.
+// Bases are element offsets from the start of the robot workspace.
+struct alignas(16) LinkMeta {
+    int32_t node_base;  // in 64-byte node records
+    int32_t tri_base;   // in floats: first float of the link's leaf-order triangles
+    int32_t id_base;    // in int32: first input index of the link's leaves
+    int32_t n_tri;
+    float root[6];      // padded box of the whole mesh (lo.x, hi.x, lo.y, ...)
+    int32_t pad1[6];
+};
+static_assert(sizeof(LinkMeta) == 64, "link directory entry is 64 bytes");
+
+// Instance transform written by the top-level build: M = R^T (row-major),
+// t = link position; o_local = M (o - t), d_local = M d.
+struct alignas(16) InstXform {
+    float m[9];
+    float t[3];
+};
+static_assert(sizeof(InstXform) == 48, "instance transform is 48 bytes");
+
+constexpr int kMaxLinks = 64;
+constexpr int kMaxDepth = 64;          // bits in the traversal trail
+constexpr float kPadRel = 9.5367431640625e-07f;  // 2^-20, outward box padding
+constexpr float kPadAbs = 1.0e-5f;               // metres
+constexpr float kInstPadRel = 9.5367431640625e-07f;
+constexpr float kInstPadAbs = 1.0e-4f;
+
+inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+
+// Byte layout of one hierarchy inside a workspace.
+struct BvhLayout {
+    int64_t n_prim = 0, n_nodes = 0;
+    size_t nodes = 0, tris = 0, tri_id = 0, keys = 0;
+    // build scratch
+    size_t keys_alt = 0, vals = 0, vals_alt = 0, prim_box = 0, flags = 0, leaf_parent = 0,
+           hist = 0, partial = 0, cbounds = 0, depth = 0, end = 0;
+    int64_t n_blocks_sort = 0, n_blocks_red = 0;
+};
+
+BvhLayout bvh_layout(int64_t n, size_t base);
+
+// Host-side launchers (each returns a hipError_t of its enqueue).
+hipError_t launch_blas_build(const float* tri, int64_t n, char* ws, const BvhLayout& L,
+                             hipStream_t s);
+hipError_t launch_tlas_build(const float* link_pos, const float* link_quat, int n_env,
+                             int n_links, const LinkMeta* meta, Node* tlas, InstXform* xf,
+                             hipStream_t s);
+
+struct RenderLaunch {
+    const Node* terrain_nodes;
+    const float* terrain_tris;
+    const int32_t* terrain_tri_id;
+    const Node* link_nodes;
+    const float* link_tris;
+    const int32_t* link_tri_id;
+    const LinkMeta* link_meta;
+    const Node* tlas;
+    const InstXform* xf;
+    const float* link_pos;
+    const float* link_quat;
+    const float* cam_pos;
+    const float* cam_quat;
+    const float* intr;
+    float* depth;
+    int32_t* inst;
+    int32_t* tri;
+    int n_env, n_cam, width, height, n_links, depth_mode, n_terrain;
+    float far_plane;
+};
+hipError_t launch_render(const RenderLaunch& a, hipStream_t s);
+
+struct PostLaunch {
+    const float* depth_in;
+    const int32_t* inst_in;
+    const uint32_t* cam_uid;
+    float* ring;  // [L][n_pix]
+    float* depth_out;
+    uint8_t* drop_out;
+    uint8_t* lat_out;
+    int64_t n_pix;
+    int n_env, n_cam, height, width, ring_len;
+    uint64_t step, s0;
+    uint64_t seed;
+    uint64_t drop_thr;  // floor(p_drop * 2^32) in [0, 2^32]
+    float sigma_abs, sigma_rel, near_plane, far_plane, fill;
+    int lat_min, lat_max;
+    uint32_t flags;
+};
+hipError_t launch_post(const PostLaunch& a, hipStream_t s);
+
+void set_error(const std::string& msg);
+
+}  // namespace rc

@@ -1,0 +1,273 @@
+"""GPU parity: librc (through its C-ABI) against the FP64 oracle and the CPU LBVH model."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import lbvh
+import scenegen as sg
+from parity import assert_parity
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+def rc():
+    import paper_2602_03002_amd as m
+    return m
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def make_scene(w, step=0):
+    m = rc()
+    sc = m.Scene(dev(w["terrain"]))
+    B = int(w["link_off"].shape[0] - 1)
+    if B > 0:
+        sc.set_robot(dev(w["link_tri"]), w["link_off"].tolist())
+    return sc
+
+
+def render(sc, w, step=0, depth_mode=0):
+    B = sc.n_links
+    lp = dev(w["link_pos"][step]) if B else None
+    lq = dev(w["link_quat"][step]) if B else None
+    d, i, t = sc.render(dev(w["cam_pos"]), dev(w["cam_quat"]), dev(w["intr"]), w["W"], w["H"],
+                        w["far"], link_pos=lp, link_quat=lq, depth_mode=depth_mode)
+    torch.cuda.synchronize()
+    return d.cpu().numpy(), i.cpu().numpy(), t.cpu().numpy()
+
+
+def oracle_render(w, step=0, depth_mode=0, rays=None):
+    return oracle.render(w["terrain"], w["link_tri"], w["link_off"], w["link_pos"][step],
+                         w["link_quat"][step], w["cam_pos"], w["cam_quat"], w["intr"], w["W"],
+                         w["H"], w["far"], depth_mode=depth_mode, rays=rays)
+
+
+# ---------------------------------------------------------------------------
+# hierarchy build: bit-exact against the CPU model
+# ---------------------------------------------------------------------------
+
+def ws_bytes(ws):
+    torch.cuda.synchronize()
+    return ws.view().cpu().numpy()
+
+
+def check_bvh(buf, lay, tri):
+    model = lbvh.build(tri)
+    n, m = lay.n_prim, lay.n_nodes
+    rec = buf[lay.node_offset:lay.node_offset + 64 * m].view(np.float32).reshape(m, 16)
+    ids = buf[lay.tri_id_offset:lay.tri_id_offset + 4 * n].view(np.int32)
+    assert np.array_equal(ids, model["tri_id"]), "leaf order differs"
+    if n > 1:
+        keys = buf[lay.key_offset:lay.key_offset + 8 * n].view(np.uint64)
+        assert np.array_equal(keys, model["keys"]), "Morton keys differ"
+    assert np.array_equal(rec.view(np.uint32), model["records"].view(np.uint32)), "node records differ"
+    tris = buf[lay.tri_offset:lay.tri_offset + 36 * n].view(np.float32).reshape(n, 9)
+    assert np.array_equal(tris, np.asarray(tri, np.float32).reshape(-1, 9)[model["tri_id"]])
+    assert lay.max_depth == model["depth"]
+
+
+@pytest.mark.parametrize("which", ["profile", "tiles2", "single"])
+def test_terrain_bvh_bit_exact(which):
+    say(f"[bvh] terrain {which}")
+    if which == "profile":
+        tri = sg.small_plain_case()["terrain"]
+    elif which == "tiles2":
+        tri = sg.TileTerrain(2).triangles()
+    else:
+        tri = np.array([[[0, 0, 0], [1, 0, 0], [0, 1, 0]]], np.float32)
+    sc = rc().Scene(dev(tri))
+    check_bvh(ws_bytes(sc.ws), sc.bvh_layout(-1), tri)
+
+
+def test_link_bvh_bit_exact():
+    say("[bvh] 30 link meshes")
+    rob = sg.Robot()
+    lt, off = rob.link_triangles()
+    sc = rc().Scene(dev(sg.small_plain_case()["terrain"]))
+    sc.set_robot(dev(lt), off.tolist())
+    buf = ws_bytes(sc.robot_ws)
+    for b in (0, 13, 29):
+        check_bvh(buf, sc.bvh_layout(b), lt[off[b]:off[b + 1]])
+
+
+# ---------------------------------------------------------------------------
+# rendering parity
+# ---------------------------------------------------------------------------
+
+def test_small_plain_case_full_frame():
+    say("[render] 1 env x 1 cam 32x24, terrain profile")
+    w = sg.small_plain_case()
+    sc = make_scene(w)
+    d, i, t = render(sc, w)
+    ref = oracle_render(w)
+    assert_parity(d, i, t, ref, w["far"], label="small plain case")
+    assert np.all(i == 0)
+
+
+@pytest.mark.parametrize("depth_mode", [0, 1])
+def test_robot_scene_full_frame_ragged(depth_mode):
+    say(f"[render] 4 envs x 2 cams 37x29 (ragged tiles), 2x2 tiles, 30 links, mode {depth_mode}")
+    w = sg.robot_scene(2, 2, 4.0, 2, 37, 29, steps=2, label="parity-ragged")
+    sc = make_scene(w)
+    for step in (0, 1):
+        d, i, t = render(sc, w, step, depth_mode)
+        ref = oracle_render(w, step, depth_mode)
+        r = assert_parity(d, i, t, ref, w["far"], label=f"ragged step {step} mode {depth_mode}")
+        assert (i >= 0).mean() > 0.5
+        assert ((i >= 0) & (i < 30)).sum() > 20, "the cameras should see the robot"
+        del r
+
+
+def test_single_link_and_single_triangle():
+    say("[render] one link, one-triangle terrain")
+    w = sg.robot_scene(1, 1, 4.0, 2, 16, 12, steps=1, label="single")
+    w["link_tri"] = w["link_tri"][:512]
+    w["link_off"] = np.array([0, 512], np.int64)
+    w["link_pos"] = np.ascontiguousarray(w["link_pos"][:, :, 10:11])  # a leg link in view
+    w["link_quat"] = np.ascontiguousarray(w["link_quat"][:, :, 10:11])
+    w["terrain"] = np.array([[[-5, -5, 0], [5, -5, 0], [0, 5, 0]]], np.float32) + \
+        np.float32([w["cam_pos"][0, 0, 0], w["cam_pos"][0, 0, 1], w["cam_pos"][0, 0, 2] - 1.0])
+    sc = make_scene(w)
+    d, i, t = render(sc, w)
+    ref = oracle_render(w)
+    assert_parity(d, i, t, ref, w["far"], label="single link + single triangle")
+
+
+def test_far_plane_misses():
+    say("[render] everything beyond the far plane")
+    w = sg.small_plain_case()
+    w["far"] = 0.5
+    sc = make_scene(w)
+    d, i, t = render(sc, w)
+    assert np.all(i == -1) and np.all(t == -1) and np.all(d == np.float32(0.5))
+
+
+def test_render_is_deterministic():
+    say("[render] determinism")
+    w = sg.robot_scene(2, 2, 4.0, 2, 64, 48, steps=1, label="det")
+    sc = make_scene(w)
+    a = render(sc, w)
+    b = render(sc, w)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+def sampled(w, n, seed):
+    total = w["E"] * w["C"] * w["H"] * w["W"]
+    return np.sort(np.random.default_rng(seed).choice(total, size=n, replace=False))
+
+
+def test_64_envs_sampled():
+    say("[render] 64 envs x 2 cams 64x48, 10x10 tiles (~500k tris), 2048 sampled rays")
+    w = sg.robots_64()
+    sc = make_scene(w)
+    for step in (0, 2):
+        d, i, t = render(sc, w, step)
+        rays = sampled(w, 2048, 100 + step)
+        ref = oracle_render(w, step, rays=rays)
+        assert_parity(d.ravel()[rays], i.ravel()[rays], t.ravel()[rays], ref, w["far"],
+                      label=f"64 envs step {step}")
+
+
+def test_4096_envs_sampled():
+    say("[render] 4096 envs x 2 cams 64x48, 20x20 tiles (~2M tris), 1024 sampled rays")
+    w = sg.robots_4096(steps=3)
+    sc = make_scene(w)
+    for step in (0, 2):
+        d, i, t = render(sc, w, step)
+        assert (i >= 0).mean() > 0.9
+        rays = sampled(w, 1024, 200 + step)
+        ref = oracle_render(w, step, rays=rays)
+        assert_parity(d.ravel()[rays], i.ravel()[rays], t.ravel()[rays], ref, w["far"],
+                      label=f"4096 envs step {step}")
+
+
+# ---------------------------------------------------------------------------
+# sensor model
+# ---------------------------------------------------------------------------
+
+def run_post(depth, inst, params_kw, s0=0, cam_uid=None, max_latency=3):
+    m = rc()
+    S, E, C, H, W = depth.shape
+    post = m.Post(E, C, H, W, max_latency)
+    p = m.post_params(**params_kw)
+    uid = dev(cam_uid) if cam_uid is not None else None
+    outs, drops, lats = [], [], []
+    for s in range(S):
+        o, dr, la = post.process(dev(depth[s]), dev(inst[s]), p, s0 + s, cam_uid=uid)
+        torch.cuda.synchronize()
+        outs.append(o.cpu().numpy())
+        drops.append(dr.cpu().numpy())
+        lats.append(la.cpu().numpy())
+    return np.stack(outs), np.stack(drops), np.stack(lats)
+
+
+@pytest.mark.parametrize("s0,with_uid", [(0, False), (5, True)])
+def test_post_matches_oracle(s0, with_uid):
+    say(f"[post] 3 envs x 2 cams 29x37, 9 steps from {s0}, uid table {with_uid}")
+    depth, inst = sg.synthetic_frames(3, 2, 29, 37, 9)
+    kw = dict(seed=0x1234_5678_9ABC, sigma_abs=0.01, sigma_rel=0.02, p_drop=0.02, near=0.05,
+              far=3.0, fill=0.0, lat_min=1, lat_max=3)
+    uid = (np.arange(6, dtype=np.uint32) * 7 + 100) if with_uid else None
+    out, drop, lat = run_post(depth, inst, kw, s0=s0, cam_uid=uid)
+    ro, rd, rl = oracle.post(depth, inst, oracle.make_params(**kw), s0=s0, cam_uid=uid)
+    assert np.array_equal(lat, rl), "latency draws differ"
+    assert np.array_equal(drop, rd), "dropout masks differ"
+    assert np.max(np.abs(out - ro)) <= 1e-5
+
+
+def test_post_identity_and_errors():
+    say("[post] everything off; out-of-order step")
+    depth, inst = sg.synthetic_frames(2, 1, 8, 8, 2)
+    out, drop, lat = run_post(depth, inst, dict(seed=1, near=0.05, far=3.0))
+    near, far = np.float32(0.05), np.float32(3.0)
+    expect = np.where(inst >= 0, np.clip(depth, near, far), far)
+    assert np.array_equal(out, expect) and not drop.any() and not lat.any()
+    m = rc()
+    post = m.Post(2, 1, 8, 8, 3)
+    p = m.post_params(seed=1)
+    post.process(dev(depth[0]), dev(inst[0]), p, 10)
+    with pytest.raises(m.RcError):
+        post.process(dev(depth[1]), dev(inst[1]), p, 12)
+
+
+def test_render_then_post_end_to_end():
+    say("[render+post] 4 envs x 2 cams 32x24, 4 steps")
+    w = sg.robot_scene(2, 2, 4.0, 2, 32, 24, steps=4, label="e2e")
+    sc = make_scene(w)
+    m = rc()
+    kw = dict(seed=77, sigma_abs=0.01, p_drop=0.02, near=0.05, far=3.0, lat_min=1, lat_max=3)
+    post = m.Post(w["E"], w["C"], w["H"], w["W"], 3)
+    p = m.post_params(**kw)
+    frames_d, frames_i, outs, refs = [], [], [], []
+    for s in range(4):
+        lp, lq = dev(w["link_pos"][s]), dev(w["link_quat"][s])
+        d, i, _ = sc.render(dev(w["cam_pos"]), dev(w["cam_quat"]), dev(w["intr"]), w["W"], w["H"],
+                            w["far"], link_pos=lp, link_quat=lq)
+        o, _, _ = post.process(d, i, p, s)
+        torch.cuda.synchronize()
+        outs.append(o.cpu().numpy())
+        ref = oracle_render(w, s)
+        refs.append(ref)
+        frames_d.append(ref["depth"].astype(np.float32).reshape(w["E"], w["C"], w["H"], w["W"]))
+        frames_i.append(ref["inst"].reshape(w["E"], w["C"], w["H"], w["W"]))
+    ro, _, rl = oracle.post(np.stack(frames_d), np.stack(frames_i), oracle.make_params(**kw))
+    # compare pixels whose shown capture comes from an unflagged oracle ray
+    for s in range(4):
+        for ec in range(w["E"] * w["C"]):
+            k = int(rl[s].ravel()[ec])
+            src = max(s - k, 0)
+            fl = refs[src]["flags"].reshape(w["E"] * w["C"], -1)[ec]
+            ok = fl == 0
+            a = outs[s].reshape(w["E"] * w["C"], -1)[ec][ok]
+            b = ro[s].reshape(w["E"] * w["C"], -1)[ec][ok]
+            assert np.max(np.abs(a - b)) <= 1e-4
