@@ -71,6 +71,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--pose-steps", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="run one plain device copy of this size first (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding "
@@ -82,6 +84,15 @@ def main():
     import scenegen as sg
     import paper_2602_03002_amd as rc
 
+    if args.copy_probe_mib > 0:
+        n = args.copy_probe_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        print(f"[bench] copy probe: {args.copy_probe_mib} MiB read + written", file=sys.stderr,
+              flush=True)
     print("[bench] generating 4096-env workload", file=sys.stderr, flush=True)
     w = sg.robots_4096(steps=args.pose_steps)
     E, C, H, W = w["E"], w["C"], w["H"], w["W"]
