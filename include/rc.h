@@ -121,18 +121,30 @@ typedef struct {
     int32_t* tri;           /* device out, same shape, or NULL */
 } rc_render_args;
 
-/* Workspace bytes of rc_render for n_env environments (the per-environment
- * top-level hierarchies over the link instances, rebuilt on every call). */
-rc_status rc_render_size(const rc_scene* scene, int32_t n_env, size_t* ws_bytes);
+/* Workspace bytes of rc_render for n_env x n_cam images of width x height:
+ * the per-environment top-level hierarchies over the link instances (rebuilt
+ * on every call) and the list of rays handed to the exact pass. */
+rc_status rc_render_size(const rc_scene* scene, int32_t n_env, int32_t n_cam, int32_t width,
+                         int32_t height, size_t* ws_bytes);
 
 /* Rebuild every environment's top-level hierarchy from its link poses, then
  * cast one ray per (env, cam, pixel): link hits first, then the terrain under
  * the shrunken bound, closest hit kept (ties: lower inst, then lower tri).
- * A hit counts when 0 < depth <= far_plane.  Errors: INVALID_ARG (sizes < 1,
- * width or height > 65535, NULL required pointers, bad mode), WORKSPACE,
- * STATE (no terrain), DEVICE. */
+ * A hit counts when 0 < depth <= far_plane.  Hit decisions are exact: a ray
+ * whose closest hit could hinge on a triangle edge test FP32 cannot decide
+ * is re-cast by a second pass that repeats such tests in FP64.  Errors:
+ * INVALID_ARG (sizes < 1, width or height > 65535, more than 2^32 - 1 rays,
+ * NULL required pointers, bad mode), WORKSPACE, STATE (no terrain), DEVICE.
+ * The workspace's first bytes after the top level hold the exact-pass ray
+ * count (uint32) of the last call; see rc_render_exact_count. */
 rc_status rc_render(const rc_scene* scene, const rc_render_args* args, void* ws,
                     size_t ws_bytes, rc_stream stream);
+
+/* Number of rays the last rc_render on this workspace sent to the exact pass
+ * (a diagnostic).  Synchronises `stream`. */
+rc_status rc_render_exact_count(const rc_scene* scene, int32_t n_env, int32_t n_cam,
+                                int32_t width, int32_t height, const void* ws, int64_t* count,
+                                rc_stream stream);
 
 /* ---------------------------------------------------------------------
  * Sensor model: latency, noise, dropout (Sec. 1, Sec. 4.1, Table 6).

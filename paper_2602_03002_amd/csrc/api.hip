@@ -235,20 +235,45 @@ rc_status rc_robot_meshes(rc_scene* scene, const float* link_tri, const int64_t*
     return RC_OK;
 }
 
-static size_t render_layout(int32_t n_env, int32_t n_links, size_t* xf_off) {
-    if (n_links <= 0) { *xf_off = 0; return 256; }
-    const int64_t n_rec = n_links > 1 ? n_links - 1 : 1;
-    size_t o = align_up((size_t)n_env * n_rec * sizeof(Node));
-    *xf_off = o;
-    o = align_up(o + (size_t)n_env * n_links * sizeof(InstXform));
-    return o;
+// Render workspace: top-level records and instance transforms (with links),
+// then the exact pass's counter and its list (one slot per ray).
+struct RenderWs {
+    size_t xf, count, list, end;
+};
+
+static RenderWs render_layout(int64_t n_env, int64_t n_rays, int32_t n_links) {
+    RenderWs L;
+    size_t o = 0;
+    if (n_links > 0) {
+        const int64_t n_rec = n_links > 1 ? n_links - 1 : 1;
+        o = align_up((size_t)n_env * n_rec * sizeof(Node));
+        L.xf = o;
+        o = align_up(o + (size_t)n_env * n_links * sizeof(InstXform));
+    } else {
+        L.xf = 0;
+    }
+    L.count = o;
+    o = align_up(o + 4);
+    L.list = o;
+    o = align_up(o + (size_t)n_rays * 4);
+    L.end = o;
+    return L;
 }
 
-rc_status rc_render_size(const rc_scene* scene, int32_t n_env, size_t* ws_bytes) {
+static bool render_dims_ok(int32_t n_env, int32_t n_cam, int32_t width, int32_t height) {
+    if (n_env < 1 || n_cam < 1 || width < 1 || height < 1 || width > 65535 || height > 65535)
+        return false;
+    const int64_t n_rays = (int64_t)n_env * n_cam * width * height;
+    return n_rays <= (int64_t)0xFFFFFFFF;
+}
+
+rc_status rc_render_size(const rc_scene* scene, int32_t n_env, int32_t n_cam, int32_t width,
+                         int32_t height, size_t* ws_bytes) {
     if (!scene || !ws_bytes) return fail(RC_ERR_INVALID_ARG, "rc_render_size: NULL pointer");
-    if (n_env < 1) return fail(RC_ERR_INVALID_ARG, "rc_render_size: n_env must be >= 1");
-    size_t xo;
-    *ws_bytes = render_layout(n_env, scene->n_links, &xo);
+    if (!render_dims_ok(n_env, n_cam, width, height))
+        return fail(RC_ERR_INVALID_ARG, "rc_render_size: sizes must be >= 1, width and height "
+                                        "<= 65535, at most 2^32 - 1 rays");
+    *ws_bytes = render_layout(n_env, (int64_t)n_env * n_cam * width * height, scene->n_links).end;
     return RC_OK;
 }
 
@@ -256,13 +281,9 @@ rc_status rc_render(const rc_scene* scene, const rc_render_args* a, void* ws, si
                     rc_stream stream) {
     if (!scene || !a) return fail(RC_ERR_INVALID_ARG, "rc_render: NULL scene or args");
     if (!scene->ws) return fail(RC_ERR_STATE, "rc_render: scene has no terrain");
-    if (a->n_env < 1 || a->n_cam < 1 || a->width < 1 || a->height < 1 || a->width > 65535 ||
-        a->height > 65535)
-        return fail(RC_ERR_INVALID_ARG, "rc_render: sizes must be >= 1 (width, height <= 65535)");
-    const int64_t n_img = (int64_t)a->n_env * a->n_cam;
-    const int64_t tiles = n_img * ((a->width + 7) / 8) * ((a->height + 7) / 8);
-    if (tiles > (int64_t)0x7FFFFFFF / 2)
-        return fail(RC_ERR_UNSUPPORTED, "rc_render: too many pixels for one launch");
+    if (!render_dims_ok(a->n_env, a->n_cam, a->width, a->height))
+        return fail(RC_ERR_INVALID_ARG, "rc_render: sizes must be >= 1, width and height <= 65535, "
+                                        "at most 2^32 - 1 rays");
     if (!a->cam_pos || !a->cam_quat || !a->intr || !a->depth)
         return fail(RC_ERR_INVALID_ARG, "rc_render: cam_pos, cam_quat, intr and depth are required");
     if (scene->n_links > 0 && (!a->link_pos || !a->link_quat))
@@ -271,11 +292,12 @@ rc_status rc_render(const rc_scene* scene, const rc_render_args* a, void* ws, si
         return fail(RC_ERR_INVALID_ARG, "rc_render: far_plane must be finite and > 0");
     if (a->depth_mode != RC_DEPTH_PLANAR && a->depth_mode != RC_DEPTH_RANGE)
         return fail(RC_ERR_INVALID_ARG, "rc_render: unknown depth_mode");
-    size_t xf_off;
-    size_t need = render_layout(a->n_env, scene->n_links, &xf_off);
-    if (scene->n_links > 0 && (!ws || ws_bytes < need || !aligned(ws)))
-        return fail(RC_ERR_WORKSPACE, "rc_render: workspace needs " + std::to_string(need) +
+    const int64_t n_rays = (int64_t)a->n_env * a->n_cam * a->width * a->height;
+    const RenderWs W = render_layout(a->n_env, n_rays, scene->n_links);
+    if (!ws || ws_bytes < W.end || !aligned(ws))
+        return fail(RC_ERR_WORKSPACE, "rc_render: workspace needs " + std::to_string(W.end) +
                                           " bytes, 256-byte aligned");
+    const size_t xf_off = W.xf;
     hipStream_t s = (hipStream_t)stream;
     RenderLaunch L;
     L.terrain_nodes = (const Node*)(scene->ws + scene->terrain.nodes);
@@ -302,6 +324,9 @@ rc_status rc_render(const rc_scene* scene, const rc_render_args* a, void* ws, si
     L.n_links = scene->n_links;
     L.depth_mode = a->depth_mode;
     L.n_terrain = (int)scene->terrain.n_prim;
+    L.exact_count = (uint32_t*)((char*)ws + W.count);
+    L.exact_list = (uint32_t*)((char*)ws + W.list);
+    L.exact_cap = n_rays;
     L.far_plane = a->far_plane;
     hipError_t e = hipSuccess;
     if (scene->n_links > 0)
@@ -309,6 +334,22 @@ rc_status rc_render(const rc_scene* scene, const rc_render_args* a, void* ws, si
                               (Node*)ws, (InstXform*)((char*)ws + xf_off), s);
     if (e == hipSuccess) e = launch_render(L, s);
     if (e != hipSuccess) return hip_fail(e, "rc_render: launch");
+    return RC_OK;
+}
+
+rc_status rc_render_exact_count(const rc_scene* scene, int32_t n_env, int32_t n_cam,
+                                int32_t width, int32_t height, const void* ws, int64_t* count,
+                                rc_stream stream) {
+    if (!scene || !ws || !count) return fail(RC_ERR_INVALID_ARG, "rc_render_exact_count: NULL pointer");
+    if (!render_dims_ok(n_env, n_cam, width, height))
+        return fail(RC_ERR_INVALID_ARG, "rc_render_exact_count: bad sizes");
+    const RenderWs W = render_layout(n_env, (int64_t)n_env * n_cam * width * height, scene->n_links);
+    uint32_t c = 0;
+    hipError_t e = hipMemcpyAsync(&c, (const char*)ws + W.count, 4, hipMemcpyDeviceToHost,
+                                  (hipStream_t)stream);
+    if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "rc_render_exact_count");
+    *count = c;
     return RC_OK;
 }
 

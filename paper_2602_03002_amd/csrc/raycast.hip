@@ -31,19 +31,20 @@ namespace {
 
 constexpr int kTile = 8;             // 8 x 8 pixels per wavefront
 constexpr int kWavesPerBlock = 4;
-constexpr float kEdgeRel = 1.0f / 256.0f;  // FP32 edge decision margin (relative)
+// FP32 edge decisions are trusted when every edge function is farther than
+// kappa * (|U| + |V| + |W|) from zero.  The FP32 error relative to that sum is
+// about 1e-5 for terrain triangles (world frame) and about 1e-4 for the small
+// link triangles seen through the FP32 link transform; the margins below are
+// 20-40 times larger.
+constexpr float kTerrainKappa = 1.0f / 4096.0f;
+constexpr float kLinkKappa = 1.0f / 256.0f;
 
-struct TRay {
-    float ox, oy, oz;     // origin
-    float ix, iy, iz;     // 1 / d (components clamped away from 0)
-    float oix, oiy, oiz;  // o * (1 / d)
-    float m1x, m1y, m1z;  // shear rows: x' = m1 . (v - o), y' = m2 . (v - o),
-    float m2x, m2y, m2z;  //              z' = m3 . (v - o)
-    float m3x, m3y, m3z;
+struct Slab {  // box-test form of a ray: t = b * (1/d) - o * (1/d)
+    float ix, iy, iz, oix, oiy, oiz;
 };
 
-struct Ray64 {  // world ray: o exact (float), d = (dx, dy, dz) + (lx, ly, lz)
-    float ox, oy, oz, dx, dy, dz, lx, ly, lz;
+struct Shear {  // rows of the watertight shear: x' = m1.(v-o), y' = m2.(v-o), z' = m3.(v-o)
+    float m1x, m1y, m1z, m2x, m2y, m2z, m3x, m3y, m3z;
 };
 
 __device__ __forceinline__ float safe_inv(float d) {
@@ -51,11 +52,16 @@ __device__ __forceinline__ float safe_inv(float d) {
     return 1.0f / a;
 }
 
-__device__ __forceinline__ void make_tray(float ox, float oy, float oz, float dx, float dy,
-                                          float dz, TRay& r) {
-    r.ox = ox; r.oy = oy; r.oz = oz;
-    r.ix = safe_inv(dx); r.iy = safe_inv(dy); r.iz = safe_inv(dz);
-    r.oix = ox * r.ix; r.oiy = oy * r.iy; r.oiz = oz * r.iz;
+__device__ __forceinline__ Slab make_slab(float ox, float oy, float oz, float dx, float dy, float dz) {
+    Slab s;
+    s.ix = safe_inv(dx); s.iy = safe_inv(dy); s.iz = safe_inv(dz);
+    s.oix = ox * s.ix; s.oiy = oy * s.iy; s.oiz = oz * s.iz;
+    return s;
+}
+
+// Woop, Benthin, Wald (2013): kz = dominant axis of d, (kx, ky) the next two
+// (swapped when d[kz] < 0), Sx = d[kx]/d[kz], Sy = d[ky]/d[kz], Sz = 1/d[kz].
+__device__ __forceinline__ Shear make_shear(float dx, float dy, float dz) {
     float ax = fabsf(dx), ay = fabsf(dy), az = fabsf(dz);
     int kz = (ax > ay) ? (ax > az ? 0 : 2) : (ay > az ? 1 : 2);
     int kx = kz == 2 ? 0 : kz + 1;
@@ -66,20 +72,22 @@ __device__ __forceinline__ void make_tray(float ox, float oy, float oz, float dx
     float dky = ky == 0 ? dx : (ky == 1 ? dy : dz);
     float sz = 1.0f / dk;
     float sx = dkx * sz, sy = dky * sz;
-    r.m1x = (kx == 0) ? 1.0f : (kz == 0 ? -sx : 0.0f);
-    r.m1y = (kx == 1) ? 1.0f : (kz == 1 ? -sx : 0.0f);
-    r.m1z = (kx == 2) ? 1.0f : (kz == 2 ? -sx : 0.0f);
-    r.m2x = (ky == 0) ? 1.0f : (kz == 0 ? -sy : 0.0f);
-    r.m2y = (ky == 1) ? 1.0f : (kz == 1 ? -sy : 0.0f);
-    r.m2z = (ky == 2) ? 1.0f : (kz == 2 ? -sy : 0.0f);
-    r.m3x = kz == 0 ? sz : 0.0f;
-    r.m3y = kz == 1 ? sz : 0.0f;
-    r.m3z = kz == 2 ? sz : 0.0f;
+    Shear m;
+    m.m1x = (kx == 0) ? 1.0f : (kz == 0 ? -sx : 0.0f);
+    m.m1y = (kx == 1) ? 1.0f : (kz == 1 ? -sx : 0.0f);
+    m.m1z = (kx == 2) ? 1.0f : (kz == 2 ? -sx : 0.0f);
+    m.m2x = (ky == 0) ? 1.0f : (kz == 0 ? -sy : 0.0f);
+    m.m2y = (ky == 1) ? 1.0f : (kz == 1 ? -sy : 0.0f);
+    m.m2z = (ky == 2) ? 1.0f : (kz == 2 ? -sy : 0.0f);
+    m.m3x = kz == 0 ? sz : 0.0f;
+    m.m3y = kz == 1 ? sz : 0.0f;
+    m.m3z = kz == 2 ? sz : 0.0f;
+    return m;
 }
 
-// Slab test of one box (lo.x, hi.x, lo.y, hi.y, lo.z, hi.z) over (0, tmax].
+// Slab test of one box (lo.x, hi.x, lo.y, hi.y, lo.z, hi.z) over [0, tmax].
 __device__ __forceinline__ bool slab(float lx, float hx, float ly, float hy, float lz, float hz,
-                                     const TRay& r, float tmax, float& tn) {
+                                     const Slab& r, float tmax, float& tn) {
     float tx0 = __fmaf_rn(lx, r.ix, -r.oix), tx1 = __fmaf_rn(hx, r.ix, -r.oix);
     float ty0 = __fmaf_rn(ly, r.iy, -r.oiy), ty1 = __fmaf_rn(hy, r.iy, -r.oiy);
     float tz0 = __fmaf_rn(lz, r.iz, -r.oiz), tz1 = __fmaf_rn(hz, r.iz, -r.oiz);
@@ -89,19 +97,16 @@ __device__ __forceinline__ bool slab(float lx, float hx, float ly, float hy, flo
     return a <= b;
 }
 
-// FP64 watertight test of one triangle against an FP64 ray; closed triangle,
-// both sides; returns whether it is hit at t > 0 and sets t.
-__device__ __noinline__ bool tri_test64(const float* __restrict__ v, double ox, double oy, double oz,
-                                        double dx, double dy, double dz, double& t) {
-    double ax = fabs(dx), ay = fabs(dy), az = fabs(dz);
+// FP64 watertight test of one triangle; closed triangle, both sides; hit at t > 0.
+__device__ __forceinline__ bool tri_test64(const float* __restrict__ v, const double o[3],
+                                           const double d[3], double& t) {
+    double ax = fabs(d[0]), ay = fabs(d[1]), az = fabs(d[2]);
     int kz = (ax > ay) ? (ax > az ? 0 : 2) : (ay > az ? 1 : 2);
     int kx = kz == 2 ? 0 : kz + 1;
     int ky = kx == 2 ? 0 : kx + 1;
-    double d[3] = {dx, dy, dz};
     if (d[kz] < 0.0) { int s = kx; kx = ky; ky = s; }
     double sz = 1.0 / d[kz];
     double sx = d[kx] * sz, sy = d[ky] * sz;
-    double o[3] = {ox, oy, oz};
     double X[3], Y[3], Z[3];
     for (int k = 0; k < 3; ++k) {
         double p[3] = {(double)v[3 * k] - o[0], (double)v[3 * k + 1] - o[1], (double)v[3 * k + 2] - o[2]};
@@ -119,101 +124,146 @@ __device__ __noinline__ bool tri_test64(const float* __restrict__ v, double ox, 
     return t > 0.0;
 }
 
-// FP64 ray of `link` in env `e` (or the world ray for link < 0).
-__device__ __noinline__ bool refine(const float* __restrict__ v, const Ray64& w, int link, int e,
-                                    int n_links, const float* __restrict__ link_pos,
-                                    const float* __restrict__ link_quat, double& t) {
-    double ox = w.ox, oy = w.oy, oz = w.oz;
-    double dx = (double)w.dx + (double)w.lx, dy = (double)w.dy + (double)w.ly,
-           dz = (double)w.dz + (double)w.lz;
+__device__ __forceinline__ void quat_mat64(const float* __restrict__ q, double R[9]) {
+    double x = q[0], y = q[1], z = q[2], w = q[3];
+    double n = sqrt(x * x + y * y + z * z + w * w);
+    x /= n; y /= n; z /= n; w /= n;
+    R[0] = 1 - 2 * (y * y + z * z); R[1] = 2 * (x * y - z * w); R[2] = 2 * (x * z + y * w);
+    R[3] = 2 * (x * y + z * w); R[4] = 1 - 2 * (x * x + z * z); R[5] = 2 * (y * z - x * w);
+    R[6] = 2 * (x * z - y * w); R[7] = 2 * (y * z + x * w); R[8] = 1 - 2 * (x * x + y * y);
+}
+
+// FP64 camera ray of pixel (x, y) of image ec: o = p_c, d = R(q_c) K^-1 [x+.5, y+.5, 1].
+__device__ __forceinline__ void pixel_ray64(const float* __restrict__ cam_pos,
+                                            const float* __restrict__ cam_quat,
+                                            const float* __restrict__ intr, int64_t ec, int x, int y,
+                                            double o[3], double d[3], double& rx, double& ry) {
+    const float* K = intr + 4 * ec;
+    rx = ((double)x + 0.5 - (double)K[2]) / (double)K[0];
+    ry = ((double)y + 0.5 - (double)K[3]) / (double)K[1];
+    double R[9];
+    quat_mat64(cam_quat + 4 * ec, R);
+    d[0] = R[0] * rx + R[1] * ry + R[2];
+    d[1] = R[3] * rx + R[4] * ry + R[5];
+    d[2] = R[6] * rx + R[7] * ry + R[8];
+    o[0] = cam_pos[3 * ec]; o[1] = cam_pos[3 * ec + 1]; o[2] = cam_pos[3 * ec + 2];
+}
+
+// The exact-decision path: rebuild the pixel's FP64 ray (and its FP64 link-frame
+// ray for link >= 0) and repeat the triangle test in FP64.  Rarely taken, so it
+// recomputes everything instead of keeping an FP64 ray live in registers.
+__device__ __noinline__ bool refine(const float* __restrict__ v, const float* __restrict__ cam_pos,
+                                    const float* __restrict__ cam_quat,
+                                    const float* __restrict__ intr, int64_t ec, int x, int y,
+                                    int link, int e, int n_links,
+                                    const float* __restrict__ link_pos,
+                                    const float* __restrict__ link_quat, double* t) {
+    double o[3], d[3], rx, ry;
+    pixel_ray64(cam_pos, cam_quat, intr, ec, x, y, o, d, rx, ry);
     if (link >= 0) {
         const int64_t eb = (int64_t)e * n_links + link;
-        const float* q = link_quat + 4 * eb;
+        double R[9];
+        quat_mat64(link_quat + 4 * eb, R);
         const float* p = link_pos + 3 * eb;
-        double x = q[0], y = q[1], z = q[2], ww = q[3];
-        double n = sqrt(x * x + y * y + z * z + ww * ww);
-        x /= n; y /= n; z /= n; ww /= n;
-        double R[9] = {1 - 2 * (y * y + z * z), 2 * (x * y - z * ww), 2 * (x * z + y * ww),
-                       2 * (x * y + z * ww), 1 - 2 * (x * x + z * z), 2 * (y * z - x * ww),
-                       2 * (x * z - y * ww), 2 * (y * z + x * ww), 1 - 2 * (x * x + y * y)};
-        double px = ox - (double)p[0], py = oy - (double)p[1], pz = oz - (double)p[2];
-        double lox = R[0] * px + R[3] * py + R[6] * pz;
-        double loy = R[1] * px + R[4] * py + R[7] * pz;
-        double loz = R[2] * px + R[5] * py + R[8] * pz;
-        double ldx = R[0] * dx + R[3] * dy + R[6] * dz;
-        double ldy = R[1] * dx + R[4] * dy + R[7] * dz;
-        double ldz = R[2] * dx + R[5] * dy + R[8] * dz;
-        return tri_test64(v, lox, loy, loz, ldx, ldy, ldz, t);
+        double q[3] = {o[0] - (double)p[0], o[1] - (double)p[1], o[2] - (double)p[2]};
+        double lo[3], ld[3];
+        for (int k = 0; k < 3; ++k) {
+            lo[k] = R[k] * q[0] + R[3 + k] * q[1] + R[6 + k] * q[2];
+            ld[k] = R[k] * d[0] + R[3 + k] * d[1] + R[6 + k] * d[2];
+        }
+        return tri_test64(v, lo, ld, *t);
     }
-    return tri_test64(v, ox, oy, oz, dx, dy, dz, t);
+    return tri_test64(v, o, d, *t);
 }
 
 struct Hit {
-    float tmax;          // current bound = depth parameter of the best hit so far
-    uint64_t key;        // (inst << 32) | tri of the best hit, ~0 for none
+    float tmax;    // current bound = ray parameter of the best hit so far
+    uint64_t key;  // (inst << 32) | tri of the best hit, ~0 for none
+    float tu;      // fast pass: smallest ray parameter of an FP32-undecided test
 };
 
-// Test leaf `leaf` of a hierarchy whose leaf-order triangles start at `tris`.
-__device__ __forceinline__ void leaf_tri(const float* __restrict__ tris,
-                                         const int32_t* __restrict__ ids, int leaf, uint32_t inst,
-                                         const TRay& r, Hit& h, const Ray64& w, int link, int e,
-                                         int n_links, const float* __restrict__ link_pos,
-                                         const float* __restrict__ link_quat) {
-    const float* v = tris + 9 * (int64_t)leaf;
-    float p0x = v[0] - r.ox, p0y = v[1] - r.oy, p0z = v[2] - r.oz;
-    float p1x = v[3] - r.ox, p1y = v[4] - r.oy, p1z = v[5] - r.oz;
-    float p2x = v[6] - r.ox, p2y = v[7] - r.oy, p2z = v[8] - r.oz;
-    float Ax = __fmaf_rn(r.m1z, p0z, __fmaf_rn(r.m1y, p0y, r.m1x * p0x));
-    float Ay = __fmaf_rn(r.m2z, p0z, __fmaf_rn(r.m2y, p0y, r.m2x * p0x));
-    float Bx = __fmaf_rn(r.m1z, p1z, __fmaf_rn(r.m1y, p1y, r.m1x * p1x));
-    float By = __fmaf_rn(r.m2z, p1z, __fmaf_rn(r.m2y, p1y, r.m2x * p1x));
-    float Cx = __fmaf_rn(r.m1z, p2z, __fmaf_rn(r.m1y, p2y, r.m1x * p2x));
-    float Cy = __fmaf_rn(r.m2z, p2z, __fmaf_rn(r.m2y, p2y, r.m2x * p2x));
-    float U = __fmaf_rn(Cx, By, -(Cy * Bx));
-    float V = __fmaf_rn(Ax, Cy, -(Ay * Cx));
-    float W = __fmaf_rn(Bx, Ay, -(By * Ax));
-    float thr = (fabsf(U) + fabsf(V) + fabsf(W)) * kEdgeRel;
-    bool neg = (U < -thr) || (V < -thr) || (W < -thr);
-    bool pos = (U > thr) || (V > thr) || (W > thr);
-    if (neg && pos) return;  // certain miss
+struct PixelRef {  // what the exact-decision path needs to rebuild the ray
+    const float* cam_pos;
+    const float* cam_quat;
+    const float* intr;
+    const float* link_pos;
+    const float* link_quat;
+    int64_t ec;
+    int x, y, e, n_links;
+};
+
+// Test one triangle (leaf-order record v) against the ray (origin o, shear m).
+// FP32 decides when all three edge functions clearly share a sign (hit) or
+// clearly disagree (miss).  Otherwise the fast pass only records the plane
+// distance in h.tu (the ray is re-cast by the exact pass if that could beat
+// its final hit), and the exact pass repeats the test in FP64.
+template <bool EXACT>
+__device__ __forceinline__ void tri_test(const float* __restrict__ v, int32_t tri_id, uint32_t inst,
+                                         float ox, float oy, float oz, const Shear& m, float kappa,
+                                         Hit& h, const PixelRef& px, int link) {
+    const float p0x = v[0] - ox, p0y = v[1] - oy, p0z = v[2] - oz;
+    const float p1x = v[3] - ox, p1y = v[4] - oy, p1z = v[5] - oz;
+    const float p2x = v[6] - ox, p2y = v[7] - oy, p2z = v[8] - oz;
+    const float Ax = __fmaf_rn(m.m1z, p0z, __fmaf_rn(m.m1y, p0y, m.m1x * p0x));
+    const float Ay = __fmaf_rn(m.m2z, p0z, __fmaf_rn(m.m2y, p0y, m.m2x * p0x));
+    const float Bx = __fmaf_rn(m.m1z, p1z, __fmaf_rn(m.m1y, p1y, m.m1x * p1x));
+    const float By = __fmaf_rn(m.m2z, p1z, __fmaf_rn(m.m2y, p1y, m.m2x * p1x));
+    const float Cx = __fmaf_rn(m.m1z, p2z, __fmaf_rn(m.m1y, p2y, m.m1x * p2x));
+    const float Cy = __fmaf_rn(m.m2z, p2z, __fmaf_rn(m.m2y, p2y, m.m2x * p2x));
+    const float U = __fmaf_rn(Cx, By, -(Cy * Bx));
+    const float V = __fmaf_rn(Ax, Cy, -(Ay * Cx));
+    const float W = __fmaf_rn(Bx, Ay, -(By * Ax));
+    const float thr = (fabsf(U) + fabsf(V) + fabsf(W)) * kappa;
+    const bool neg = (U < -thr) || (V < -thr) || (W < -thr);
+    const bool pos = (U > thr) || (V > thr) || (W > thr);
+    if (neg && pos) return;  // certainly outside
+    const bool sure = thr > 0.0f && (neg != pos);
     float t;
-    bool sure = !(neg && pos) && ((U >= thr && V >= thr && W >= thr) ||
-                                  (U <= -thr && V <= -thr && W <= -thr)) && thr > 0.0f;
-    if (sure) {
-        float Az = __fmaf_rn(r.m3z, p0z, __fmaf_rn(r.m3y, p0y, r.m3x * p0x));
-        float Bz = __fmaf_rn(r.m3z, p1z, __fmaf_rn(r.m3y, p1y, r.m3x * p1x));
-        float Cz = __fmaf_rn(r.m3z, p2z, __fmaf_rn(r.m3y, p2y, r.m3x * p2x));
-        float det = U + V + W;
-        float T = __fmaf_rn(W, Cz, __fmaf_rn(V, Bz, U * Az));
+    if (!EXACT || sure) {
+        const float Az = __fmaf_rn(m.m3z, p0z, __fmaf_rn(m.m3y, p0y, m.m3x * p0x));
+        const float Bz = __fmaf_rn(m.m3z, p1z, __fmaf_rn(m.m3y, p1y, m.m3x * p1x));
+        const float Cz = __fmaf_rn(m.m3z, p2z, __fmaf_rn(m.m3y, p2y, m.m3x * p2x));
+        const float det = U + V + W;
+        const float T = __fmaf_rn(W, Cz, __fmaf_rn(V, Bz, U * Az));
         t = T / det;
+        if (!EXACT && !sure) {
+            // undecided in FP32: remember how near it could be; a plane behind
+            // the origin (well conditioned) cannot matter
+            const bool cond = fabsf(det) > thr;
+            if (!(cond && t < -1e-3f)) h.tu = fminf(h.tu, (cond && t > 0.0f) ? t : 0.0f);
+            return;
+        }
     } else {
         double t64;
-        if (!refine(v, w, link, e, n_links, link_pos, link_quat, t64)) return;
+        if (!refine(v, px.cam_pos, px.cam_quat, px.intr, px.ec, px.x, px.y, link, px.e, px.n_links,
+                    px.link_pos, px.link_quat, &t64))
+            return;
         t = (float)t64;
     }
     if (!(t > 0.0f) || t > h.tmax) return;
-    uint64_t key = ((uint64_t)inst << 32) | (uint32_t)ids[leaf];
+    const uint64_t key = ((uint64_t)inst << 32) | (uint32_t)tri_id;
     if (t < h.tmax || key < h.key) {
         h.tmax = t;
         h.key = key;
     }
 }
 
-// Stackless nearest-first traversal of one hierarchy of n_nodes records and
-// n_prim leaves.  `leaf(i)` handles leaf i.  Indices are range-checked and the
-// loop is bounded (a valid hierarchy needs fewer than 2 n_nodes + 2 steps),
-// so a corrupt hierarchy ends the ray instead of faulting or spinning.
+// Per-lane stackless nearest-first traversal of one hierarchy of n_nodes
+// records and n_prim leaves; `leaf(i)` handles leaf i.  Indices are range
+// checked and the loop is bounded (a valid hierarchy needs fewer than
+// 2 n_nodes + 2 steps), so a corrupt hierarchy ends the ray instead of
+// faulting or spinning.
 template <typename Leaf>
 __device__ __forceinline__ void traverse(const Node* __restrict__ nodes, int n_nodes, int n_prim,
-                                         const TRay& r, Hit& h, Leaf&& leaf) {
+                                         const Slab& r, Hit& h, Leaf&& leaf) {
     uint64_t trail = 0;
     int cur = 0;
     int budget = 2 * n_nodes + 2;
     for (;;) {
         if ((unsigned)cur >= (unsigned)n_nodes || --budget < 0) return;
         const float4* np = reinterpret_cast<const float4*>(nodes + cur);
-        float4 q0 = np[0], q1 = np[1], q2 = np[2];
-        int4 q3 = reinterpret_cast<const int4*>(np)[3];
+        const float4 q0 = np[0], q1 = np[1], q2 = np[2];
+        const int4 q3 = reinterpret_cast<const int4*>(np)[3];
         float tn0, tn1;
         bool h0 = slab(q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, r, h.tmax, tn0);
         bool h1 = slab(q1.z, q1.w, q2.x, q2.y, q2.z, q2.w, r, h.tmax, tn1);
@@ -221,13 +271,15 @@ __device__ __forceinline__ void traverse(const Node* __restrict__ nodes, int n_n
         h0 = h0 && (c0 >= 0 || (unsigned)~c0 < (unsigned)n_prim);
         h1 = h1 && (c1 >= 0 || (unsigned)~c1 < (unsigned)n_prim);
         const bool l0 = h0 && c0 < 0, l1 = h1 && c1 < 0;
-        if (l0 || l1) {
-            if (l0 && l1) {
-                const bool first1 = tn1 < tn0;
-                leaf(first1 ? ~c1 : ~c0);
-                if ((first1 ? tn0 : tn1) <= h.tmax) leaf(first1 ? ~c0 : ~c1);
-            } else {
-                leaf(l0 ? ~c0 : ~c1);
+        if (l0 || l1) {  // leaf children first, nearest first
+            const bool swap = l0 && l1 && tn1 < tn0;
+            const int la = (l0 && !swap) ? ~c0 : ~c1;
+            const int lb = (l0 && l1) ? (swap ? ~c0 : ~c1) : -1;
+            const float tb = swap ? tn0 : tn1;
+            for (int k = 0; k < 2; ++k) {
+                const int lf = k == 0 ? la : lb;
+                if (lf < 0 || (k == 1 && tb > h.tmax)) break;
+                leaf(lf);
             }
         }
         const bool g0 = h0 && !l0 && tn0 <= h.tmax;
@@ -253,13 +305,140 @@ __device__ __forceinline__ void traverse(const Node* __restrict__ nodes, int n_n
             }
             trail >>= 1;
             if ((unsigned)par >= (unsigned)n_nodes || --budget < 0) return;
-            int4 pq = reinterpret_cast<const int4*>(nodes + par)[3];
+            const int4 pq = reinterpret_cast<const int4*>(nodes + par)[3];
             par = pq.z;
             sib = pq.w;
         }
     }
 }
 
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Enter link b of env e: take the ray to the link frame (o_b = R_b^T (o - t_b),
+// d_b = R_b^T d) and traverse the link's hierarchy under the current bound.
+template <bool EXACT>
+__device__ __forceinline__ void enter_link(const RenderLaunch& a, int e, int b, float ox, float oy,
+                                           float oz, float dx, float dy, float dz, Hit& h,
+                                           const PixelRef& px) {
+    const InstXform X = a.xf[(int64_t)e * a.n_links + b];
+    const float px_ = ox - X.t[0], py_ = oy - X.t[1], pz_ = oz - X.t[2];
+    const float lox = __fmaf_rn(X.m[2], pz_, __fmaf_rn(X.m[1], py_, X.m[0] * px_));
+    const float loy = __fmaf_rn(X.m[5], pz_, __fmaf_rn(X.m[4], py_, X.m[3] * px_));
+    const float loz = __fmaf_rn(X.m[8], pz_, __fmaf_rn(X.m[7], py_, X.m[6] * px_));
+    const float ldx = __fmaf_rn(X.m[2], dz, __fmaf_rn(X.m[1], dy, X.m[0] * dx));
+    const float ldy = __fmaf_rn(X.m[5], dz, __fmaf_rn(X.m[4], dy, X.m[3] * dx));
+    const float ldz = __fmaf_rn(X.m[8], dz, __fmaf_rn(X.m[7], dy, X.m[6] * dx));
+    const Slab ls = make_slab(lox, loy, loz, ldx, ldy, ldz);
+    const Shear lm = make_shear(ldx, ldy, ldz);
+    const LinkMeta M = a.link_meta[b];
+    const float* __restrict__ tris = a.link_tris + M.tri_base;
+    const int32_t* __restrict__ ids = a.link_tri_id + M.id_base;
+    traverse(a.link_nodes + M.node_base, M.n_tri > 1 ? M.n_tri - 1 : 1, M.n_tri, ls, h, [&](int i) {
+        tri_test<EXACT>(tris + 9 * (int64_t)i, ids[i], (uint32_t)b, lox, loy, loz, lm, kLinkKappa, h,
+                        px, b);
+    });
+}
+
+// One pixel ray: robot bodies first, then the terrain under their bound
+// (Algorithm 1's query order).  WAVE: the wavefront shares the environment
+// and walks its top-level hierarchy together (trail and node records are
+// wave-uniform, in scalar registers; a node is entered if any lane's ray hits
+// it, a link only by the lanes whose rays hit its box).  Otherwise each lane
+// walks the top level alone.
+template <bool EXACT, bool WAVE>
+__device__ __forceinline__ Hit cast_ray(const RenderLaunch& a, int64_t ec, int e, int x, int y,
+                                        double& scale) {
+    double o64[3], d64[3], rx, ry;
+    pixel_ray64(a.cam_pos, a.cam_quat, a.intr, ec, x, y, o64, d64, rx, ry);
+    const float ox = (float)o64[0], oy = (float)o64[1], oz = (float)o64[2];
+    const float dx = (float)d64[0], dy = (float)d64[1], dz = (float)d64[2];
+    scale = a.depth_mode == RC_DEPTH_RANGE ? sqrt(rx * rx + ry * ry + 1.0) : 1.0;
+    Hit h;
+    h.tmax = (float)((double)a.far_plane / scale);
+    h.key = ~0ull;
+    h.tu = INFINITY;
+    const PixelRef px{a.cam_pos, a.cam_quat, a.intr, a.link_pos, a.link_quat, ec, x, y, e, a.n_links};
+
+    if (a.n_links > 0) {
+        const int n_rec = a.n_links > 1 ? a.n_links - 1 : 1;
+        const Node* __restrict__ tl = a.tlas + (int64_t)e * n_rec;
+        if (!WAVE) {
+            const Slab ws = make_slab(ox, oy, oz, dx, dy, dz);
+            traverse(tl, n_rec, a.n_links, ws, h, [&](int b) {
+                enter_link<EXACT>(a, e, b, ox, oy, oz, dx, dy, dz, h, px);
+            });
+        } else {
+            uint32_t trail = 0;
+            int cur = 0;
+            int budget = 2 * n_rec + 2;
+            for (;;) {
+                cur = uni(cur);
+                if ((unsigned)cur >= (unsigned)n_rec || --budget < 0) break;
+                const Node N = tl[cur];
+                const Slab ws = make_slab(ox, oy, oz, dx, dy, dz);
+                float tn0, tn1;
+                bool h0 = slab(N.b0[0], N.b0[1], N.b0[2], N.b0[3], N.b0[4], N.b0[5], ws, h.tmax, tn0);
+                bool h1 = slab(N.b1[0], N.b1[1], N.b1[2], N.b1[3], N.b1[4], N.b1[5], ws, h.tmax, tn1);
+                const int c0 = N.c0, c1 = N.c1;
+                h0 = h0 && (c0 >= 0 || (unsigned)~c0 < (unsigned)a.n_links);
+                h1 = h1 && (c1 >= 0 || (unsigned)~c1 < (unsigned)a.n_links);
+                for (int k = 0; k < 2; ++k) {  // instance children
+                    const int c = k == 0 ? c0 : c1;
+                    const bool hk = k == 0 ? h0 : h1;
+                    if (c >= 0 || __ballot(hk) == 0ull) continue;
+                    if (hk) enter_link<EXACT>(a, e, ~c, ox, oy, oz, dx, dy, dz, h, px);
+                }
+                const bool g0 = c0 >= 0 && h0 && tn0 <= h.tmax;
+                const bool g1 = c1 >= 0 && h1 && tn1 <= h.tmax;
+                const uint64_t G0 = __ballot(g0), G1 = __ballot(g1);
+                if (G0 && G1) {
+                    const int want1 = __popcll(__ballot(g1 && (!g0 || tn1 < tn0)));
+                    const int want0 = __popcll(__ballot(g0 && (!g1 || tn0 <= tn1)));
+                    trail = (trail << 1) | 1u;
+                    cur = want1 > want0 ? c1 : c0;
+                    continue;
+                }
+                if (G0 || G1) {
+                    trail <<= 1;
+                    cur = G0 ? c0 : c1;
+                    continue;
+                }
+                int par = N.parent, sib = N.sibling;
+                bool done = false;
+                for (;;) {
+                    if (trail == 0u) { done = true; break; }
+                    if (trail & 1u) { trail ^= 1u; cur = sib; break; }
+                    trail >>= 1;
+                    par = uni(par);
+                    if ((unsigned)par >= (unsigned)n_rec || --budget < 0) { done = true; break; }
+                    sib = tl[par].sibling;
+                    par = tl[par].parent;
+                }
+                if (done) break;
+            }
+        }
+    }
+    {
+        const Slab ws = make_slab(ox, oy, oz, dx, dy, dz);
+        const Shear wm = make_shear(dx, dy, dz);
+        traverse(a.terrain_nodes, a.n_terrain > 1 ? a.n_terrain - 1 : 1, a.n_terrain, ws, h,
+                 [&](int i) {
+                     tri_test<EXACT>(a.terrain_tris + 9 * (int64_t)i, a.terrain_tri_id[i],
+                                     (uint32_t)a.n_links, ox, oy, oz, wm, kTerrainKappa, h, px, -1);
+                 });
+    }
+    return h;
+}
+
+__device__ __forceinline__ void write_out(const RenderLaunch& a, int64_t p, const Hit& h,
+                                          double scale) {
+    const bool hit = h.key != ~0ull;
+    a.depth[p] = hit ? (float)((double)h.tmax * scale) : a.far_plane;
+    if (a.inst) a.inst[p] = hit ? (int32_t)(h.key >> 32) : -1;
+    if (a.tri) a.tri[p] = hit ? (int32_t)(uint32_t)h.key : -1;
+}
+
+// Fast pass: one 8x8 tile per wavefront, FP32 decisions only.
 __global__ void __launch_bounds__(256) k_render(RenderLaunch a, int64_t n_logical, int64_t per_xcd) {
     // XCD-aware order: hardware deals blocks round-robin over the 8 XCDs, so
     // give each XCD a contiguous run of tiles (neighbouring environments share
@@ -268,8 +447,7 @@ __global__ void __launch_bounds__(256) k_render(RenderLaunch a, int64_t n_logica
     const int64_t lb = (bid & 7) * per_xcd + (bid >> 3);
     if (lb >= n_logical) return;
     const int lane = threadIdx.x & 63;
-    const int64_t tile = (int64_t)__builtin_amdgcn_readfirstlane((int)(lb * kWavesPerBlock)) +
-                         __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t tile = (int64_t)uni((int)(lb * kWavesPerBlock)) + uni(threadIdx.x >> 6);
     const int tiles_x = (a.width + kTile - 1) / kTile;
     const int tiles_y = (a.height + kTile - 1) / kTile;
     const int64_t tiles_img = (int64_t)tiles_x * tiles_y;
@@ -280,72 +458,35 @@ __global__ void __launch_bounds__(256) k_render(RenderLaunch a, int64_t n_logica
     const int y = (tin / tiles_x) * kTile + (lane >> 3);
     if (x >= a.width || y >= a.height) return;
     const int e = (int)(ec / a.n_cam);
-
-    // 1. ray generation in FP64
-    const float* K = a.intr + 4 * ec;
-    const float* qc = a.cam_quat + 4 * ec;
-    const float* pc = a.cam_pos + 3 * ec;
-    double rx = ((double)x + 0.5 - (double)K[2]) / (double)K[0];
-    double ry = ((double)y + 0.5 - (double)K[3]) / (double)K[1];
-    double qx = qc[0], qy = qc[1], qz = qc[2], qw = qc[3];
-    double qn = sqrt(qx * qx + qy * qy + qz * qz + qw * qw);
-    qx /= qn; qy /= qn; qz /= qn; qw /= qn;
-    double dx = (1 - 2 * (qy * qy + qz * qz)) * rx + 2 * (qx * qy - qz * qw) * ry + 2 * (qx * qz + qy * qw);
-    double dy = 2 * (qx * qy + qz * qw) * rx + (1 - 2 * (qx * qx + qz * qz)) * ry + 2 * (qy * qz - qx * qw);
-    double dz = 2 * (qx * qz - qy * qw) * rx + 2 * (qy * qz + qx * qw) * ry + (1 - 2 * (qx * qx + qy * qy));
-    Ray64 w;
-    w.ox = pc[0]; w.oy = pc[1]; w.oz = pc[2];
-    w.dx = (float)dx; w.dy = (float)dy; w.dz = (float)dz;
-    w.lx = (float)(dx - (double)w.dx);
-    w.ly = (float)(dy - (double)w.dy);
-    w.lz = (float)(dz - (double)w.dz);
-    const double scale = a.depth_mode == RC_DEPTH_RANGE ? sqrt(rx * rx + ry * ry + 1.0) : 1.0;
-    Hit h;
-    h.tmax = (float)((double)a.far_plane / scale);
-    h.key = ~0ull;
-
-    TRay r;
-    // 2. robot bodies through the environment's top-level hierarchy
-    if (a.n_links > 0) {
-        make_tray(w.ox, w.oy, w.oz, w.dx, w.dy, w.dz, r);
-        const int n_rec = a.n_links > 1 ? a.n_links - 1 : 1;
-        const Node* tl = a.tlas + (int64_t)e * n_rec;
-        traverse(tl, n_rec, a.n_links, r, h, [&](int b) {
-            const InstXform X = a.xf[(int64_t)e * a.n_links + b];
-            const float px = w.ox - X.t[0], py = w.oy - X.t[1], pz = w.oz - X.t[2];
-            const float lox = __fmaf_rn(X.m[2], pz, __fmaf_rn(X.m[1], py, X.m[0] * px));
-            const float loy = __fmaf_rn(X.m[5], pz, __fmaf_rn(X.m[4], py, X.m[3] * px));
-            const float loz = __fmaf_rn(X.m[8], pz, __fmaf_rn(X.m[7], py, X.m[6] * px));
-            const float ldx = __fmaf_rn(X.m[2], w.dz, __fmaf_rn(X.m[1], w.dy, X.m[0] * w.dx));
-            const float ldy = __fmaf_rn(X.m[5], w.dz, __fmaf_rn(X.m[4], w.dy, X.m[3] * w.dx));
-            const float ldz = __fmaf_rn(X.m[8], w.dz, __fmaf_rn(X.m[7], w.dy, X.m[6] * w.dx));
-            TRay lr;
-            make_tray(lox, loy, loz, ldx, ldy, ldz, lr);
-            const LinkMeta M = a.link_meta[b];
-            const float* tris = a.link_tris + M.tri_base;
-            const int32_t* ids = a.link_tri_id + M.id_base;
-            traverse(a.link_nodes + M.node_base, M.n_tri > 1 ? M.n_tri - 1 : 1, M.n_tri, lr, h,
-                     [&](int leafi) {
-                leaf_tri(tris, ids, leafi, (uint32_t)b, lr, h, w, b, e, a.n_links, a.link_pos,
-                         a.link_quat);
-            });
-        });
-    }
-    // 3. terrain under the bound left by the bodies
-    make_tray(w.ox, w.oy, w.oz, w.dx, w.dy, w.dz, r);
-    traverse(a.terrain_nodes, a.n_terrain > 1 ? a.n_terrain - 1 : 1, a.n_terrain, r, h,
-             [&](int leafi) {
-        leaf_tri(a.terrain_tris, a.terrain_tri_id, leafi, (uint32_t)a.n_links, r, h, w, -1, e,
-                 a.n_links, a.link_pos, a.link_quat);
-    });
-
-    // 4. output D[e, c, y, x]
+    double scale;
+    const Hit h = cast_ray<false, true>(a, ec, e, x, y, scale);
     const int64_t p = ec * (int64_t)a.width * a.height + (int64_t)y * a.width + x;
-    const bool hit = h.key != ~0ull;
-    a.depth[p] = hit ? (float)((double)h.tmax * scale) : a.far_plane;
-    if (a.inst) a.inst[p] = hit ? (int32_t)(h.key >> 32) : -1;
-    if (a.tri) a.tri[p] = hit ? (int32_t)(uint32_t)h.key : -1;
+    write_out(a, p, h, scale);
+    // an FP32-undecided triangle at or before the hit: re-cast exactly
+    if (h.tu <= h.tmax * (1.0f + 1.0f / 1024.0f)) {
+        const uint32_t slot = atomicAdd(a.exact_count, 1u);
+        if ((int64_t)slot < a.exact_cap) a.exact_list[slot] = (uint32_t)p;
+    }
 }
+
+// Exact pass: the rays the fast pass listed, each lane on its own, with FP64
+// decisions for undecided triangles.
+__global__ void __launch_bounds__(256) k_render_exact(RenderLaunch a) {
+    const uint32_t n = *a.exact_count;
+    const int64_t hw = (int64_t)a.width * a.height;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (int64_t)n && i < a.exact_cap;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t p = a.exact_list[i];
+        const int64_t ec = p / hw;
+        const int pin = (int)(p - ec * hw);
+        const int x = pin % a.width, y = pin / a.width;
+        double scale;
+        const Hit h = cast_ray<true, false>(a, ec, (int)(ec / a.n_cam), x, y, scale);
+        write_out(a, p, h, scale);
+    }
+}
+
+__global__ void k_zero_count(uint32_t* c) { *c = 0u; }
 
 }  // namespace
 
@@ -355,8 +496,10 @@ hipError_t launch_render(const RenderLaunch& a, hipStream_t s) {
     const int64_t tiles = (int64_t)a.n_env * a.n_cam * tiles_x * tiles_y;
     const int64_t n_logical = (tiles + kWavesPerBlock - 1) / kWavesPerBlock;
     const int64_t per_xcd = (n_logical + 7) / 8;
+    hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(1), 0, s, a.exact_count);
     hipLaunchKernelGGL(k_render, dim3((unsigned)(per_xcd * 8)), dim3(64 * kWavesPerBlock), 0, s, a,
                        n_logical, per_xcd);
+    hipLaunchKernelGGL(k_render_exact, dim3(1024), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

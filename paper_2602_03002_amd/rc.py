@@ -20,7 +20,7 @@ EXPORTED = [
     "rc_version", "rc_status_string", "rc_last_error",
     "rc_scene_size", "rc_scene_create", "rc_scene_destroy",
     "rc_robot_size", "rc_robot_meshes",
-    "rc_render_size", "rc_render",
+    "rc_render_size", "rc_render", "rc_render_exact_count",
     "rc_post_size", "rc_post_create", "rc_post_reset", "rc_postprocess", "rc_post_destroy",
     "rc_bvh_layout_of",
 ]
@@ -77,7 +77,8 @@ def lib():
         L.rc_scene_destroy.argtypes = [vp]
         L.rc_robot_size.argtypes = [vp, i32, ctypes.POINTER(sz)]
         L.rc_robot_meshes.argtypes = [vp, vp, vp, i32, vp, sz, vp]
-        L.rc_render_size.argtypes = [vp, i32, ctypes.POINTER(sz)]
+        L.rc_render_size.argtypes = [vp, i32, i32, i32, i32, ctypes.POINTER(sz)]
+        L.rc_render_exact_count.argtypes = [vp, i32, i32, i32, i32, vp, ctypes.POINTER(i64), vp]
         L.rc_render.argtypes = [vp, ctypes.POINTER(RenderArgs), vp, sz, vp]
         L.rc_post_size.argtypes = [i32, i32, i32, i32, i32, ctypes.POINTER(sz)]
         L.rc_post_create.argtypes = [i32, i32, i32, i32, i32, vp, sz, ctypes.POINTER(vp)]
@@ -166,14 +167,23 @@ class Scene:
         self.n_links = nb
         self._render_ws = {}
 
-    def render_workspace(self, n_env):
-        ws = self._render_ws.get(n_env)
+    def render_workspace(self, n_env, n_cam, width, height):
+        key = (n_env, n_cam, width, height)
+        ws = self._render_ws.get(key)
         if ws is None:
             size = ctypes.c_size_t()
-            check(lib().rc_render_size(self.handle, n_env, ctypes.byref(size)))
+            check(lib().rc_render_size(self.handle, n_env, n_cam, width, height, ctypes.byref(size)))
             ws = Workspace(size.value, self.device)
-            self._render_ws[n_env] = ws
+            self._render_ws[key] = ws
         return ws
+
+    def exact_count(self, n_env, n_cam, width, height, stream=None):
+        """Rays the last render with these sizes sent to the exact pass."""
+        ws = self.render_workspace(n_env, n_cam, width, height)
+        c = ctypes.c_int64()
+        check(lib().rc_render_exact_count(self.handle, n_env, n_cam, width, height,
+                                          ctypes.c_void_p(ws.ptr), ctypes.byref(c), _stream(stream)))
+        return c.value
 
     def render(self, cam_pos, cam_quat, intr, width, height, far_plane, link_pos=None,
                link_quat=None, depth_mode=RC_DEPTH_PLANAR, out=None, ids=True, stream=None):
@@ -191,7 +201,7 @@ class Scene:
             tri = torch.empty_like(depth, dtype=torch.int32) if ids else None
         else:
             depth, inst, tri = out
-        ws = self.render_workspace(E)
+        ws = self.render_workspace(E, C, width, height)
         a = RenderArgs(E, C, width, height, _ptr(link_pos) if self.n_links else None,
                        _ptr(link_quat) if self.n_links else None, _ptr(cam_pos), _ptr(cam_quat),
                        _ptr(intr), float(far_plane), depth_mode, _ptr(depth), _ptr(inst), _ptr(tri))

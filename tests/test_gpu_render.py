@@ -271,3 +271,53 @@ def test_render_then_post_end_to_end():
             a = outs[s].reshape(w["E"] * w["C"], -1)[ec][ok]
             b = ro[s].reshape(w["E"] * w["C"], -1)[ec][ok]
             assert np.max(np.abs(a - b)) <= 1e-4
+
+
+def look_quat(direction):
+    from scipy.spatial.transform import Rotation
+    z = np.asarray(direction, float)
+    z = z / np.linalg.norm(z)
+    up = np.array([0.0, 0.0, 1.0]) if abs(z[2]) < 0.99 else np.array([1.0, 0.0, 0.0])
+    x = np.cross(z, up)
+    x /= np.linalg.norm(x)
+    return Rotation.from_matrix(np.stack([x, np.cross(z, x), z], 1)).as_quat()
+
+
+@pytest.mark.parametrize("as_link", [False, True])
+def test_watertight_vertices_and_edges(as_link):
+    """Rays aimed exactly at every vertex and edge midpoint of a closed convex
+    mesh (decisions FP32 cannot make: the exact pass must take them) hit it."""
+    say(f"[render] watertight vertex/edge rays, mesh as {'link' if as_link else 'terrain'}")
+    V, T = sg.octasphere(3)
+    mesh = (V[T] * 0.3).astype(np.float32)
+    centre = np.array([5.0, -3.0, 1.5])
+    pts = {tuple(v) for v in mesh.reshape(-1, 3).astype(np.float64)}
+    for t in mesh.astype(np.float64):
+        for i in range(3):
+            pts.add(tuple(0.5 * (t[i] + t[(i + 1) % 3])))
+    pts = np.array(sorted(pts))
+    E = pts.shape[0]
+    dirs = pts / np.linalg.norm(pts, axis=1, keepdims=True)
+    cam_pos = (centre + 2.0 * dirs)[:, None, :].astype(np.float32)
+    cam_quat = np.array([[look_quat(-p)] for p in dirs], np.float32)
+    intr = np.tile(np.float32([1, 1, 0.5, 0.5]), (E, 1, 1))
+    far_tri = np.array([[[50, 50, 50], [51, 50, 50], [50, 51, 50]]], np.float32)
+    if as_link:
+        w = dict(terrain=far_tri, link_tri=mesh, link_off=np.array([0, mesh.shape[0]], np.int64),
+                 link_pos=np.tile(centre.astype(np.float32), (1, E, 1, 1)),
+                 link_quat=np.tile(np.float32([0, 0, 0, 1]), (1, E, 1, 1)))
+        inst_expect = 0
+    else:
+        w = dict(terrain=(mesh + centre).astype(np.float32), link_tri=np.zeros((0, 3, 3), np.float32),
+                 link_off=np.zeros(1, np.int64), link_pos=np.zeros((1, E, 0, 3), np.float32),
+                 link_quat=np.zeros((1, E, 0, 4), np.float32))
+        inst_expect = 0
+    w.update(E=E, C=1, W=1, H=1, cam_pos=cam_pos, cam_quat=cam_quat, intr=intr, far=10.0)
+    sc = make_scene(w)
+    d, i, t = render(sc, w)
+    n_exact = sc.exact_count(E, 1, 1, 1)
+    say(f"  {E} rays, {n_exact} re-cast by the exact pass")
+    assert np.all(i.ravel() == inst_expect), "a ray slipped through an edge or vertex"
+    ref = oracle_render(w)
+    assert_parity(d, i, t, ref, w["far"], label="watertight")
+    assert n_exact > 0
