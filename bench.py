@@ -151,6 +151,7 @@ def main():
     rays = E * C * H * W
     value = rays * args.steps / (gpu_ms / 1e3) / 1e6
 
+    exact_rays = sc.exact_count(E, C, W, H)
     bpr, ref = bytes_per_ray()
     roof = None
     if bpr is not None:
@@ -171,7 +172,8 @@ def main():
                                f"20x20-tile terrain ({w['terrain'].shape[0]} tris), "
                                "per-step pose rebuild + noise/dropout/latency",
                    "rays_per_step": rays, "wall_s": round(wall, 3),
-                   "render_ms_median": round(statistics.median(render_ms), 3)},
+                   "render_ms_median": round(statistics.median(render_ms), 3),
+                   "exact_pass_rays_last_step": exact_rays},
         "roofline": roof, "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

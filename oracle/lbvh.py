@@ -40,12 +40,13 @@ def prim_boxes(tri):
 
 
 def morton_keys(lo, hi):
+    """Box centres quantised to 21 bits with one scale for all axes
+    (2^21 / largest centroid extent), then bit-interleaved."""
     c = (lo + hi) * np.float32(0.5)
     cmin, cmax = c.min(axis=0), c.max(axis=0)
-    ext = cmax - cmin
-    with np.errstate(divide="ignore"):
-        s = np.where(ext > 0, np.float32(2097152.0) / np.where(ext > 0, ext, np.float32(1)), np.float32(0))
-    f = (c - cmin) * s.astype(np.float32)
+    ext = np.float32((cmax - cmin).max())
+    s = np.float32(2097152.0) / ext if ext > 0 else np.float32(0)
+    f = (c - cmin) * np.float32(s)
     f = np.minimum(np.maximum(f, np.float32(0)), np.float32(2097151.0))
     q = f.astype(np.uint32)
     return (_spread3(q[:, 0]) << np.uint64(2)) | (_spread3(q[:, 1]) << np.uint64(1)) | _spread3(q[:, 2])

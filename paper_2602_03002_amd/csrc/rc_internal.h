@@ -89,7 +89,7 @@ struct RenderLaunch {
     int32_t* inst;
     int32_t* tri;
     uint32_t* exact_count;  // rays the fast pass hands to the exact pass
-    uint32_t* exact_list;
+    uint2* exact_list;      // (pixel index, bits of the fast pass's bound)
     int64_t exact_cap;
     int n_env, n_cam, width, height, n_links, depth_mode, n_terrain;
     float far_plane;

@@ -1,0 +1,86 @@
+"""Pins for the CPU LBVH model: brute-force bit interleaving, the defining
+properties of the Karras hierarchy, and box containment."""
+import numpy as np
+
+from oracle import lbvh
+import scenegen as sg
+
+
+def test_morton_matches_bit_by_bit_interleave():
+    rng = np.random.default_rng(0)
+    q = rng.integers(0, 2 ** 21, size=(200, 3)).astype(np.uint32)
+    fast = (lbvh._spread3(q[:, 0]) << np.uint64(2)) | (lbvh._spread3(q[:, 1]) << np.uint64(1)) | \
+        lbvh._spread3(q[:, 2])
+    for i in range(200):
+        assert int(fast[i]) == lbvh.interleave_bits(q[i])
+
+
+def test_morton_quantisation_is_isotropic_and_clamped():
+    # centroids on a line along x from 0 to 8 and a tiny z range: x uses all 21
+    # bits, z uses few (one scale for all axes)
+    lo = np.zeros((3, 3), np.float32)
+    lo[:, 0] = [0.0, 4.0, 8.0]
+    lo[:, 2] = [0.0, 0.001, 0.002]
+    keys = lbvh.morton_keys(lo, lo)
+    qx = [sum(((int(k) >> (3 * b + 2)) & 1) << b for b in range(21)) for k in keys]
+    qz = [sum(((int(k) >> (3 * b)) & 1) << b for b in range(21)) for k in keys]
+    assert qx == [0, 2 ** 20, 2 ** 21 - 1]
+    assert qz[2] == int(np.float32(0.002) * np.float32(2 ** 21 / 8.0))
+
+
+def _leaf_ranges(c0, c1, n):
+    """Leaves under every internal node, by explicit descent."""
+    out = {}
+
+    def leaves(ref):
+        if ref < 0:
+            return [~ref]
+        if ref not in out:
+            out[ref] = leaves(c0[ref]) + leaves(c1[ref])
+        return out[ref]
+    leaves(0)
+    return out
+
+
+def test_karras_hierarchy_properties():
+    rng = np.random.default_rng(1)
+    for n in (2, 3, 17, 64, 257):
+        keys = np.sort(rng.integers(0, 2 ** 12, size=n).astype(np.uint64))  # many duplicates
+        c0, c1, parent, sibling = lbvh.karras(keys)
+        rng_of = _leaf_ranges(c0, c1, n)
+        assert sorted(rng_of[0]) == list(range(n)), "every leaf reached exactly once"
+        assert len(rng_of) == n - 1, "every internal node reachable from the root"
+        for i, lv in rng_of.items():
+            assert lv == list(range(lv[0], lv[-1] + 1)), "internal nodes cover contiguous ranges"
+            left = rng_of[c0[i]] if c0[i] >= 0 else [~c0[i]]
+            # split at the highest differing bit of (key, index) between the halves
+            a, b = left[-1], left[-1] + 1
+
+            def kd(u, v):
+                if keys[u] != keys[v]:
+                    return 64 - int(int(keys[u]) ^ int(keys[v])).bit_length()
+                return 64 + 32 - int(u ^ v).bit_length()
+            inside = min(kd(lv[0], lv[-1]), 1000)
+            assert kd(a, b) == inside, "split at the node's common-prefix boundary"
+            for c in (c0[i], c1[i]):
+                if c >= 0:
+                    assert parent[c] == i
+                    assert sibling[c] == (c1[i] if c == c0[i] else c0[i])
+
+
+def test_boxes_contain_children_and_leaves():
+    tri = sg.TileTerrain(1).triangles()[:3000]
+    m = lbvh.build(tri)
+    rec = m["records"]
+    ints = rec.view(np.int32)
+    t = tri.reshape(-1, 9)[m["tri_id"]].reshape(-1, 3, 3)
+    for i in range(rec.shape[0]):
+        for h in (0, 1):
+            lo, hi = rec[i, 6 * h:6 * h + 6:2], rec[i, 6 * h + 1:6 * h + 6:2]
+            c = ints[i, 12 + h]
+            if c < 0:
+                assert np.all(t[~c].min(0) > lo) and np.all(t[~c].max(0) < hi)
+            else:
+                clo = np.minimum(rec[c, 0:6:2], rec[c, 6:12:2])
+                chi = np.maximum(rec[c, 1:6:2], rec[c, 7:12:2])
+                assert np.all(clo >= lo) and np.all(chi <= hi), "parents contain their children"
