@@ -147,6 +147,104 @@ rc_status rc_render_exact_count(const rc_scene* scene, int32_t n_env, int32_t n_
                                 rc_stream stream);
 
 /* ---------------------------------------------------------------------
+ * Batched uneven form: environments with different camera counts and image
+ * sizes in one persistent launch (Algorithm 1 over a camera table; the
+ * paper batches per-environment intrinsics K_e^-1, Sec. 3.2.2).
+ * ------------------------------------------------------------------- */
+
+/* One camera of a batch (64 bytes, device memory). */
+typedef struct {
+    int32_t env;         /* environment: row of link_pos / link_quat */
+    int32_t width;       /* image size in pixels, 1..65535 */
+    int32_t height;
+    uint32_t out_offset; /* first pixel of this image in the packed outputs */
+    uint32_t cam_uid;    /* camera id for the sensor model's counters */
+    float pos[3];        /* camera centre (world, m) */
+    float quat[4];       /* optical -> world, (x, y, z, w) */
+    float intr[4];       /* fx, fy, cx, cy */
+} rc_cam_desc;
+
+typedef struct {
+    int32_t n_env, n_desc;
+    const float* link_pos;     /* device [n_env][n_links][3] */
+    const float* link_quat;    /* device [n_env][n_links][4] */
+    const rc_cam_desc* desc;   /* device [n_desc]; images packed row-major at out_offset */
+    int64_t n_pixels;          /* pixels of the packed outputs */
+    int32_t max_width;         /* no descriptor's image is wider (1..65535) */
+    int32_t max_height;        /* ... or taller (1..65535) */
+    float far_plane;
+    int32_t depth_mode;
+    float* depth;              /* device out [n_pixels] */
+    int32_t* inst;             /* device out [n_pixels] or NULL */
+    int32_t* tri;              /* device out [n_pixels] or NULL */
+} rc_batch_args;
+
+/* Workspace bytes of rc_render_batched. */
+rc_status rc_render_batched_size(const rc_scene* scene, int32_t n_env, int32_t n_desc,
+                                 int64_t n_pixels, size_t* ws_bytes);
+
+/* Render every described camera in one launch: per-environment top levels
+ * are rebuilt, a device prefix sum turns the cameras into a tile table, and
+ * either persistent wavefronts pull chunks of tiles from a work counter or a
+ * flat camera-major grid gives each tile a wavefront (the schedule says
+ * which; rc_autotune picks).  Results equal rc_render's for the same camera
+ * bit for bit.  Descriptors are read on the device: one that is out of range
+ * (env, size beyond max_width x max_height, or an image that does not fit in
+ * n_pixels) renders nothing and sets bit 0 of the status word that
+ * rc_render_batched_status reports.  Nothing here allocates or synchronises,
+ * so the call can be captured into a graph (rc_graph_capture_batched). */
+rc_status rc_render_batched(const rc_scene* scene, const rc_batch_args* args, void* ws,
+                            size_t ws_bytes, rc_stream stream);
+
+/* Status word of the last batched render on `ws` (0 = all descriptors
+ * valid) and the number of rays it re-cast exactly; synchronises `stream`. */
+rc_status rc_render_batched_status(const rc_scene* scene, const rc_batch_args* args,
+                                   const void* ws, uint32_t* status, int64_t* exact_rays,
+                                   rc_stream stream);
+
+/* ---------------------------------------------------------------------
+ * Launch schedule and autotuning.
+ * ------------------------------------------------------------------- */
+
+typedef struct {
+    int32_t tile_w, tile_h;  /* pixels per wavefront tile, tile_w * tile_h = 64 */
+    int32_t rays_per_lane;   /* tiles per wavefront, stacked vertically: 1 or 2 */
+    int32_t waves;           /* resident wavefronts per SIMD asked for: 6, 7 or 8 */
+    int32_t persistent;      /* batched form only: 1 persistent work queue, 0 flat grid */
+} rc_render_config;
+
+/* Schedule used by rc_render (batched = 0) or rc_render_batched (batched = 1). */
+rc_status rc_get_render_config(const rc_scene* scene, int32_t batched, rc_render_config* cfg);
+rc_status rc_set_render_config(rc_scene* scene, int32_t batched, const rc_render_config* cfg);
+
+/* Time every candidate schedule (tile 8x8, 16x4, 4x16, 32x2; 1 or 2 tiles
+ * per wavefront; 6, 7 or 8 wavefronts per SIMD; for the batched form also
+ * persistent or flat) on this exact launch -
+ * exactly one of `plain` and `batched` non-NULL - with `reps` timed runs
+ * each after one warm-up, keep the fastest for that mode in the scene and
+ * return it with its mean time.  Overwrites the launch's outputs.
+ * Synchronises `stream`. */
+rc_status rc_autotune(rc_scene* scene, const rc_render_args* plain, const rc_batch_args* batched,
+                      void* ws, size_t ws_bytes, int32_t reps, rc_stream stream,
+                      rc_render_config* best, float* best_ms);
+
+/* ---------------------------------------------------------------------
+ * Graph capture of the batched launch.
+ * ------------------------------------------------------------------- */
+
+typedef struct rc_graph rc_graph;
+
+/* Capture one rc_render_batched call (its top-level build, tile table,
+ * persistent render and exact pass) into an executable HIP graph.  Replays
+ * read the same device buffers, so the caller updates poses and descriptors
+ * in place between replays.  `stream` must not be capturing already. */
+rc_status rc_graph_capture_batched(const rc_scene* scene, const rc_batch_args* args, void* ws,
+                                   size_t ws_bytes, rc_stream stream, rc_graph** out);
+/* Enqueue one replay on `stream`. */
+rc_status rc_graph_launch(rc_graph* graph, rc_stream stream);
+rc_status rc_graph_destroy(rc_graph* graph);
+
+/* ---------------------------------------------------------------------
  * Sensor model: latency, noise, dropout (Sec. 1, Sec. 4.1, Table 6).
  * ------------------------------------------------------------------- */
 
@@ -204,6 +302,18 @@ rc_status rc_postprocess(rc_post* post, const float* depth_in, const int32_t* in
                          const rc_post_params* params, uint64_t step, const uint32_t* cam_uid,
                          float* depth_out, uint8_t* drop_out, uint8_t* lat_out,
                          rc_stream stream);
+
+/* Sensor-model state over packed outputs of n_pixels (the batched form). */
+rc_status rc_post_size_packed(int64_t n_pixels, int32_t max_latency, size_t* ws_bytes);
+rc_status rc_post_create_packed(int64_t n_pixels, int32_t max_latency, void* ws, size_t ws_bytes,
+                                rc_post** out);
+
+/* rc_postprocess over a batch: pixel p of camera d is packed at
+ * desc[d].out_offset + p and uses desc[d].cam_uid; lat_out is [n_desc]. */
+rc_status rc_postprocess_batched(rc_post* post, const float* depth_in, const int32_t* inst_in,
+                                 const rc_post_params* params, uint64_t step,
+                                 const rc_cam_desc* desc, int32_t n_desc, float* depth_out,
+                                 uint8_t* drop_out, uint8_t* lat_out, rc_stream stream);
 
 /* Release the handle (not the workspace). NULL is a no-op. */
 rc_status rc_post_destroy(rc_post* post);

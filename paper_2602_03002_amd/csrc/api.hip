@@ -18,10 +18,18 @@ struct rc_scene {
     size_t meta_off = 0;
     std::vector<rc::BvhLayout> links;
     std::vector<int32_t> link_depth;
+    rc::RenderCfg cfg;          // fast-pass schedule of rc_render (set by rc_autotune)
+    rc::RenderCfg cfg_batched;  // ... of rc_render_batched
+};
+
+struct rc_graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
 };
 
 struct rc_post {
     int32_t n_env, n_cam, height, width, max_latency;
+    bool packed;
     int64_t n_pix;
     float* ring;
     bool started;
@@ -236,12 +244,14 @@ rc_status rc_robot_meshes(rc_scene* scene, const float* link_tri, const int64_t*
 }
 
 // Render workspace: top-level records and instance transforms (with links),
-// then the exact pass's counter and its list (one slot per ray).
+// the exact pass's counter and bounded list, and for the batched form the
+// tile table, the eight per-XCD queue counters (64 bytes apart) and a status word.
 struct RenderWs {
-    size_t xf, count, list, end;
+    size_t xf, count, list, tiles, queues, status, end;
+    int64_t cap;
 };
 
-static RenderWs render_layout(int64_t n_env, int64_t n_rays, int32_t n_links) {
+static RenderWs render_layout(int64_t n_env, int64_t n_pixels, int32_t n_links, int64_t n_desc) {
     RenderWs L;
     size_t o = 0;
     if (n_links > 0) {
@@ -254,8 +264,17 @@ static RenderWs render_layout(int64_t n_env, int64_t n_rays, int32_t n_links) {
     }
     L.count = o;
     o = align_up(o + 4);
+    // a bounded list (a pixel in 16 typically suffices by far); on overflow the
+    // exact pass re-casts every pixel
+    L.cap = n_pixels / 16 > 4096 ? n_pixels / 16 : 4096;
     L.list = o;
-    o = align_up(o + (size_t)n_rays * 8);
+    o = align_up(o + (size_t)L.cap * 16);
+    L.tiles = o;
+    o = align_up(o + (size_t)(n_desc > 0 ? n_desc + 1 : 1) * 4);
+    L.queues = o;
+    o = align_up(o + 8 * 64);
+    L.status = o;
+    o = align_up(o + 4);
     L.end = o;
     return L;
 }
@@ -273,33 +292,11 @@ rc_status rc_render_size(const rc_scene* scene, int32_t n_env, int32_t n_cam, in
     if (!render_dims_ok(n_env, n_cam, width, height))
         return fail(RC_ERR_INVALID_ARG, "rc_render_size: sizes must be >= 1, width and height "
                                         "<= 65535, at most 2^32 - 1 rays");
-    *ws_bytes = render_layout(n_env, (int64_t)n_env * n_cam * width * height, scene->n_links).end;
+    *ws_bytes = render_layout(n_env, (int64_t)n_env * n_cam * width * height, scene->n_links, 0).end;
     return RC_OK;
 }
 
-rc_status rc_render(const rc_scene* scene, const rc_render_args* a, void* ws, size_t ws_bytes,
-                    rc_stream stream) {
-    if (!scene || !a) return fail(RC_ERR_INVALID_ARG, "rc_render: NULL scene or args");
-    if (!scene->ws) return fail(RC_ERR_STATE, "rc_render: scene has no terrain");
-    if (!render_dims_ok(a->n_env, a->n_cam, a->width, a->height))
-        return fail(RC_ERR_INVALID_ARG, "rc_render: sizes must be >= 1, width and height <= 65535, "
-                                        "at most 2^32 - 1 rays");
-    if (!a->cam_pos || !a->cam_quat || !a->intr || !a->depth)
-        return fail(RC_ERR_INVALID_ARG, "rc_render: cam_pos, cam_quat, intr and depth are required");
-    if (scene->n_links > 0 && (!a->link_pos || !a->link_quat))
-        return fail(RC_ERR_INVALID_ARG, "rc_render: link_pos and link_quat are required with links");
-    if (!(a->far_plane > 0.0f) || !std::isfinite(a->far_plane))
-        return fail(RC_ERR_INVALID_ARG, "rc_render: far_plane must be finite and > 0");
-    if (a->depth_mode != RC_DEPTH_PLANAR && a->depth_mode != RC_DEPTH_RANGE)
-        return fail(RC_ERR_INVALID_ARG, "rc_render: unknown depth_mode");
-    const int64_t n_rays = (int64_t)a->n_env * a->n_cam * a->width * a->height;
-    const RenderWs W = render_layout(a->n_env, n_rays, scene->n_links);
-    if (!ws || ws_bytes < W.end || !aligned(ws))
-        return fail(RC_ERR_WORKSPACE, "rc_render: workspace needs " + std::to_string(W.end) +
-                                          " bytes, 256-byte aligned");
-    const size_t xf_off = W.xf;
-    hipStream_t s = (hipStream_t)stream;
-    RenderLaunch L;
+static void fill_scene(const rc_scene* scene, RenderLaunch& L) {
     L.terrain_nodes = (const Node*)(scene->ws + scene->terrain.nodes);
     L.terrain_tris = (const float*)(scene->ws + scene->terrain.tris);
     L.terrain_tri_id = (const int32_t*)(scene->ws + scene->terrain.tri_id);
@@ -307,8 +304,34 @@ rc_status rc_render(const rc_scene* scene, const rc_render_args* a, void* ws, si
     L.link_tris = (const float*)scene->robot_ws;
     L.link_tri_id = (const int32_t*)scene->robot_ws;
     L.link_meta = scene->robot_ws ? (const LinkMeta*)(scene->robot_ws + scene->meta_off) : nullptr;
+    L.n_links = scene->n_links;
+    L.n_terrain = (int)scene->terrain.n_prim;
+}
+
+static rc_status prep_plain(const rc_scene* scene, const rc_render_args* a, void* ws,
+                            size_t ws_bytes, RenderLaunch& L, const char* who) {
+    const std::string w(who);
+    if (!scene || !a) return fail(RC_ERR_INVALID_ARG, w + ": NULL scene or args");
+    if (!scene->ws) return fail(RC_ERR_STATE, w + ": scene has no terrain");
+    if (!render_dims_ok(a->n_env, a->n_cam, a->width, a->height))
+        return fail(RC_ERR_INVALID_ARG, w + ": sizes must be >= 1, width and height <= 65535, "
+                                            "at most 2^32 - 1 rays");
+    if (!a->cam_pos || !a->cam_quat || !a->intr || !a->depth)
+        return fail(RC_ERR_INVALID_ARG, w + ": cam_pos, cam_quat, intr and depth are required");
+    if (scene->n_links > 0 && (!a->link_pos || !a->link_quat))
+        return fail(RC_ERR_INVALID_ARG, w + ": link_pos and link_quat are required with links");
+    if (!(a->far_plane > 0.0f) || !std::isfinite(a->far_plane))
+        return fail(RC_ERR_INVALID_ARG, w + ": far_plane must be finite and > 0");
+    if (a->depth_mode != RC_DEPTH_PLANAR && a->depth_mode != RC_DEPTH_RANGE)
+        return fail(RC_ERR_INVALID_ARG, w + ": unknown depth_mode");
+    const int64_t n_rays = (int64_t)a->n_env * a->n_cam * a->width * a->height;
+    const RenderWs W = render_layout(a->n_env, n_rays, scene->n_links, 0);
+    if (!ws || ws_bytes < W.end || !aligned(ws))
+        return fail(RC_ERR_WORKSPACE, w + ": workspace needs " + std::to_string(W.end) +
+                                          " bytes, 256-byte aligned");
+    fill_scene(scene, L);
     L.tlas = scene->n_links > 0 ? (const Node*)ws : nullptr;
-    L.xf = scene->n_links > 0 ? (const InstXform*)((char*)ws + xf_off) : nullptr;
+    L.xf = scene->n_links > 0 ? (const InstXform*)((char*)ws + W.xf) : nullptr;
     L.link_pos = a->link_pos;
     L.link_quat = a->link_quat;
     L.cam_pos = a->cam_pos;
@@ -321,19 +344,282 @@ rc_status rc_render(const rc_scene* scene, const rc_render_args* a, void* ws, si
     L.n_cam = a->n_cam;
     L.width = a->width;
     L.height = a->height;
-    L.n_links = scene->n_links;
     L.depth_mode = a->depth_mode;
-    L.n_terrain = (int)scene->terrain.n_prim;
-    L.exact_count = (uint32_t*)((char*)ws + W.count);
-    L.exact_list = (uint2*)((char*)ws + W.list);
-    L.exact_cap = n_rays;
     L.far_plane = a->far_plane;
+    L.exact_count = (uint32_t*)((char*)ws + W.count);
+    L.exact_list = (uint4*)((char*)ws + W.list);
+    L.exact_cap = W.cap;
+    L.desc = nullptr;
+    L.n_desc = 0;
+    L.max_width = a->width;
+    L.max_height = a->height;
+    L.n_pixels = n_rays;
+    return RC_OK;
+}
+
+static hipError_t run_plain(const rc_scene* scene, const RenderLaunch& L, void* ws,
+                            const RenderCfg& cfg, hipStream_t s) {
     hipError_t e = hipSuccess;
     if (scene->n_links > 0)
-        e = launch_tlas_build(a->link_pos, a->link_quat, a->n_env, scene->n_links, L.link_meta,
-                              (Node*)ws, (InstXform*)((char*)ws + xf_off), s);
-    if (e == hipSuccess) e = launch_render(L, s);
+        e = launch_tlas_build(L.link_pos, L.link_quat, L.n_env, scene->n_links, L.link_meta,
+                              (Node*)ws, (InstXform*)L.xf, s);
+    if (e == hipSuccess) e = launch_render(L, cfg, s);
+    return e;
+}
+
+rc_status rc_render(const rc_scene* scene, const rc_render_args* a, void* ws, size_t ws_bytes,
+                    rc_stream stream) {
+    RenderLaunch L;
+    rc_status st = prep_plain(scene, a, ws, ws_bytes, L, "rc_render");
+    if (st != RC_OK) return st;
+    hipError_t e = run_plain(scene, L, ws, scene->cfg, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "rc_render: launch");
+    return RC_OK;
+}
+
+// ---- batched form ----
+
+static bool batch_dims_ok(int32_t n_env, int32_t n_desc, int64_t n_pixels) {
+    return n_env >= 1 && n_desc >= 1 && n_desc <= (1 << 24) && n_pixels >= 1 &&
+           n_pixels <= (int64_t)0xFFFFFFFF;
+}
+
+rc_status rc_render_batched_size(const rc_scene* scene, int32_t n_env, int32_t n_desc,
+                                 int64_t n_pixels, size_t* ws_bytes) {
+    if (!scene || !ws_bytes) return fail(RC_ERR_INVALID_ARG, "rc_render_batched_size: NULL pointer");
+    if (!batch_dims_ok(n_env, n_desc, n_pixels))
+        return fail(RC_ERR_INVALID_ARG, "rc_render_batched_size: need n_env >= 1, 1 <= n_desc <= "
+                                        "2^24, 1 <= n_pixels <= 2^32 - 1");
+    *ws_bytes = render_layout(n_env, n_pixels, scene->n_links, n_desc).end;
+    return RC_OK;
+}
+
+static int persistent_blocks(const RenderCfg& cfg) {
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0, n = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0)
+            cus = n;
+        else
+            cus = 256;
+    }
+    // one block = 4 wavefronts, `waves` resident wavefronts per SIMD, 4 SIMDs per CU
+    int b = cus * cfg.waves;
+    return (b + 7) / 8 * 8;
+}
+
+static rc_status prep_batched(const rc_scene* scene, const rc_batch_args* a, void* ws,
+                              size_t ws_bytes, RenderLaunch& L, RenderWs& W, const char* who) {
+    const std::string w(who);
+    if (!scene || !a) return fail(RC_ERR_INVALID_ARG, w + ": NULL scene or args");
+    if (!scene->ws) return fail(RC_ERR_STATE, w + ": scene has no terrain");
+    if (!batch_dims_ok(a->n_env, a->n_desc, a->n_pixels))
+        return fail(RC_ERR_INVALID_ARG, w + ": need n_env >= 1, 1 <= n_desc <= 2^24, "
+                                            "1 <= n_pixels <= 2^32 - 1");
+    if (!a->desc || !a->depth) return fail(RC_ERR_INVALID_ARG, w + ": desc and depth are required");
+    if (a->max_width < 1 || a->max_width > 65535 || a->max_height < 1 || a->max_height > 65535)
+        return fail(RC_ERR_INVALID_ARG, w + ": max_width and max_height must be in [1, 65535]");
+    if (scene->n_links > 0 && (!a->link_pos || !a->link_quat))
+        return fail(RC_ERR_INVALID_ARG, w + ": link_pos and link_quat are required with links");
+    if (!(a->far_plane > 0.0f) || !std::isfinite(a->far_plane))
+        return fail(RC_ERR_INVALID_ARG, w + ": far_plane must be finite and > 0");
+    if (a->depth_mode != RC_DEPTH_PLANAR && a->depth_mode != RC_DEPTH_RANGE)
+        return fail(RC_ERR_INVALID_ARG, w + ": unknown depth_mode");
+    W = render_layout(a->n_env, a->n_pixels, scene->n_links, a->n_desc);
+    if (!ws || ws_bytes < W.end || !aligned(ws))
+        return fail(RC_ERR_WORKSPACE, w + ": workspace needs " + std::to_string(W.end) +
+                                          " bytes, 256-byte aligned");
+    fill_scene(scene, L);
+    L.tlas = scene->n_links > 0 ? (const Node*)ws : nullptr;
+    L.xf = scene->n_links > 0 ? (const InstXform*)((char*)ws + W.xf) : nullptr;
+    L.link_pos = a->link_pos;
+    L.link_quat = a->link_quat;
+    L.cam_pos = L.cam_quat = L.intr = nullptr;
+    L.depth = a->depth;
+    L.inst = a->inst;
+    L.tri = a->tri;
+    L.n_env = a->n_env;
+    L.n_cam = 1;
+    L.width = L.height = 1;
+    L.depth_mode = a->depth_mode;
+    L.far_plane = a->far_plane;
+    L.exact_count = (uint32_t*)((char*)ws + W.count);
+    L.exact_list = (uint4*)((char*)ws + W.list);
+    L.exact_cap = W.cap;
+    L.desc = a->desc;
+    L.n_desc = a->n_desc;
+    L.max_width = a->max_width;
+    L.max_height = a->max_height;
+    L.n_pixels = a->n_pixels;
+    return RC_OK;
+}
+
+static hipError_t run_batched(const rc_scene* scene, const RenderLaunch& L, void* ws,
+                              const RenderWs& W, const RenderCfg& cfg, hipStream_t s) {
+    hipError_t e = hipSuccess;
+    if (scene->n_links > 0)
+        e = launch_tlas_build(L.link_pos, L.link_quat, L.n_env, scene->n_links, L.link_meta,
+                              (Node*)ws, (InstXform*)L.xf, s);
+    if (e == hipSuccess)
+        e = launch_render_batched(L, cfg, (uint32_t*)((char*)ws + W.tiles),
+                                  (uint32_t*)((char*)ws + W.queues), (uint32_t*)((char*)ws + W.status),
+                                  persistent_blocks(cfg), s);
+    return e;
+}
+
+rc_status rc_render_batched(const rc_scene* scene, const rc_batch_args* a, void* ws,
+                            size_t ws_bytes, rc_stream stream) {
+    RenderLaunch L;
+    RenderWs W;
+    rc_status st = prep_batched(scene, a, ws, ws_bytes, L, W, "rc_render_batched");
+    if (st != RC_OK) return st;
+    hipError_t e = run_batched(scene, L, ws, W, scene->cfg_batched, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "rc_render_batched: launch");
+    return RC_OK;
+}
+
+rc_status rc_render_batched_status(const rc_scene* scene, const rc_batch_args* a, const void* ws,
+                                   uint32_t* status, int64_t* exact_rays, rc_stream stream) {
+    if (!scene || !a || !ws || !status) return fail(RC_ERR_INVALID_ARG, "rc_render_batched_status: NULL");
+    if (!batch_dims_ok(a->n_env, a->n_desc, a->n_pixels))
+        return fail(RC_ERR_INVALID_ARG, "rc_render_batched_status: bad sizes");
+    const RenderWs W = render_layout(a->n_env, a->n_pixels, scene->n_links, a->n_desc);
+    uint32_t v[2] = {0, 0};
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipMemcpyAsync(&v[0], (const char*)ws + W.status, 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(&v[1], (const char*)ws + W.count, 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "rc_render_batched_status");
+    *status = v[0];
+    if (exact_rays) *exact_rays = v[1];
+    return RC_OK;
+}
+
+// ---- schedules and autotuning ----
+
+static RenderCfg to_cfg(const rc_render_config& c) {
+    RenderCfg r;
+    r.tile_w = c.tile_w; r.tile_h = c.tile_h; r.rays_per_lane = c.rays_per_lane; r.waves = c.waves;
+    r.persistent = c.persistent ? 1 : 0;
+    return r;
+}
+
+static rc_render_config from_cfg(const RenderCfg& c) {
+    rc_render_config r;
+    r.tile_w = c.tile_w; r.tile_h = c.tile_h; r.rays_per_lane = c.rays_per_lane; r.waves = c.waves;
+    r.persistent = c.persistent;
+    return r;
+}
+
+rc_status rc_get_render_config(const rc_scene* scene, int32_t batched, rc_render_config* cfg) {
+    if (!scene || !cfg) return fail(RC_ERR_INVALID_ARG, "rc_get_render_config: NULL pointer");
+    *cfg = from_cfg(batched ? scene->cfg_batched : scene->cfg);
+    return RC_OK;
+}
+
+rc_status rc_set_render_config(rc_scene* scene, int32_t batched, const rc_render_config* cfg) {
+    if (!scene || !cfg) return fail(RC_ERR_INVALID_ARG, "rc_set_render_config: NULL pointer");
+    RenderCfg c = to_cfg(*cfg);
+    if (!render_cfg_ok(c))
+        return fail(RC_ERR_INVALID_ARG, "rc_set_render_config: need tile_w * tile_h = 64, "
+                                        "rays_per_lane in {1, 2}, waves in {6, 7, 8}");
+    (batched ? scene->cfg_batched : scene->cfg) = c;
+    return RC_OK;
+}
+
+rc_status rc_autotune(rc_scene* scene, const rc_render_args* plain, const rc_batch_args* batched,
+                      void* ws, size_t ws_bytes, int32_t reps, rc_stream stream,
+                      rc_render_config* best, float* best_ms) {
+    if (!scene || (!plain) == (!batched))
+        return fail(RC_ERR_INVALID_ARG, "rc_autotune: give exactly one of plain and batched");
+    if (reps < 1 || reps > 1000) return fail(RC_ERR_INVALID_ARG, "rc_autotune: reps in [1, 1000]");
+    RenderLaunch L;
+    RenderWs W;
+    rc_status st = plain ? prep_plain(scene, plain, ws, ws_bytes, L, "rc_autotune")
+                         : prep_batched(scene, batched, ws, ws_bytes, L, W, "rc_autotune");
+    if (st != RC_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return fail(RC_ERR_DEVICE, "rc_autotune: hipEventCreate");
+    const int tiles[4][2] = {{8, 8}, {16, 4}, {4, 16}, {32, 2}};
+    RenderCfg win;
+    float win_ms = INFINITY;
+    hipError_t e = hipSuccess;
+    const int n_modes = plain ? 1 : 2;
+    for (int pm = 0; pm < n_modes && e == hipSuccess; ++pm)
+    for (int t = 0; t < 4 && e == hipSuccess; ++t)
+        for (int rpl = 1; rpl <= 2 && e == hipSuccess; ++rpl)
+            for (int wv = 6; wv <= 8 && e == hipSuccess; ++wv) {
+                RenderCfg c;
+                c.tile_w = tiles[t][0]; c.tile_h = tiles[t][1]; c.rays_per_lane = rpl; c.waves = wv;
+                c.persistent = pm;
+                for (int r = 0; r <= reps && e == hipSuccess; ++r) {
+                    if (r == 1) e = hipEventRecord(e0, s);
+                    if (e == hipSuccess)
+                        e = plain ? run_plain(scene, L, ws, c, s) : run_batched(scene, L, ws, W, c, s);
+                }
+                if (e == hipSuccess) e = hipEventRecord(e1, s);
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
+                float ms = 0.0f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                ms /= (float)reps;
+                if (e == hipSuccess && ms < win_ms) { win_ms = ms; win = c; }
+            }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (e != hipSuccess) return hip_fail(e, "rc_autotune");
+    (plain ? scene->cfg : scene->cfg_batched) = win;
+    if (best) *best = from_cfg(win);
+    if (best_ms) *best_ms = win_ms;
+    return RC_OK;
+}
+
+// ---- graphs ----
+
+rc_status rc_graph_capture_batched(const rc_scene* scene, const rc_batch_args* a, void* ws,
+                                   size_t ws_bytes, rc_stream stream, rc_graph** out) {
+    if (!out) return fail(RC_ERR_INVALID_ARG, "rc_graph_capture_batched: out is NULL");
+    RenderLaunch L;
+    RenderWs W;
+    rc_status st = prep_batched(scene, a, ws, ws_bytes, L, W, "rc_graph_capture_batched");
+    if (st != RC_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    hipStreamCaptureStatus cs;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
+        return fail(RC_ERR_STATE, "rc_graph_capture_batched: stream is already capturing");
+    rc_graph* g = new (std::nothrow) rc_graph();
+    if (!g) return fail(RC_ERR_DEVICE, "rc_graph_capture_batched: out of host memory");
+    persistent_blocks(scene->cfg_batched);  // device query outside the capture
+    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        hipError_t er = run_batched(scene, L, ws, W, scene->cfg_batched, s);
+        e = hipStreamEndCapture(s, &g->graph);
+        if (er != hipSuccess) e = er;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        if (g->graph) hipGraphDestroy(g->graph);
+        delete g;
+        return hip_fail(e, "rc_graph_capture_batched");
+    }
+    *out = g;
+    return RC_OK;
+}
+
+rc_status rc_graph_launch(rc_graph* graph, rc_stream stream) {
+    if (!graph || !graph->exec) return fail(RC_ERR_INVALID_ARG, "rc_graph_launch: NULL graph");
+    hipError_t e = hipGraphLaunch(graph->exec, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "rc_graph_launch");
+    return RC_OK;
+}
+
+rc_status rc_graph_destroy(rc_graph* graph) {
+    if (!graph) return RC_OK;
+    if (graph->exec) hipGraphExecDestroy(graph->exec);
+    if (graph->graph) hipGraphDestroy(graph->graph);
+    delete graph;
     return RC_OK;
 }
 
@@ -343,7 +629,7 @@ rc_status rc_render_exact_count(const rc_scene* scene, int32_t n_env, int32_t n_
     if (!scene || !ws || !count) return fail(RC_ERR_INVALID_ARG, "rc_render_exact_count: NULL pointer");
     if (!render_dims_ok(n_env, n_cam, width, height))
         return fail(RC_ERR_INVALID_ARG, "rc_render_exact_count: bad sizes");
-    const RenderWs W = render_layout(n_env, (int64_t)n_env * n_cam * width * height, scene->n_links);
+    const RenderWs W = render_layout(n_env, (int64_t)n_env * n_cam * width * height, scene->n_links, 0);
     uint32_t c = 0;
     hipError_t e = hipMemcpyAsync(&c, (const char*)ws + W.count, 4, hipMemcpyDeviceToHost,
                                   (hipStream_t)stream);
@@ -387,6 +673,7 @@ rc_status rc_post_create(int32_t n_env, int32_t n_cam, int32_t height, int32_t w
     rc_post* p = new (std::nothrow) rc_post();
     if (!p) return fail(RC_ERR_DEVICE, "rc_post_create: out of host memory");
     p->n_env = n_env; p->n_cam = n_cam; p->height = height; p->width = width;
+    p->packed = false;
     p->max_latency = max_latency;
     p->n_pix = (int64_t)n_env * n_cam * height * width;
     p->ring = (float*)ws;
@@ -402,37 +689,32 @@ rc_status rc_post_reset(rc_post* post) {
     return RC_OK;
 }
 
-rc_status rc_postprocess(rc_post* post, const float* depth_in, const int32_t* inst_in,
-                         const rc_post_params* pp, uint64_t step, const uint32_t* cam_uid,
-                         float* depth_out, uint8_t* drop_out, uint8_t* lat_out, rc_stream stream) {
+static rc_status post_common(rc_post* post, const float* depth_in, const rc_post_params* pp,
+                             uint64_t step, float* depth_out, PostLaunch& L, const char* who) {
+    const std::string w(who);
     if (!post || !pp || !depth_in || !depth_out)
-        return fail(RC_ERR_INVALID_ARG, "rc_postprocess: NULL required pointer");
-    if (step >= (1ull << 48)) return fail(RC_ERR_INVALID_ARG, "rc_postprocess: step >= 2^48");
+        return fail(RC_ERR_INVALID_ARG, w + ": NULL required pointer");
+    if (step >= (1ull << 48)) return fail(RC_ERR_INVALID_ARG, w + ": step >= 2^48");
     if (!(pp->p_drop >= 0.0f && pp->p_drop <= 1.0f))
-        return fail(RC_ERR_INVALID_ARG, "rc_postprocess: p_drop must be in [0, 1]");
+        return fail(RC_ERR_INVALID_ARG, w + ": p_drop must be in [0, 1]");
     if (!(pp->near_plane <= pp->far_plane) || !std::isfinite(pp->near_plane) ||
         !std::isfinite(pp->far_plane))
-        return fail(RC_ERR_INVALID_ARG, "rc_postprocess: need finite near_plane <= far_plane");
+        return fail(RC_ERR_INVALID_ARG, w + ": need finite near_plane <= far_plane");
     if (!std::isfinite(pp->sigma_abs) || !std::isfinite(pp->sigma_rel) || !std::isfinite(pp->fill))
-        return fail(RC_ERR_INVALID_ARG, "rc_postprocess: non-finite noise or fill parameter");
+        return fail(RC_ERR_INVALID_ARG, w + ": non-finite noise or fill parameter");
     if (pp->flags & ~(RC_POST_NOISE | RC_POST_DROPOUT | RC_POST_LATENCY))
-        return fail(RC_ERR_INVALID_ARG, "rc_postprocess: unknown flag");
+        return fail(RC_ERR_INVALID_ARG, w + ": unknown flag");
     if (pp->flags & RC_POST_LATENCY) {
         if (pp->lat_min < 0 || pp->lat_max < pp->lat_min)
-            return fail(RC_ERR_INVALID_ARG, "rc_postprocess: need 0 <= lat_min <= lat_max");
+            return fail(RC_ERR_INVALID_ARG, w + ": need 0 <= lat_min <= lat_max");
         if (pp->lat_max > post->max_latency)
-            return fail(RC_ERR_INVALID_ARG, "rc_postprocess: lat_max exceeds the ring's max_latency");
+            return fail(RC_ERR_INVALID_ARG, w + ": lat_max exceeds the ring's max_latency");
     }
     if (post->started && step != post->last + 1)
-        return fail(RC_ERR_STATE, "rc_postprocess: steps must be consecutive (call rc_post_reset)");
-    PostLaunch L;
+        return fail(RC_ERR_STATE, w + ": steps must be consecutive (call rc_post_reset)");
     L.depth_in = depth_in;
-    L.inst_in = inst_in;
-    L.cam_uid = cam_uid;
     L.ring = post->ring;
     L.depth_out = depth_out;
-    L.drop_out = drop_out;
-    L.lat_out = lat_out;
     L.n_pix = post->n_pix;
     L.n_env = post->n_env; L.n_cam = post->n_cam; L.height = post->height; L.width = post->width;
     L.ring_len = post->max_latency + 1;
@@ -445,10 +727,81 @@ rc_status rc_postprocess(rc_post* post, const float* depth_in, const int32_t* in
     L.near_plane = pp->near_plane; L.far_plane = pp->far_plane; L.fill = pp->fill;
     L.lat_min = pp->lat_min; L.lat_max = pp->lat_max;
     L.flags = pp->flags;
-    hipError_t e = launch_post(L, (hipStream_t)stream);
-    if (e != hipSuccess) return hip_fail(e, "rc_postprocess: launch");
+    return RC_OK;
+}
+
+static void post_advance(rc_post* post, uint64_t step) {
     if (!post->started) { post->started = true; post->s0 = step; }
     post->last = step;
+}
+
+rc_status rc_postprocess(rc_post* post, const float* depth_in, const int32_t* inst_in,
+                         const rc_post_params* pp, uint64_t step, const uint32_t* cam_uid,
+                         float* depth_out, uint8_t* drop_out, uint8_t* lat_out, rc_stream stream) {
+    PostLaunch L;
+    rc_status st = post_common(post, depth_in, pp, step, depth_out, L, "rc_postprocess");
+    if (st != RC_OK) return st;
+    if (post->packed)
+        return fail(RC_ERR_STATE, "rc_postprocess: state was created packed; use rc_postprocess_batched");
+    L.inst_in = inst_in;
+    L.cam_uid = cam_uid;
+    L.drop_out = drop_out;
+    L.lat_out = lat_out;
+    hipError_t e = launch_post(L, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "rc_postprocess: launch");
+    post_advance(post, step);
+    return RC_OK;
+}
+
+rc_status rc_post_size_packed(int64_t n_pixels, int32_t max_latency, size_t* ws_bytes) {
+    if (!ws_bytes) return fail(RC_ERR_INVALID_ARG, "rc_post_size_packed: ws_bytes is NULL");
+    if (n_pixels < 1 || n_pixels > (int64_t)0xFFFFFFFF || max_latency < 0 || max_latency > 255)
+        return fail(RC_ERR_INVALID_ARG, "rc_post_size_packed: need 1 <= n_pixels <= 2^32 - 1, "
+                                        "0 <= max_latency <= 255");
+    *ws_bytes = align_up((size_t)n_pixels * 4 * (size_t)(max_latency + 1));
+    return RC_OK;
+}
+
+rc_status rc_post_create_packed(int64_t n_pixels, int32_t max_latency, void* ws, size_t ws_bytes,
+                                rc_post** out) {
+    if (!out || !ws) return fail(RC_ERR_INVALID_ARG, "rc_post_create_packed: NULL pointer");
+    size_t need;
+    rc_status st = rc_post_size_packed(n_pixels, max_latency, &need);
+    if (st != RC_OK) return st;
+    if (ws_bytes < need || !aligned(ws))
+        return fail(RC_ERR_WORKSPACE, "rc_post_create_packed: workspace needs " + std::to_string(need) +
+                                          " bytes, 256-byte aligned");
+    rc_post* p = new (std::nothrow) rc_post();
+    if (!p) return fail(RC_ERR_DEVICE, "rc_post_create_packed: out of host memory");
+    p->n_env = p->n_cam = p->height = p->width = 0;
+    p->packed = true;
+    p->max_latency = max_latency;
+    p->n_pix = n_pixels;
+    p->ring = (float*)ws;
+    p->started = false;
+    p->s0 = p->last = 0;
+    *out = p;
+    return RC_OK;
+}
+
+rc_status rc_postprocess_batched(rc_post* post, const float* depth_in, const int32_t* inst_in,
+                                 const rc_post_params* pp, uint64_t step, const rc_cam_desc* desc,
+                                 int32_t n_desc, float* depth_out, uint8_t* drop_out,
+                                 uint8_t* lat_out, rc_stream stream) {
+    PostLaunch L;
+    rc_status st = post_common(post, depth_in, pp, step, depth_out, L, "rc_postprocess_batched");
+    if (st != RC_OK) return st;
+    if (!post->packed)
+        return fail(RC_ERR_STATE, "rc_postprocess_batched: state was not created packed");
+    if (!desc || n_desc < 1 || n_desc > (1 << 24))
+        return fail(RC_ERR_INVALID_ARG, "rc_postprocess_batched: need desc and 1 <= n_desc <= 2^24");
+    L.inst_in = inst_in;
+    L.cam_uid = nullptr;
+    L.drop_out = drop_out;
+    L.lat_out = lat_out;
+    hipError_t e = launch_post_batched(L, desc, n_desc, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "rc_postprocess_batched: launch");
+    post_advance(post, step);
     return RC_OK;
 }
 

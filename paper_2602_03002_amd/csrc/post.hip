@@ -30,13 +30,9 @@ __device__ __forceinline__ uint32_t step_hi(uint64_t s) {
     return (uint32_t)(((s >> 32) & 0xFFFFull) << 16);
 }
 
-__global__ void __launch_bounds__(256) k_post(PostLaunch a) {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= a.n_pix) return;
-    const int64_t hw = (int64_t)a.height * a.width;
-    const int64_t ec = p / hw;
-    const uint32_t pix = (uint32_t)(p - ec * hw);
-    const uint32_t uid = a.cam_uid ? a.cam_uid[ec] : (uint32_t)ec;
+// Sensor model of packed pixel p: pixel `pix` of its image, camera `uid`.
+__device__ __forceinline__ void post_pixel(const PostLaunch& a, int64_t p, uint32_t pix, uint32_t uid,
+                                           uint8_t* lat_slot) {
     const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
     const uint64_t s = a.step;
 
@@ -80,7 +76,29 @@ __global__ void __launch_bounds__(256) k_post(PostLaunch a) {
     }
     a.depth_out[p] = out;
     if (a.drop_out) a.drop_out[p] = out_drop ? 1 : 0;
-    if (a.lat_out && pix == 0) a.lat_out[ec] = (uint8_t)k;
+    if (lat_slot && pix == 0) *lat_slot = (uint8_t)k;
+}
+
+// Plain layout [env][cam][height][width]: one thread per pixel.
+__global__ void __launch_bounds__(256) k_post(PostLaunch a) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= a.n_pix) return;
+    const int64_t hw = (int64_t)a.height * a.width;
+    const int64_t ec = p / hw;
+    const uint32_t pix = (uint32_t)(p - ec * hw);
+    const uint32_t uid = a.cam_uid ? a.cam_uid[ec] : (uint32_t)ec;
+    post_pixel(a, p, pix, uid, a.lat_out ? a.lat_out + ec : nullptr);
+}
+
+// Packed batch: block row x = camera, the blocks of a row stride over its pixels.
+__global__ void __launch_bounds__(256) k_post_batched(PostLaunch a, const rc_cam_desc* desc) {
+    const rc_cam_desc D = desc[blockIdx.x];
+    const int64_t np = (int64_t)D.width * D.height;
+    if (D.width < 1 || D.height < 1 || (int64_t)D.out_offset + np > a.n_pix) return;
+    for (int64_t q = (int64_t)blockIdx.y * blockDim.x + threadIdx.x; q < np;
+         q += (int64_t)gridDim.y * blockDim.x)
+        post_pixel(a, (int64_t)D.out_offset + q, (uint32_t)q, D.cam_uid,
+                   a.lat_out ? a.lat_out + blockIdx.x : nullptr);
 }
 
 }  // namespace
@@ -88,6 +106,12 @@ __global__ void __launch_bounds__(256) k_post(PostLaunch a) {
 hipError_t launch_post(const PostLaunch& a, hipStream_t s) {
     const unsigned blocks = (unsigned)((a.n_pix + 255) / 256);
     hipLaunchKernelGGL(k_post, dim3(blocks), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_post_batched(const PostLaunch& a, const rc_cam_desc* desc, int n_desc,
+                               hipStream_t s) {
+    hipLaunchKernelGGL(k_post_batched, dim3((unsigned)n_desc, 8), dim3(256), 0, s, a, desc);
     return hipGetLastError();
 }
 

@@ -29,8 +29,12 @@ namespace rc {
 
 namespace {
 
-constexpr int kTile = 8;             // 8 x 8 pixels per wavefront
 constexpr int kWavesPerBlock = 4;
+constexpr int kChunk = 8;  // tiles a wavefront of the batched launch takes at a time
+
+struct TileCfg {
+    int tw, th, rpl;  // tile width and height (tw * th = 64), tiles per wavefront
+};
 // FP32 edge decisions are trusted when every edge function is farther than
 // kappa * (|U| + |V| + |W|) from zero.  Measured on the 4096-env workload, the
 // FP32 error of the normalised edge functions is at most 3.7e-6 for terrain
@@ -133,33 +137,39 @@ __device__ __forceinline__ void quat_mat64(const float* __restrict__ q, double R
     R[6] = 2 * (x * z - y * w); R[7] = 2 * (y * z + x * w); R[8] = 1 - 2 * (x * x + y * y);
 }
 
-// FP64 camera ray of pixel (x, y) of image ec: o = p_c, d = R(q_c) K^-1 [x+.5, y+.5, 1].
-__device__ __forceinline__ void pixel_ray64(const float* __restrict__ cam_pos,
-                                            const float* __restrict__ cam_quat,
-                                            const float* __restrict__ intr, int64_t ec, int x, int y,
-                                            double o[3], double d[3], double& rx, double& ry) {
-    const float* K = intr + 4 * ec;
+// A camera: centre p_c [3], quaternion q_c [4] (optical -> world), intrinsics
+// (fx, fy, cx, cy) [4]; either rows of the plain [env][cam] arrays or fields
+// of a batched camera descriptor.
+struct CamRef {
+    const float* pos;
+    const float* quat;
+    const float* intr;
+};
+
+// FP64 camera ray of pixel (x, y): o = p_c, d = R(q_c) K^-1 [x+.5, y+.5, 1].
+__device__ __forceinline__ void pixel_ray64(const CamRef& cam, int x, int y, double o[3],
+                                            double d[3], double& rx, double& ry) {
+    const float* K = cam.intr;
     rx = ((double)x + 0.5 - (double)K[2]) / (double)K[0];
     ry = ((double)y + 0.5 - (double)K[3]) / (double)K[1];
     double R[9];
-    quat_mat64(cam_quat + 4 * ec, R);
+    quat_mat64(cam.quat, R);
     d[0] = R[0] * rx + R[1] * ry + R[2];
     d[1] = R[3] * rx + R[4] * ry + R[5];
     d[2] = R[6] * rx + R[7] * ry + R[8];
-    o[0] = cam_pos[3 * ec]; o[1] = cam_pos[3 * ec + 1]; o[2] = cam_pos[3 * ec + 2];
+    o[0] = cam.pos[0]; o[1] = cam.pos[1]; o[2] = cam.pos[2];
 }
 
 // The exact-decision path: rebuild the pixel's FP64 ray (and its FP64 link-frame
 // ray for link >= 0) and repeat the triangle test in FP64.  Rarely taken, so it
 // recomputes everything instead of keeping an FP64 ray live in registers.
-__device__ __noinline__ bool refine(const float* __restrict__ v, const float* __restrict__ cam_pos,
-                                    const float* __restrict__ cam_quat,
-                                    const float* __restrict__ intr, int64_t ec, int x, int y,
+__device__ __noinline__ bool refine(const float* __restrict__ v, const float* cam_pos,
+                                    const float* cam_quat, const float* cam_intr, int x, int y,
                                     int link, int e, int n_links,
                                     const float* __restrict__ link_pos,
                                     const float* __restrict__ link_quat, double* t) {
     double o[3], d[3], rx, ry;
-    pixel_ray64(cam_pos, cam_quat, intr, ec, x, y, o, d, rx, ry);
+    pixel_ray64(CamRef{cam_pos, cam_quat, cam_intr}, x, y, o, d, rx, ry);
     if (link >= 0) {
         const int64_t eb = (int64_t)e * n_links + link;
         double R[9];
@@ -183,12 +193,9 @@ struct Hit {
 };
 
 struct PixelRef {  // what the exact-decision path needs to rebuild the ray
-    const float* cam_pos;
-    const float* cam_quat;
-    const float* intr;
+    CamRef cam;
     const float* link_pos;
     const float* link_quat;
-    int64_t ec;
     int x, y, e, n_links;
 };
 
@@ -236,7 +243,7 @@ __device__ __forceinline__ void tri_test(const float* __restrict__ v, int32_t tr
         }
     } else {
         double t64;
-        if (!refine(v, px.cam_pos, px.cam_quat, px.intr, px.ec, px.x, px.y, link, px.e, px.n_links,
+        if (!refine(v, px.cam.pos, px.cam.quat, px.cam.intr, px.x, px.y, link, px.e, px.n_links,
                     px.link_pos, px.link_quat, &t64))
             return;
         t = (float)t64;
@@ -347,10 +354,10 @@ __device__ __forceinline__ void enter_link(const RenderLaunch& a, int e, int b, 
 // it, a link only by the lanes whose rays hit its box).  Otherwise each lane
 // walks the top level alone.
 template <bool EXACT, bool WAVE>
-__device__ __forceinline__ Hit cast_ray(const RenderLaunch& a, int64_t ec, int e, int x, int y,
+__device__ __forceinline__ Hit cast_ray(const RenderLaunch& a, const CamRef& cam, int e, int x, int y,
                                         double& scale, float bound) {
     double o64[3], d64[3], rx, ry;
-    pixel_ray64(a.cam_pos, a.cam_quat, a.intr, ec, x, y, o64, d64, rx, ry);
+    pixel_ray64(cam, x, y, o64, d64, rx, ry);
     const float ox = (float)o64[0], oy = (float)o64[1], oz = (float)o64[2];
     const float dx = (float)d64[0], dy = (float)d64[1], dz = (float)d64[2];
     scale = a.depth_mode == RC_DEPTH_RANGE ? sqrt(rx * rx + ry * ry + 1.0) : 1.0;
@@ -358,7 +365,7 @@ __device__ __forceinline__ Hit cast_ray(const RenderLaunch& a, int64_t ec, int e
     h.tmax = fminf((float)((double)a.far_plane / scale), bound);
     h.key = ~0ull;
     h.tu = INFINITY;
-    const PixelRef px{a.cam_pos, a.cam_quat, a.intr, a.link_pos, a.link_quat, ec, x, y, e, a.n_links};
+    const PixelRef px{cam, a.link_pos, a.link_quat, x, y, e, a.n_links};
 
     if (a.n_links > 0) {
         const int n_rec = a.n_links > 1 ? a.n_links - 1 : 1;
@@ -473,78 +480,307 @@ __device__ __forceinline__ void write_out(const RenderLaunch& a, int64_t p, cons
     if (a.tri) a.tri[p] = hit ? (int32_t)(uint32_t)h.key : -1;
 }
 
-// Fast pass: one 8x8 tile per wavefront, FP32 decisions only.
-__global__ void __launch_bounds__(256) k_render(RenderLaunch a, int64_t n_logical, int64_t per_xcd) {
+__device__ __forceinline__ CamRef plain_cam(const RenderLaunch& a, int64_t ec) {
+    return CamRef{a.cam_pos + 3 * ec, a.cam_quat + 4 * ec, a.intr + 4 * ec};
+}
+
+__device__ __forceinline__ CamRef desc_cam(const rc_cam_desc* d) {
+    return CamRef{d->pos, d->quat, d->intr};
+}
+
+// Cast the rpl stacked tw x th sub-tiles of one wavefront tile of an image
+// (width x height, env e, camera `cam`, output pixels from `out0`); lanes
+// past the image edge trace a copy of an edge pixel (so wave-wide reductions
+// see only real rays) and write nothing.  Rays whose closest hit could hinge
+// on an FP32-undecided triangle go to the exact pass's list, with the certain
+// hit found here as their starting bound.
+template <int RPL>
+__device__ __forceinline__ void cast_tile(const RenderLaunch& a, const TileCfg& c, const CamRef& cam,
+                                          int e, uint32_t cam_index, int width, int height,
+                                          int64_t out0, int tx, int ty) {
+    const int lane = threadIdx.x & 63;
+    const int span_h = c.th * RPL;
+    const int xt = tx * c.tw + (lane % c.tw);
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+        const int y0 = ty * span_h + r * c.th;
+        if (y0 >= height) break;  // wave-uniform
+        const int yt = y0 + lane / c.tw;
+        const bool valid = xt < width && yt < height;
+        const int x = xt < width ? xt : width - 1;
+        const int y = yt < height ? yt : height - 1;
+        double scale;
+        const Hit h = cast_ray<false, true>(a, cam, e, x, y, scale, INFINITY);
+        if (!valid) continue;
+        const int64_t p = out0 + (int64_t)y * width + x;
+        write_out(a, p, h, scale);
+        if (h.tu <= h.tmax * (1.0f + 1.0f / 1024.0f)) {
+            const uint32_t slot = atomicAdd(a.exact_count, 1u);
+            if ((int64_t)slot < a.exact_cap)
+                a.exact_list[slot] = make_uint4((uint32_t)p, cam_index,
+                                                (uint32_t)x | ((uint32_t)y << 16),
+                                                __float_as_uint(h.tmax));
+        }
+    }
+}
+
+// Fast pass over the plain [env][cam][H][W] layout.  WAVES asks the compiler
+// for at least that many resident wavefronts per SIMD (fewer registers per
+// lane, maybe a few spills); the autotuner picks it and the tile schedule.
+template <int WAVES, int RPL>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES, 8)))
+k_render(RenderLaunch a, TileCfg c, int64_t n_logical, int64_t per_xcd) {
     // XCD-aware order: hardware deals blocks round-robin over the 8 XCDs, so
     // give each XCD a contiguous run of tiles (neighbouring environments share
     // terrain nodes in that XCD's L2).
     const int64_t bid = blockIdx.x;
     const int64_t lb = (bid & 7) * per_xcd + (bid >> 3);
     if (lb >= n_logical) return;
-    const int lane = threadIdx.x & 63;
     const int64_t tile = (int64_t)uni((int)(lb * kWavesPerBlock)) + uni(threadIdx.x >> 6);
-    const int tiles_x = (a.width + kTile - 1) / kTile;
-    const int tiles_y = (a.height + kTile - 1) / kTile;
+    const int span_h = c.th * c.rpl;
+    const int tiles_x = (a.width + c.tw - 1) / c.tw;
+    const int tiles_y = (a.height + span_h - 1) / span_h;
     const int64_t tiles_img = (int64_t)tiles_x * tiles_y;
     const int64_t ec = tile / tiles_img;
     if (ec >= (int64_t)a.n_env * a.n_cam) return;
     const int tin = (int)(tile - ec * tiles_img);
-    const int xt = (tin % tiles_x) * kTile + (lane & 7);
-    const int yt = (tin / tiles_x) * kTile + (lane >> 3);
-    // lanes past the image edge trace a copy of an edge pixel (so wave-wide
-    // reductions see only real rays) and write nothing
-    const bool valid = xt < a.width && yt < a.height;
-    const int x = xt < a.width ? xt : a.width - 1;
-    const int y = yt < a.height ? yt : a.height - 1;
-    const int e = (int)(ec / a.n_cam);
-    double scale;
-    const Hit h = cast_ray<false, true>(a, ec, e, x, y, scale, INFINITY);
-    if (!valid) return;
-    const int64_t p = ec * (int64_t)a.width * a.height + (int64_t)y * a.width + x;
-    write_out(a, p, h, scale);
-    // an FP32-undecided triangle at or before the hit: re-cast exactly, with the
-    // certain hit found here as the starting bound (nothing farther can win)
-    if (h.tu <= h.tmax * (1.0f + 1.0f / 1024.0f)) {
-        const uint32_t slot = atomicAdd(a.exact_count, 1u);
-        if ((int64_t)slot < a.exact_cap)
-            a.exact_list[slot] = make_uint2((uint32_t)p, __float_as_uint(h.tmax));
+    cast_tile<RPL>(a, c, plain_cam(a, ec), (int)(ec / a.n_cam), (uint32_t)ec, a.width, a.height,
+                   ec * (int64_t)a.width * a.height, tin % tiles_x, tin / tiles_x);
+}
+
+// Batched uneven form, setup: validate each camera descriptor, count its
+// tiles, prefix-sum them (one block) and reset the work counter, the exact
+// list and the status word.  An invalid descriptor gets no tiles and sets
+// bit 0 of *status.
+__global__ void __launch_bounds__(1024) k_batch_prep(RenderLaunch a, TileCfg c, uint32_t* tile_start,
+                                                     uint32_t* queues, uint32_t* status) {
+    __shared__ uint32_t sums[1024];
+    if (threadIdx.x == 0) *status = 0u;
+    const int n = a.n_desc;
+    const int chunk = (n + 1023) / 1024;
+    const int b = threadIdx.x * chunk, e = min(b + chunk, n);
+    uint32_t local = 0;
+    bool bad = false;
+    for (int d = b; d < e; ++d) {
+        const rc_cam_desc& D = a.desc[d];
+        const bool ok = D.env >= 0 && D.env < a.n_env && D.width >= 1 && D.height >= 1 &&
+                        D.width <= a.max_width && D.height <= a.max_height &&
+                        (int64_t)D.out_offset + (int64_t)D.width * D.height <= a.n_pixels;
+        bad |= !ok;
+        const int span_h = c.th * c.rpl;
+        local += ok ? (uint32_t)(((D.width + c.tw - 1) / c.tw) * ((D.height + span_h - 1) / span_h)) : 0u;
+    }
+    sums[threadIdx.x] = local;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const uint32_t add = threadIdx.x >= (unsigned)off ? sums[threadIdx.x - off] : 0u;
+        __syncthreads();
+        sums[threadIdx.x] += add;
+        __syncthreads();
+    }
+    uint32_t run = sums[threadIdx.x] - local;
+    for (int d = b; d < e; ++d) {
+        tile_start[d] = run;
+        const rc_cam_desc& D = a.desc[d];
+        const bool ok = D.env >= 0 && D.env < a.n_env && D.width >= 1 && D.height >= 1 &&
+                        D.width <= a.max_width && D.height <= a.max_height &&
+                        (int64_t)D.out_offset + (int64_t)D.width * D.height <= a.n_pixels;
+        const int span_h = c.th * c.rpl;
+        run += ok ? (uint32_t)(((D.width + c.tw - 1) / c.tw) * ((D.height + span_h - 1) / span_h)) : 0u;
+    }
+    if (threadIdx.x == 1023) tile_start[n] = sums[1023];
+    if (threadIdx.x == 0) queues[0] = 0u;
+    if (threadIdx.x == 0) *a.exact_count = 0u;
+    if (bad) atomicOr(status, 1u);
+}
+
+// Batched uneven form: one persistent launch.  Each wavefront takes chunks
+// of kChunk consecutive tiles from one work counter (consecutive tiles are
+// neighbouring pixels of one camera, so a chunk's rays share cache lines on
+// the XCD that runs it) until the tiles run out; the tile table maps a tile
+// to its camera descriptor by binary search.
+template <int WAVES, int RPL>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES, 8)))
+k_render_batched(RenderLaunch a, TileCfg c, const uint32_t* __restrict__ tile_start,
+                 uint32_t* queue) {
+    const int lane = threadIdx.x & 63;
+    const uint32_t n_tiles = tile_start[a.n_desc];
+    for (;;) {
+        uint32_t t0 = 0;
+        if (lane == 0) t0 = atomicAdd(queue, (uint32_t)kChunk);
+        t0 = (uint32_t)uni((int)__shfl(t0, 0, 64));
+        if (t0 >= n_tiles) break;
+        const uint32_t t1 = min(t0 + (uint32_t)kChunk, n_tiles);
+        for (uint32_t tile = t0; tile < t1; ++tile) {
+            // the descriptor owning this tile: last d with tile_start[d] <= tile
+            int lo = 0, hi = a.n_desc - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (tile_start[mid] <= tile) lo = mid; else hi = mid - 1;
+            }
+            const int d = uni(lo);
+            const rc_cam_desc* D = a.desc + d;
+            const int width = D->width;
+            const int tiles_x = (width + c.tw - 1) / c.tw;
+            const int tin = (int)(tile - tile_start[d]);
+            cast_tile<RPL>(a, c, desc_cam(D), D->env, (uint32_t)d, width, D->height,
+                           (int64_t)D->out_offset, tin % tiles_x, tin / tiles_x);
+        }
     }
 }
 
+// Batched uneven form, flat launch: wavefront (camera d, tile k) of a
+// camera-major grid sized for the largest image; tiles past a camera's own
+// count exit at once.  No loop around the tile, so no state is carried
+// between tiles (the persistent form's loop costs registers).
+template <int WAVES, int RPL>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES, 8)))
+k_render_flat(RenderLaunch a, TileCfg c, const uint32_t* __restrict__ tile_start, int tiles_per_cam,
+              int64_t n_logical, int64_t per_xcd) {
+    const int64_t bid = blockIdx.x;
+    const int64_t lb = (bid & 7) * per_xcd + (bid >> 3);
+    if (lb >= n_logical) return;
+    const int64_t w = (int64_t)uni((int)(lb * kWavesPerBlock)) + uni(threadIdx.x >> 6);
+    const int d = (int)(w / tiles_per_cam);
+    const int k = (int)(w - (int64_t)d * tiles_per_cam);
+    if (d >= a.n_desc) return;
+    const uint32_t n_own = tile_start[d + 1] - tile_start[d];  // 0 for an invalid descriptor
+    if ((uint32_t)k >= n_own) return;
+    const rc_cam_desc* D = a.desc + d;
+    const int width = D->width;
+    const int tiles_x = (width + c.tw - 1) / c.tw;
+    cast_tile<RPL>(a, c, desc_cam(D), D->env, (uint32_t)d, width, D->height, (int64_t)D->out_offset,
+                   k % tiles_x, k / tiles_x);
+}
+
 // Exact pass: the rays the fast pass listed, each lane on its own, with FP64
-// decisions for undecided triangles.
-__global__ void __launch_bounds__(256) k_render_exact(RenderLaunch a) {
-    const uint32_t n = *a.exact_count;
-    const int64_t hw = (int64_t)a.width * a.height;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (int64_t)n && i < a.exact_cap;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const uint2 item = a.exact_list[i];
-        const int64_t p = item.x;
-        const int64_t ec = p / hw;
-        const int pin = (int)(p - ec * hw);
-        const int x = pin % a.width, y = pin / a.width;
-        double scale;
-        const Hit h = cast_ray<true, false>(a, ec, (int)(ec / a.n_cam), x, y, scale,
-                                            __uint_as_float(item.y));
-        write_out(a, p, h, scale);
+// decisions for undecided triangles.  Small blocks spread the few rays over
+// all compute units.  If the list overflowed, every pixel is re-cast.
+__device__ __forceinline__ void exact_one(const RenderLaunch& a, int64_t p, uint32_t cam_index, int x,
+                                          int y, float bound) {
+    CamRef cam;
+    int e;
+    if (a.desc) {
+        const rc_cam_desc* D = a.desc + cam_index;
+        cam = desc_cam(D);
+        e = D->env;
+    } else {
+        cam = plain_cam(a, cam_index);
+        e = (int)(cam_index / (uint32_t)a.n_cam);
     }
+    double scale;
+    const Hit h = cast_ray<true, false>(a, cam, e, x, y, scale, bound);
+    write_out(a, p, h, scale);
 }
 
 __global__ void k_zero_count(uint32_t* c) { *c = 0u; }
 
+__global__ void __launch_bounds__(64) k_render_exact(RenderLaunch a, const uint32_t* tile_start) {
+    const uint32_t n = *a.exact_count;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if ((int64_t)n <= a.exact_cap) {
+        for (int64_t i = gid; i < (int64_t)n; i += stride) {
+            const uint4 it = a.exact_list[i];
+            exact_one(a, it.x, it.y, (int)(it.z & 0xFFFFu), (int)(it.z >> 16), __uint_as_float(it.w));
+        }
+        return;
+    }
+    // overflow: re-cast every pixel exactly
+    if (!a.desc) {
+        const int64_t hw = (int64_t)a.width * a.height;
+        for (int64_t p = gid; p < a.n_pixels; p += stride) {
+            const int64_t ec = p / hw;
+            const int pin = (int)(p - ec * hw);
+            exact_one(a, p, (uint32_t)ec, pin % a.width, pin / a.width, INFINITY);
+        }
+    } else {
+        for (int d = 0; d < a.n_desc; ++d) {
+            const rc_cam_desc& D = a.desc[d];
+            if (tile_start[d + 1] == tile_start[d]) continue;  // invalid descriptor
+            const int64_t np = (int64_t)D.width * D.height;
+            for (int64_t q = gid; q < np; q += stride)
+                exact_one(a, (int64_t)D.out_offset + q, (uint32_t)d, (int)(q % D.width),
+                          (int)(q / D.width), INFINITY);
+        }
+    }
+}
+
 }  // namespace
 
-hipError_t launch_render(const RenderLaunch& a, hipStream_t s) {
-    const int tiles_x = (a.width + kTile - 1) / kTile;
-    const int tiles_y = (a.height + kTile - 1) / kTile;
+hipError_t launch_render(const RenderLaunch& a, const RenderCfg& cfg, hipStream_t s) {
+    TileCfg c{cfg.tile_w, cfg.tile_h, cfg.rays_per_lane};
+    const int span_h = c.th * c.rpl;
+    const int tiles_x = (a.width + c.tw - 1) / c.tw;
+    const int tiles_y = (a.height + span_h - 1) / span_h;
     const int64_t tiles = (int64_t)a.n_env * a.n_cam * tiles_x * tiles_y;
     const int64_t n_logical = (tiles + kWavesPerBlock - 1) / kWavesPerBlock;
     const int64_t per_xcd = (n_logical + 7) / 8;
+    const dim3 grid((unsigned)(per_xcd * 8)), block(64 * kWavesPerBlock);
     hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(1), 0, s, a.exact_count);
-    hipLaunchKernelGGL(k_render, dim3((unsigned)(per_xcd * 8)), dim3(64 * kWavesPerBlock), 0, s, a,
-                       n_logical, per_xcd);
-    hipLaunchKernelGGL(k_render_exact, dim3(1024), dim3(256), 0, s, a);
+#define RC_PLAIN(W, R) hipLaunchKernelGGL((k_render<W, R>), grid, block, 0, s, a, c, n_logical, per_xcd)
+    const int v = 10 * cfg.waves + c.rpl;
+    switch (v) {
+        case 71: RC_PLAIN(7, 1); break;
+        case 72: RC_PLAIN(7, 2); break;
+        case 81: RC_PLAIN(8, 1); break;
+        case 82: RC_PLAIN(8, 2); break;
+        case 62: RC_PLAIN(6, 2); break;
+        default: RC_PLAIN(6, 1); break;
+    }
+#undef RC_PLAIN
+    hipLaunchKernelGGL(k_render_exact, dim3(4096), dim3(64), 0, s, a, (const uint32_t*)nullptr);
     return hipGetLastError();
+}
+
+hipError_t launch_render_batched(const RenderLaunch& a, const RenderCfg& cfg, uint32_t* tile_start,
+                                 uint32_t* queues, uint32_t* status, int persistent_blocks,
+                                 hipStream_t s) {
+    TileCfg c{cfg.tile_w, cfg.tile_h, cfg.rays_per_lane};
+    hipLaunchKernelGGL(k_batch_prep, dim3(1), dim3(1024), 0, s, a, c, tile_start, queues, status);
+    const dim3 block(64 * kWavesPerBlock);
+    const int v = 10 * cfg.waves + c.rpl;
+    if (cfg.persistent) {
+        const dim3 grid((unsigned)persistent_blocks);
+#define RC_BATCH(W, R) \
+    hipLaunchKernelGGL((k_render_batched<W, R>), grid, block, 0, s, a, c, tile_start, queues)
+        switch (v) {
+            case 71: RC_BATCH(7, 1); break;
+            case 72: RC_BATCH(7, 2); break;
+            case 81: RC_BATCH(8, 1); break;
+            case 82: RC_BATCH(8, 2); break;
+            case 62: RC_BATCH(6, 2); break;
+            default: RC_BATCH(6, 1); break;
+        }
+#undef RC_BATCH
+    } else {
+        const int span_h = c.th * c.rpl;
+        const int tiles_per_cam = ((a.max_width + c.tw - 1) / c.tw) * ((a.max_height + span_h - 1) / span_h);
+        const int64_t waves = (int64_t)a.n_desc * tiles_per_cam;
+        const int64_t n_logical = (waves + kWavesPerBlock - 1) / kWavesPerBlock;
+        const int64_t per_xcd = (n_logical + 7) / 8;
+        const dim3 grid((unsigned)(per_xcd * 8));
+#define RC_FLAT(W, R)                                                                         \
+    hipLaunchKernelGGL((k_render_flat<W, R>), grid, block, 0, s, a, c, (const uint32_t*)tile_start, \
+                       tiles_per_cam, n_logical, per_xcd)
+        switch (v) {
+            case 71: RC_FLAT(7, 1); break;
+            case 72: RC_FLAT(7, 2); break;
+            case 81: RC_FLAT(8, 1); break;
+            case 82: RC_FLAT(8, 2); break;
+            case 62: RC_FLAT(6, 2); break;
+            default: RC_FLAT(6, 1); break;
+        }
+#undef RC_FLAT
+    }
+    hipLaunchKernelGGL(k_render_exact, dim3(4096), dim3(64), 0, s, a, (const uint32_t*)tile_start);
+    return hipGetLastError();
+}
+
+bool render_cfg_ok(const RenderCfg& c) {
+    return c.tile_w >= 1 && c.tile_h >= 1 && c.tile_w * c.tile_h == 64 &&
+           (c.rays_per_lane == 1 || c.rays_per_lane == 2) &&
+           (c.waves == 6 || c.waves == 7 || c.waves == 8);
 }
 
 }  // namespace rc

@@ -89,12 +89,27 @@ struct RenderLaunch {
     int32_t* inst;
     int32_t* tri;
     uint32_t* exact_count;  // rays the fast pass hands to the exact pass
-    uint2* exact_list;      // (pixel index, bits of the fast pass's bound)
+    uint4* exact_list;      // (pixel, camera index, x | y << 16, bits of the fast pass's bound)
     int64_t exact_cap;
+    const rc_cam_desc* desc;  // batched form: camera descriptors (NULL: plain layout)
+    int n_desc;
+    int max_width, max_height;  // batched form: largest image a descriptor may have
+    int64_t n_pixels;         // output pixels
     int n_env, n_cam, width, height, n_links, depth_mode, n_terrain;
     float far_plane;
 };
-hipError_t launch_render(const RenderLaunch& a, hipStream_t s);
+// Launch schedule of the fast pass (chosen by the autotuner).
+struct RenderCfg {
+    int tile_w = 8, tile_h = 8;  // pixels per wavefront tile, tile_w * tile_h = 64
+    int rays_per_lane = 1;       // tiles each wavefront casts, stacked vertically
+    int waves = 6;               // resident wavefronts per SIMD asked of the compiler (6, 7, 8)
+    int persistent = 0;          // batched form: persistent work-queue launch (1) or flat grid (0)
+};
+bool render_cfg_ok(const RenderCfg& c);
+hipError_t launch_render(const RenderLaunch& a, const RenderCfg& cfg, hipStream_t s);
+hipError_t launch_render_batched(const RenderLaunch& a, const RenderCfg& cfg, uint32_t* tile_start,
+                                 uint32_t* queues, uint32_t* status, int persistent_blocks,
+                                 hipStream_t s);
 
 struct PostLaunch {
     const float* depth_in;
@@ -114,6 +129,8 @@ struct PostLaunch {
     uint32_t flags;
 };
 hipError_t launch_post(const PostLaunch& a, hipStream_t s);
+hipError_t launch_post_batched(const PostLaunch& a, const rc_cam_desc* desc, int n_desc,
+                               hipStream_t s);
 
 void set_error(const std::string& msg);
 

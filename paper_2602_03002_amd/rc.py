@@ -23,7 +23,18 @@ EXPORTED = [
     "rc_render_size", "rc_render", "rc_render_exact_count",
     "rc_post_size", "rc_post_create", "rc_post_reset", "rc_postprocess", "rc_post_destroy",
     "rc_bvh_layout_of",
+    "rc_render_batched_size", "rc_render_batched", "rc_render_batched_status",
+    "rc_get_render_config", "rc_set_render_config", "rc_autotune",
+    "rc_graph_capture_batched", "rc_graph_launch", "rc_graph_destroy",
+    "rc_post_size_packed", "rc_post_create_packed", "rc_postprocess_batched",
 ]
+
+import numpy as np  # noqa: E402
+
+# rc_cam_desc, 64 bytes
+CAM_DESC = np.dtype([("env", "<i4"), ("width", "<i4"), ("height", "<i4"), ("out_offset", "<u4"),
+                     ("cam_uid", "<u4"), ("pos", "<f4", 3), ("quat", "<f4", 4), ("intr", "<f4", 4)])
+assert CAM_DESC.itemsize == 64
 
 
 class RcError(RuntimeError):
@@ -48,6 +59,24 @@ class PostParams(ctypes.Structure):
                 ("near_plane", ctypes.c_float), ("far_plane", ctypes.c_float),
                 ("fill", ctypes.c_float), ("lat_min", ctypes.c_int32),
                 ("lat_max", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class BatchArgs(ctypes.Structure):
+    _fields_ = [("n_env", ctypes.c_int32), ("n_desc", ctypes.c_int32),
+                ("link_pos", ctypes.c_void_p), ("link_quat", ctypes.c_void_p),
+                ("desc", ctypes.c_void_p), ("n_pixels", ctypes.c_int64),
+                ("max_width", ctypes.c_int32), ("max_height", ctypes.c_int32),
+                ("far_plane", ctypes.c_float), ("depth_mode", ctypes.c_int32),
+                ("depth", ctypes.c_void_p), ("inst", ctypes.c_void_p), ("tri", ctypes.c_void_p)]
+
+
+class RenderConfig(ctypes.Structure):
+    _fields_ = [("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32),
+                ("rays_per_lane", ctypes.c_int32), ("waves", ctypes.c_int32),
+                ("persistent", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class BvhLayout(ctypes.Structure):
@@ -87,6 +116,22 @@ def lib():
                                      vp, vp, vp, vp]
         L.rc_post_destroy.argtypes = [vp]
         L.rc_bvh_layout_of.argtypes = [vp, i32, ctypes.POINTER(BvhLayout)]
+        L.rc_render_batched_size.argtypes = [vp, i32, i32, i64, ctypes.POINTER(sz)]
+        L.rc_render_batched.argtypes = [vp, ctypes.POINTER(BatchArgs), vp, sz, vp]
+        L.rc_render_batched_status.argtypes = [vp, ctypes.POINTER(BatchArgs), vp,
+                                               ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(i64), vp]
+        L.rc_get_render_config.argtypes = [vp, i32, ctypes.POINTER(RenderConfig)]
+        L.rc_set_render_config.argtypes = [vp, i32, ctypes.POINTER(RenderConfig)]
+        L.rc_autotune.argtypes = [vp, ctypes.POINTER(RenderArgs), ctypes.POINTER(BatchArgs), vp, sz,
+                                  i32, vp, ctypes.POINTER(RenderConfig), ctypes.POINTER(ctypes.c_float)]
+        L.rc_graph_capture_batched.argtypes = [vp, ctypes.POINTER(BatchArgs), vp, sz, vp,
+                                               ctypes.POINTER(vp)]
+        L.rc_graph_launch.argtypes = [vp, vp]
+        L.rc_graph_destroy.argtypes = [vp]
+        L.rc_post_size_packed.argtypes = [i64, i32, ctypes.POINTER(sz)]
+        L.rc_post_create_packed.argtypes = [i64, i32, vp, sz, ctypes.POINTER(vp)]
+        L.rc_postprocess_batched.argtypes = [vp, vp, vp, ctypes.POINTER(PostParams), ctypes.c_uint64,
+                                             vp, i32, vp, vp, vp, vp]
         for name in EXPORTED:
             if name not in ("rc_version", "rc_status_string", "rc_last_error"):
                 getattr(L, name).restype = i32
@@ -185,9 +230,8 @@ class Scene:
                                           ctypes.c_void_p(ws.ptr), ctypes.byref(c), _stream(stream)))
         return c.value
 
-    def render(self, cam_pos, cam_quat, intr, width, height, far_plane, link_pos=None,
-               link_quat=None, depth_mode=RC_DEPTH_PLANAR, out=None, ids=True, stream=None):
-        """Returns (depth [E,C,H,W] f32, inst i32 or None, tri i32 or None)."""
+    def _plain_args(self, cam_pos, cam_quat, intr, width, height, far_plane, link_pos, link_quat,
+                    depth_mode, out, ids):
         E, C = cam_pos.shape[0], cam_pos.shape[1]
         _dev_f32(cam_pos, (E, C, 3), "cam_pos")
         _dev_f32(cam_quat, (E, C, 4), "cam_quat")
@@ -201,13 +245,79 @@ class Scene:
             tri = torch.empty_like(depth, dtype=torch.int32) if ids else None
         else:
             depth, inst, tri = out
-        ws = self.render_workspace(E, C, width, height)
         a = RenderArgs(E, C, width, height, _ptr(link_pos) if self.n_links else None,
                        _ptr(link_quat) if self.n_links else None, _ptr(cam_pos), _ptr(cam_quat),
                        _ptr(intr), float(far_plane), depth_mode, _ptr(depth), _ptr(inst), _ptr(tri))
+        return a, (depth, inst, tri), self.render_workspace(E, C, width, height)
+
+    def render(self, cam_pos, cam_quat, intr, width, height, far_plane, link_pos=None,
+               link_quat=None, depth_mode=RC_DEPTH_PLANAR, out=None, ids=True, stream=None):
+        """Returns (depth [E,C,H,W] f32, inst i32 or None, tri i32 or None)."""
+        a, outs, ws = self._plain_args(cam_pos, cam_quat, intr, width, height, far_plane, link_pos,
+                                       link_quat, depth_mode, out, ids)
         check(lib().rc_render(self.handle, ctypes.byref(a), ctypes.c_void_p(ws.ptr), ws.nbytes,
                               _stream(stream)))
-        return depth, inst, tri
+        return outs
+
+    # -- batched uneven form -------------------------------------------------
+
+    def batch(self, desc, n_pixels, max_width, max_height, far_plane, link_pos=None,
+              link_quat=None, depth_mode=RC_DEPTH_PLANAR, out=None, ids=True):
+        """Argument block of a batched render.  desc: uint8 CUDA tensor holding
+        n_desc rc_cam_desc records (see CAM_DESC)."""
+        if desc.device.type != "cuda" or desc.dtype != torch.uint8 or desc.numel() % 64:
+            raise ValueError("desc: need a uint8 CUDA tensor of 64-byte rc_cam_desc records")
+        n_desc = desc.numel() // 64
+        E = link_pos.shape[0] if link_pos is not None else 1
+        if self.n_links > 0:
+            _dev_f32(link_pos, (E, self.n_links, 3), "link_pos")
+            _dev_f32(link_quat, (E, self.n_links, 4), "link_quat")
+        if out is None:
+            depth = torch.empty(n_pixels, dtype=torch.float32, device=self.device)
+            inst = torch.empty(n_pixels, dtype=torch.int32, device=self.device) if ids else None
+            tri = torch.empty(n_pixels, dtype=torch.int32, device=self.device) if ids else None
+        else:
+            depth, inst, tri = out
+        a = BatchArgs(E, n_desc, _ptr(link_pos) if self.n_links else None,
+                      _ptr(link_quat) if self.n_links else None, _ptr(desc), int(n_pixels),
+                      int(max_width), int(max_height), float(far_plane), depth_mode, _ptr(depth),
+                      _ptr(inst), _ptr(tri))
+        key = ("batch", E, n_desc, int(n_pixels))
+        ws = self._render_ws.get(key)
+        if ws is None:
+            size = ctypes.c_size_t()
+            check(lib().rc_render_batched_size(self.handle, E, n_desc, int(n_pixels), ctypes.byref(size)))
+            ws = Workspace(size.value, self.device)
+            self._render_ws[key] = ws
+        return Batch(self, a, (depth, inst, tri), ws, (desc, link_pos, link_quat))
+
+    def config(self, batched=False):
+        c = RenderConfig()
+        check(lib().rc_get_render_config(self.handle, int(batched), ctypes.byref(c)))
+        return c.as_dict()
+
+    def set_config(self, batched=False, **kw):
+        c = RenderConfig(**{**self.config(batched), **kw})
+        check(lib().rc_set_render_config(self.handle, int(batched), ctypes.byref(c)))
+
+    def autotune(self, reps=3, stream=None, batch=None, **plain):
+        """Time every schedule on one launch (plain keyword args as for render(),
+        or batch=Batch) and keep the fastest.  Returns (config dict, ms)."""
+        best, ms = RenderConfig(), ctypes.c_float()
+        if batch is not None:
+            check(lib().rc_autotune(self.handle, None, ctypes.byref(batch.args),
+                                    ctypes.c_void_p(batch.ws.ptr), batch.ws.nbytes, reps,
+                                    _stream(stream), ctypes.byref(best), ctypes.byref(ms)))
+        else:
+            a, _, ws = self._plain_args(plain["cam_pos"], plain["cam_quat"], plain["intr"],
+                                        plain["width"], plain["height"], plain["far_plane"],
+                                        plain.get("link_pos"), plain.get("link_quat"),
+                                        plain.get("depth_mode", RC_DEPTH_PLANAR), plain.get("out"),
+                                        True)
+            check(lib().rc_autotune(self.handle, ctypes.byref(a), None, ctypes.c_void_p(ws.ptr),
+                                    ws.nbytes, reps, _stream(stream), ctypes.byref(best),
+                                    ctypes.byref(ms)))
+        return best.as_dict(), ms.value
 
     def bvh_layout(self, which=-1):
         out = BvhLayout()
@@ -226,6 +336,54 @@ class Scene:
             pass
 
 
+class Batch:
+    """A batched render's arguments, outputs and workspace (keeps tensors alive)."""
+
+    def __init__(self, scene, args, outs, ws, keep):
+        self.scene, self.args, self.outs, self.ws, self._keep = scene, args, outs, ws, keep
+
+    def render(self, stream=None):
+        check(lib().rc_render_batched(self.scene.handle, ctypes.byref(self.args),
+                                      ctypes.c_void_p(self.ws.ptr), self.ws.nbytes, _stream(stream)))
+        return self.outs
+
+    def status(self, stream=None):
+        """(status word, rays re-cast exactly) of the last render; synchronises."""
+        st, n = ctypes.c_uint32(), ctypes.c_int64()
+        check(lib().rc_render_batched_status(self.scene.handle, ctypes.byref(self.args),
+                                             ctypes.c_void_p(self.ws.ptr), ctypes.byref(st),
+                                             ctypes.byref(n), _stream(stream)))
+        return st.value, n.value
+
+    def capture(self, stream=None):
+        """Capture this render into a graph; replay with Graph.launch()."""
+        g = ctypes.c_void_p()
+        check(lib().rc_graph_capture_batched(self.scene.handle, ctypes.byref(self.args),
+                                             ctypes.c_void_p(self.ws.ptr), self.ws.nbytes,
+                                             _stream(stream), ctypes.byref(g)))
+        return Graph(g, self)
+
+
+class Graph:
+    def __init__(self, handle, batch):
+        self.handle, self.batch = handle, batch
+
+    def launch(self, stream=None):
+        check(lib().rc_graph_launch(self.handle, _stream(stream)))
+        return self.batch.outs
+
+    def close(self):
+        if self.handle:
+            lib().rc_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def post_params(seed=0, sigma_abs=0.0, sigma_rel=0.0, p_drop=0.0, near=0.05, far=3.0, fill=0.0,
                 lat_min=0, lat_max=0, flags=None):
     if flags is None:
@@ -235,19 +393,45 @@ def post_params(seed=0, sigma_abs=0.0, sigma_rel=0.0, p_drop=0.0, near=0.05, far
 
 
 class Post:
-    """Sensor-model state (device ring of max_latency + 1 frames)."""
+    """Sensor-model state (device ring of max_latency + 1 frames).  Post(E, C, H, W,
+    L) for the plain layout; Post.packed(n_pixels, L) for batched outputs."""
 
-    def __init__(self, n_env, n_cam, height, width, max_latency, device="cuda"):
+    def __init__(self, n_env, n_cam, height, width, max_latency, device="cuda", _packed=None):
         L = lib()
         size = ctypes.c_size_t()
-        check(L.rc_post_size(n_env, n_cam, height, width, max_latency, ctypes.byref(size)))
-        self.ws = Workspace(size.value, device)
         h = ctypes.c_void_p()
-        check(L.rc_post_create(n_env, n_cam, height, width, max_latency,
-                               ctypes.c_void_p(self.ws.ptr), size.value, ctypes.byref(h)))
+        if _packed is None:
+            check(L.rc_post_size(n_env, n_cam, height, width, max_latency, ctypes.byref(size)))
+            self.ws = Workspace(size.value, device)
+            check(L.rc_post_create(n_env, n_cam, height, width, max_latency,
+                                   ctypes.c_void_p(self.ws.ptr), size.value, ctypes.byref(h)))
+            self.shape = (n_env, n_cam, height, width)
+        else:
+            check(L.rc_post_size_packed(_packed, max_latency, ctypes.byref(size)))
+            self.ws = Workspace(size.value, device)
+            check(L.rc_post_create_packed(_packed, max_latency, ctypes.c_void_p(self.ws.ptr),
+                                          size.value, ctypes.byref(h)))
+            self.shape = (_packed,)
         self.handle = h
-        self.shape = (n_env, n_cam, height, width)
         self.device = device
+
+    @classmethod
+    def packed(cls, n_pixels, max_latency, device="cuda"):
+        return cls(0, 0, 0, 0, max_latency, device=device, _packed=int(n_pixels))
+
+    def process_batched(self, depth, inst, params, step, desc, out=None, stream=None):
+        """Packed outputs: returns (depth_out [n_pixels], drop [n_pixels], lat [n_desc])."""
+        n_desc = desc.numel() // 64
+        if out is None:
+            d = torch.empty(self.shape, dtype=torch.float32, device=depth.device)
+            drop = torch.empty(self.shape, dtype=torch.uint8, device=depth.device)
+            lat = torch.empty(n_desc, dtype=torch.uint8, device=depth.device)
+        else:
+            d, drop, lat = out
+        check(lib().rc_postprocess_batched(self.handle, _ptr(depth), _ptr(inst), ctypes.byref(params),
+                                           int(step), _ptr(desc), n_desc, _ptr(d), _ptr(drop),
+                                           _ptr(lat), _stream(stream)))
+        return d, drop, lat
 
     def reset(self):
         check(lib().rc_post_reset(self.handle))

@@ -6,5 +6,6 @@ from .rng import MASTER_SEED, substream, splitmix64
 from .terrain import ProfileTerrain, TileTerrain, SlopeTile, StairsTile, StonesTile
 from .robot import Robot, octasphere, quat_from_matrix, N_LINKS
 from .cameras import intrinsics_from_fov, optical_axes, mounted_cameras
-from .workloads import (small_plain_case, robot_scene, robots_64, robots_4096,
+from .workloads import (small_plain_case, robot_scene, robots_64, robots_4096, uneven_cameras,
+                        uneven_4096, CAM_DESC, RES_SET,
                         synthetic_frames, SENSOR, NEAR, FAR)

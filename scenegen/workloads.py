@@ -97,3 +97,37 @@ def synthetic_frames(E, C, H, W, steps, seed=MASTER_SEED, label="frames", far=FA
     inst[miss] = -1
     depth[miss] = np.float32(far)
     return depth, inst
+
+
+# Batched uneven form: per-camera descriptors (the renderer's 64-byte layout)
+CAM_DESC = np.dtype([("env", "<i4"), ("width", "<i4"), ("height", "<i4"), ("out_offset", "<u4"),
+                     ("cam_uid", "<u4"), ("pos", "<f4", 3), ("quat", "<f4", 4), ("intr", "<f4", 4)])
+RES_SET = [(32, 24), (64, 48), (87, 58), (106, 60)]
+
+
+def uneven_cameras(scene, seed=MASTER_SEED, label="uneven", max_cams=4):
+    """Descriptors for 1..max_cams cameras per env with resolutions from RES_SET.
+
+    ``scene`` must come from robot_scene(..., n_cam=4, ...) (mounts 0..3).
+    Camera uid = e * 4 + mount index (environment-local, batch independent).
+    Returns (desc structured array, n_pixels).
+    """
+    E = scene["E"]
+    rng = substream(f"{label}/{E}", seed)
+    n_cams = rng.integers(1, max_cams + 1, E)
+    rows = []
+    off = 0
+    for e in range(E):
+        for c in range(int(n_cams[e])):
+            W, H = RES_SET[int(rng.integers(0, len(RES_SET)))]
+            K = intrinsics_from_fov(W, H, HFOV, VFOV)
+            rows.append((e, W, H, off, e * 4 + c, scene["cam_pos"][e, c], scene["cam_quat"][e, c], K))
+            off += W * H
+    return np.array(rows, dtype=CAM_DESC), off
+
+
+def uneven_4096(steps=3):
+    """4096 envs on the 20x20-tile terrain, each with 1-4 cameras of mixed sizes."""
+    sc = robot_scene(20, 64, 2.5, 4, 64, 48, steps=steps, label="uneven4096")
+    desc, n_pix = uneven_cameras(sc)
+    return sc, desc, n_pix
