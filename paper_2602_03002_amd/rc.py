@@ -356,11 +356,13 @@ class Batch:
         return st.value, n.value
 
     def capture(self, stream=None):
-        """Capture this render into a graph; replay with Graph.launch()."""
+        """Capture this render into a graph; replay with Graph.launch().  The
+        legacy null stream cannot capture, so a side stream is used by default."""
+        s = stream if stream is not None else torch.cuda.Stream()
         g = ctypes.c_void_p()
         check(lib().rc_graph_capture_batched(self.scene.handle, ctypes.byref(self.args),
                                              ctypes.c_void_p(self.ws.ptr), self.ws.nbytes,
-                                             _stream(stream), ctypes.byref(g)))
+                                             ctypes.c_void_p(s.cuda_stream), ctypes.byref(g)))
         return Graph(g, self)
 
 
