@@ -21,14 +21,44 @@ REF_VISITS = os.path.join(ROOT, "tests", "golden", "ref_visits_4096x2_64x48.json
 
 
 def bytes_per_ray():
-    """Algorithmic bytes per ray from reference visit counts (a CPU binned-SAH
-    BVH2 with ordered closest-first traversal under the same bound)."""
+    """Algorithmic bytes per ray of the ray-cast kernel, from reference visit
+    counts (a CPU binned-SAH BVH2 with ordered closest-first traversal under
+    the same bound): 12 output bytes + 56 per node + 36 per triangle + 28 per
+    instance pose."""
     if not os.path.exists(REF_VISITS):
         return None, None
     ref = json.load(open(REF_VISITS))
     c = ref["mean_counts"]
-    b = 12 + 13 + 56 * c["node"] + 36 * c["tri"] + 28 * c["inst"]
+    b = 12 + 56 * c["node"] + 36 * c["tri"] + 28 * c["inst"]
     return b, ref
+
+
+COUNTERS = os.path.join(ROOT, "profiles", "k_render_4096x2_64x48_hbm_counters.txt")
+KERNEL_SRC = [os.path.join(ROOT, "paper_2602_03002_amd", "csrc", f)
+              for f in ("raycast.hip", "rc_internal.h")]
+
+
+def kernel_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SRC:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per fast-pass launch from the committed rocprofv3 counter
+    summary, or None if the kernel source changed since it was taken."""
+    if not os.path.exists(COUNTERS):
+        return None
+    kv = {}
+    for line in open(COUNTERS):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256") != kernel_sha():
+        return None
+    return int(float(kv["traffic_bytes_per_launch"]))
 
 
 def cpu_baseline(w, budget_s=15.0, seed=5):
@@ -64,6 +94,79 @@ def cpu_baseline(w, budget_s=15.0, seed=5):
                       f"+ {w['link_tri'].shape[0]} link triangles each, FP64 brute force + band flags)"}
 
 
+def bench_batched(sc, steps, warmup):
+    """Uneven cameras (4096 envs, 1-4 cameras of 32x24..106x60 each): one
+    graph-captured batched launch per step vs the best plain alternative, one
+    rc_render per image size over the cameras of that size."""
+    import numpy as np
+    import torch
+    import scenegen as sg
+    print("[bench] batched uneven workload", file=sys.stderr, flush=True)
+    w, desc, n_pix = sg.uneven_4096(steps=3)
+    dev = "cuda"
+
+    def t(a):
+        return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+    lp_steps, lq_steps = t(w["link_pos"]), t(w["link_quat"])
+    lp, lq = lp_steps[0].clone(), lq_steps[0].clone()
+    d_dev = t(desc.view(np.uint8))
+    b = sc.batch(d_dev, n_pix, 106, 60, w["far"], link_pos=lp, link_quat=lq)
+    cfg, _ = sc.autotune(reps=2, batch=b)
+    g = b.capture()
+    stream = torch.cuda.current_stream()
+
+    def batched_step(k):
+        lp.copy_(lp_steps[k % 3])
+        lq.copy_(lq_steps[k % 3])
+        g.launch()
+
+    # plain alternative: cameras grouped by image size, each group one rc_render
+    groups = []
+    for (Wd, Hd) in sg.RES_SET:
+        sel = np.nonzero((desc["width"] == Wd) & (desc["height"] == Hd))[0]
+        if sel.size == 0:
+            continue
+        envs = t(desc["env"][sel].astype(np.int64))
+        groups.append(dict(W=Wd, H=Hd, envs=envs,
+                           cp=t(desc["pos"][sel][:, None]), cq=t(desc["quat"][sel][:, None]),
+                           K=t(desc["intr"][sel][:, None]),
+                           lp=torch.empty((sel.size, 30, 3), device=dev),
+                           lq=torch.empty((sel.size, 30, 4), device=dev)))
+
+    def plain_step(k):
+        for gr in groups:
+            torch.index_select(lp_steps[k % 3], 0, gr["envs"], out=gr["lp"])
+            torch.index_select(lq_steps[k % 3], 0, gr["envs"], out=gr["lq"])
+            sc.render(gr["cp"], gr["cq"], gr["K"], gr["W"], gr["H"], w["far"], link_pos=gr["lp"],
+                      link_quat=gr["lq"])
+
+    def timed(fn):
+        for k in range(warmup):
+            fn(k)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for k in range(steps):
+            fn(warmup + k)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    ms_b = timed(batched_step)
+    status, exact = b.status()
+    ms_p = timed(plain_step)
+    g.close()
+    return {"workload": f"{w['E']} envs, {desc.shape[0]} cameras (1-4 per env, sizes "
+                        f"{sg.RES_SET}), {n_pix} rays per step, per-step poses",
+            "value": round(n_pix / (ms_b / 1e3) / 1e6, 1), "unit": "Mrays/s",
+            "ms_per_step": round(ms_b, 4), "launch": "one graph-captured batched launch",
+            "schedule": cfg, "status": status, "exact_pass_rays": exact,
+            "plain_grouped_ms_per_step": round(ms_p, 4),
+            "plain_grouped_value": round(n_pix / (ms_p / 1e3) / 1e6, 1),
+            "speedup_vs_plain_grouped": round(ms_p / ms_b, 3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -73,6 +176,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one plain device copy of this size first (HBM counter calibration)")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the uneven batched section")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding "
@@ -120,14 +225,19 @@ def main():
     stream = torch.cuda.current_stream()
 
     def step(k, ev=None):
-        if ev is not None:
-            ev[0].record(stream)
+        # ev: events around the fast-pass kernel (the dominant kernel), recorded
+        # by the library on this stream
         sc.render(cp, cq, K, W, H, w["far"], link_pos=lp_all[k % S], link_quat=lq_all[k % S],
-                  out=(depth, inst, tri))
-        if ev is not None:
-            ev[1].record(stream)
+                  out=(depth, inst, tri), timing=ev)
         post.process(depth, inst, p, k, out=(pout, drop, lat))
 
+    tuned = None
+    if not args.no_autotune:
+        tuned, tuned_ms = sc.autotune(reps=2, cam_pos=cp, cam_quat=cq, intr=K, width=W, height=H,
+                                      far_plane=w["far"], link_pos=lp_all[0], link_quat=lq_all[0],
+                                      out=(depth, inst, tri))
+        print(f"[bench] autotuned plain schedule {tuned} ({tuned_ms:.3f} ms)", file=sys.stderr,
+              flush=True)
     for k in range(args.warmup):
         step(k)
     torch.cuda.synchronize()
@@ -135,6 +245,9 @@ def main():
 
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
            for _ in range(args.steps)]
+    for a_, b_ in evs:  # create the events before the timed region
+        a_.record(stream)
+        b_.record(stream)
     t_start = torch.cuda.Event(enable_timing=True)
     t_end = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -147,7 +260,7 @@ def main():
     wall = time.perf_counter() - w0
     gpu_ms = t_start.elapsed_time(t_end)
     ms_per_step = gpu_ms / args.steps
-    render_ms = [a.elapsed_time(b) for a, b in evs]
+    fast_ms = [a.elapsed_time(b) for a, b in evs]
     rays = E * C * H * W
     value = rays * args.steps / (gpu_ms / 1e3) / 1e6
 
@@ -155,13 +268,14 @@ def main():
     bpr, ref = bytes_per_ray()
     roof = None
     if bpr is not None:
-        r_ms = statistics.mean(render_ms)
+        r_ms = statistics.mean(fast_ms)
         achieved = bpr * rays / (r_ms / 1e3) / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "k_render (top-level build + ray cast)",
-                "bytes_per_ray": round(bpr, 1), "render_ms": round(r_ms, 3)}
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
+                "kernel": "k_render (fast pass)", "bytes_per_ray": round(bpr, 1),
+                "kernel_ms": round(r_ms, 4)}
 
+    batched = None if args.no_batched else bench_batched(sc, args.steps, args.warmup)
     cpu = None if args.no_cpu_baseline else cpu_baseline(w)
     out = {
         "metric": "depth Mrays/s at 4096 envs x 2 cams 64x48 (plain batched renderer)",
@@ -172,9 +286,9 @@ def main():
                                f"20x20-tile terrain ({w['terrain'].shape[0]} tris), "
                                "per-step pose rebuild + noise/dropout/latency",
                    "rays_per_step": rays, "wall_s": round(wall, 3),
-                   "render_ms_median": round(statistics.median(render_ms), 3),
-                   "exact_pass_rays_last_step": exact_rays},
-        "roofline": roof, "cpu_baseline": cpu,
+                   "fast_pass_ms_median": round(statistics.median(fast_ms), 4),
+                   "exact_pass_rays_last_step": exact_rays, "schedule": tuned},
+        "roofline": roof, "cpu_baseline": cpu, "batched": batched,
     }
     print(json.dumps(out), flush=True)
 

@@ -119,6 +119,8 @@ typedef struct {
     float* depth;           /* device out [n_env][n_cam][height][width] (m) */
     int32_t* inst;          /* device out, same shape, or NULL */
     int32_t* tri;           /* device out, same shape, or NULL */
+    void* const* timing;    /* NULL, or host array of two hipEvent_t recorded on the
+                               stream just before and after the fast-pass kernel */
 } rc_render_args;
 
 /* Workspace bytes of rc_render for n_env x n_cam images of width x height:
@@ -177,6 +179,7 @@ typedef struct {
     float* depth;              /* device out [n_pixels] */
     int32_t* inst;             /* device out [n_pixels] or NULL */
     int32_t* tri;              /* device out [n_pixels] or NULL */
+    void* const* timing;       /* NULL, or two hipEvent_t around the fast-pass kernel */
 } rc_batch_args;
 
 /* Workspace bytes of rc_render_batched. */
@@ -243,6 +246,90 @@ rc_status rc_graph_capture_batched(const rc_scene* scene, const rc_batch_args* a
 /* Enqueue one replay on `stream`. */
 rc_status rc_graph_launch(rc_graph* graph, rc_stream stream);
 rc_status rc_graph_destroy(rc_graph* graph);
+
+/* ---------------------------------------------------------------------
+ * Serving: a request loop over a device-resident scene.  Requests (each its
+ * own environments, cameras and image size) wait in a FIFO queue, are
+ * admitted when a stream slot is free and the arena has room for their
+ * outputs, and are packed as they arrive into batched launches that run on
+ * several streams at once (continuous batching).  Camera uids are
+ * request-local, so a request's result does not depend on its batch.
+ * ------------------------------------------------------------------- */
+
+typedef struct rc_server rc_server;
+
+typedef struct {
+    int32_t n_streams;       /* concurrent batches (1..16) */
+    int64_t max_batch_rays;  /* cap on the rays of one batch (a single larger request still runs) */
+    int64_t out_pixels;      /* capacity of the output planes (pixels) */
+    float far_plane;
+    int32_t depth_mode;
+} rc_server_config;
+
+typedef struct {
+    int32_t n_env, n_cam, width, height;
+    const float* link_pos;   /* device [n_env][n_links][3] */
+    const float* link_quat;  /* device [n_env][n_links][4] */
+    const float* cam_pos;    /* device [n_env][n_cam][3] */
+    const float* cam_quat;   /* device [n_env][n_cam][4] */
+    const float* intr;       /* device [n_env][n_cam][4] */
+} rc_request;
+
+typedef struct {
+    int64_t id;
+    int32_t status;          /* RC_OK, or the error of the batch it ran in */
+    int32_t reserved;
+    int64_t n_pixels;        /* n_env * n_cam * height * width */
+    const float* depth;      /* device [n_env][n_cam][height][width], valid until released */
+    const int32_t* inst;
+    const int32_t* tri;
+    double arrival_s, launch_s, done_s;  /* caller clock; done = first poll that saw it finish */
+} rc_result;
+
+typedef struct {
+    int64_t submitted, completed, rejected, queued, in_flight;
+    int64_t batches, rays_completed;
+    double p50_s, p99_s, mean_s, max_s;  /* arrival -> observed completion */
+    double first_arrival_s, last_done_s;
+} rc_server_stats;
+
+/* Arena bytes a server with this configuration needs: three output planes
+ * of out_pixels (depth, inst, tri) plus `scratch_bytes` for per-batch poses,
+ * camera tables and render workspaces. */
+rc_status rc_server_arena_size(const rc_server_config* cfg, size_t scratch_bytes, size_t* bytes);
+
+/* Create a server over `scene` using the caller's device arena (256-byte
+ * aligned).  It creates cfg->n_streams HIP streams of default priority and
+ * allocates no device memory. */
+rc_status rc_server_create(const rc_scene* scene, const rc_server_config* cfg, void* arena,
+                           size_t arena_bytes, rc_server** out);
+
+/* A server whose batches run on a model instead of the GPU: a batch started
+ * at t finishes at t + launch_s + rays * s_per_ray.  Same queueing,
+ * admission and batching; no device is touched.  For tests of the scheduler. */
+rc_status rc_server_create_simulated(const rc_server_config* cfg, size_t arena_bytes,
+                                     double launch_s, double s_per_ray, rc_server** out);
+
+/* Queue a request that arrived at now_s (caller clock, seconds).  Device
+ * pointers must stay valid until the request's result is released.  Errors:
+ * INVALID_ARG, WORKSPACE (the request can never fit the arena). */
+rc_status rc_server_submit(rc_server* srv, const rc_request* req, double now_s, int64_t* id);
+
+/* Advance the server at time now_s: collect finished batches (non-blocking
+ * event queries), then start new batches on free streams from the queue
+ * head while memory allows.  *n_done = results now waiting to be taken. */
+rc_status rc_server_poll(rc_server* srv, double now_s, int32_t* n_done);
+
+/* Take the oldest finished result (RC_ERR_STATE if none is waiting). */
+rc_status rc_server_next_result(rc_server* srv, rc_result* out);
+
+/* Return a taken result's output memory to the arena. */
+rc_status rc_server_release(rc_server* srv, int64_t id);
+
+rc_status rc_server_stats_get(const rc_server* srv, rc_server_stats* out);
+
+/* Wait for all batches in flight (GPU servers), then free the handle. */
+rc_status rc_server_destroy(rc_server* srv);
 
 /* ---------------------------------------------------------------------
  * Sensor model: latency, noise, dropout (Sec. 1, Sec. 4.1, Table 6).

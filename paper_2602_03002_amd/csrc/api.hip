@@ -251,7 +251,8 @@ struct RenderWs {
     int64_t cap;
 };
 
-static RenderWs render_layout(int64_t n_env, int64_t n_pixels, int32_t n_links, int64_t n_desc) {
+static RenderWs render_layout(int64_t n_env, int64_t n_pixels, int32_t n_links, int64_t n_desc,
+                              int64_t cap_rays = -1) {
     RenderWs L;
     size_t o = 0;
     if (n_links > 0) {
@@ -266,7 +267,8 @@ static RenderWs render_layout(int64_t n_env, int64_t n_pixels, int32_t n_links, 
     o = align_up(o + 4);
     // a bounded list (a pixel in 16 typically suffices by far); on overflow the
     // exact pass re-casts every pixel
-    L.cap = n_pixels / 16 > 4096 ? n_pixels / 16 : 4096;
+    const int64_t basis = cap_rays >= 0 ? cap_rays : n_pixels;
+    L.cap = basis / 16 > 4096 ? basis / 16 : 4096;
     L.list = o;
     o = align_up(o + (size_t)L.cap * 16);
     L.tiles = o;
@@ -349,6 +351,8 @@ static rc_status prep_plain(const rc_scene* scene, const rc_render_args* a, void
     L.exact_count = (uint32_t*)((char*)ws + W.count);
     L.exact_list = (uint4*)((char*)ws + W.list);
     L.exact_cap = W.cap;
+    L.ev_begin = a->timing ? (hipEvent_t)a->timing[0] : nullptr;
+    L.ev_end = a->timing ? (hipEvent_t)a->timing[1] : nullptr;
     L.desc = nullptr;
     L.n_desc = 0;
     L.max_width = a->width;
@@ -410,7 +414,8 @@ static int persistent_blocks(const RenderCfg& cfg) {
 }
 
 static rc_status prep_batched(const rc_scene* scene, const rc_batch_args* a, void* ws,
-                              size_t ws_bytes, RenderLaunch& L, RenderWs& W, const char* who) {
+                              size_t ws_bytes, RenderLaunch& L, RenderWs& W, const char* who,
+                              int64_t cap_rays = -1) {
     const std::string w(who);
     if (!scene || !a) return fail(RC_ERR_INVALID_ARG, w + ": NULL scene or args");
     if (!scene->ws) return fail(RC_ERR_STATE, w + ": scene has no terrain");
@@ -426,7 +431,7 @@ static rc_status prep_batched(const rc_scene* scene, const rc_batch_args* a, voi
         return fail(RC_ERR_INVALID_ARG, w + ": far_plane must be finite and > 0");
     if (a->depth_mode != RC_DEPTH_PLANAR && a->depth_mode != RC_DEPTH_RANGE)
         return fail(RC_ERR_INVALID_ARG, w + ": unknown depth_mode");
-    W = render_layout(a->n_env, a->n_pixels, scene->n_links, a->n_desc);
+    W = render_layout(a->n_env, a->n_pixels, scene->n_links, a->n_desc, cap_rays);
     if (!ws || ws_bytes < W.end || !aligned(ws))
         return fail(RC_ERR_WORKSPACE, w + ": workspace needs " + std::to_string(W.end) +
                                           " bytes, 256-byte aligned");
@@ -447,6 +452,8 @@ static rc_status prep_batched(const rc_scene* scene, const rc_batch_args* a, voi
     L.exact_count = (uint32_t*)((char*)ws + W.count);
     L.exact_list = (uint4*)((char*)ws + W.list);
     L.exact_cap = W.cap;
+    L.ev_begin = a->timing ? (hipEvent_t)a->timing[0] : nullptr;
+    L.ev_end = a->timing ? (hipEvent_t)a->timing[1] : nullptr;
     L.desc = a->desc;
     L.n_desc = a->n_desc;
     L.max_width = a->max_width;
@@ -539,6 +546,7 @@ rc_status rc_autotune(rc_scene* scene, const rc_render_args* plain, const rc_bat
     rc_status st = plain ? prep_plain(scene, plain, ws, ws_bytes, L, "rc_autotune")
                          : prep_batched(scene, batched, ws, ws_bytes, L, W, "rc_autotune");
     if (st != RC_OK) return st;
+    L.ev_begin = L.ev_end = nullptr;
     hipStream_t s = (hipStream_t)stream;
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
@@ -585,6 +593,7 @@ rc_status rc_graph_capture_batched(const rc_scene* scene, const rc_batch_args* a
     RenderWs W;
     rc_status st = prep_batched(scene, a, ws, ws_bytes, L, W, "rc_graph_capture_batched");
     if (st != RC_OK) return st;
+    L.ev_begin = L.ev_end = nullptr;
     hipStream_t s = (hipStream_t)stream;
     hipStreamCaptureStatus cs;
     if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
@@ -835,3 +844,29 @@ rc_status rc_bvh_layout_of(const rc_scene* scene, int32_t which, rc_bvh_layout* 
 }
 
 }  // extern "C"
+
+// Helpers for the serving loop (C++ linkage, used by server.hip).
+
+namespace rc {
+
+size_t batched_ws_bytes(const rc_scene* scene, int64_t n_env, int64_t n_desc, int64_t cap_rays) {
+    return render_layout(n_env, 1, scene->n_links, n_desc, cap_rays).end;
+}
+
+rc_status enqueue_batched(const rc_scene* scene, const rc_batch_args* a, int64_t cap_rays, void* ws,
+                          size_t ws_bytes, hipStream_t s) {
+    RenderLaunch L;
+    RenderWs W;
+    rc_status st = prep_batched(scene, a, ws, ws_bytes, L, W, "serving batch", cap_rays);
+    if (st != RC_OK) return st;
+    L.ev_begin = L.ev_end = nullptr;
+    hipError_t e = run_batched(scene, L, ws, W, scene->cfg_batched, s);
+    if (e != hipSuccess) return hip_fail(e, "serving batch: launch");
+    return RC_OK;
+}
+
+int scene_links(const rc_scene* scene) { return scene->n_links; }
+bool scene_ready(const rc_scene* scene) { return scene && scene->ws; }
+
+}  // namespace rc
+

@@ -718,6 +718,7 @@ hipError_t launch_render(const RenderLaunch& a, const RenderCfg& cfg, hipStream_
     const int64_t per_xcd = (n_logical + 7) / 8;
     const dim3 grid((unsigned)(per_xcd * 8)), block(64 * kWavesPerBlock);
     hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(1), 0, s, a.exact_count);
+    if (a.ev_begin) hipEventRecord(a.ev_begin, s);
 #define RC_PLAIN(W, R) hipLaunchKernelGGL((k_render<W, R>), grid, block, 0, s, a, c, n_logical, per_xcd)
     const int v = 10 * cfg.waves + c.rpl;
     switch (v) {
@@ -729,6 +730,7 @@ hipError_t launch_render(const RenderLaunch& a, const RenderCfg& cfg, hipStream_
         default: RC_PLAIN(6, 1); break;
     }
 #undef RC_PLAIN
+    if (a.ev_end) hipEventRecord(a.ev_end, s);
     hipLaunchKernelGGL(k_render_exact, dim3(4096), dim3(64), 0, s, a, (const uint32_t*)nullptr);
     return hipGetLastError();
 }
@@ -738,6 +740,7 @@ hipError_t launch_render_batched(const RenderLaunch& a, const RenderCfg& cfg, ui
                                  hipStream_t s) {
     TileCfg c{cfg.tile_w, cfg.tile_h, cfg.rays_per_lane};
     hipLaunchKernelGGL(k_batch_prep, dim3(1), dim3(1024), 0, s, a, c, tile_start, queues, status);
+    if (a.ev_begin) hipEventRecord(a.ev_begin, s);
     const dim3 block(64 * kWavesPerBlock);
     const int v = 10 * cfg.waves + c.rpl;
     if (cfg.persistent) {
@@ -773,6 +776,7 @@ hipError_t launch_render_batched(const RenderLaunch& a, const RenderCfg& cfg, ui
         }
 #undef RC_FLAT
     }
+    if (a.ev_end) hipEventRecord(a.ev_end, s);
     hipLaunchKernelGGL(k_render_exact, dim3(4096), dim3(64), 0, s, a, (const uint32_t*)tile_start);
     return hipGetLastError();
 }

@@ -94,6 +94,7 @@ struct RenderLaunch {
     const rc_cam_desc* desc;  // batched form: camera descriptors (NULL: plain layout)
     int n_desc;
     int max_width, max_height;  // batched form: largest image a descriptor may have
+    hipEvent_t ev_begin, ev_end;  // optional events around the fast-pass kernel
     int64_t n_pixels;         // output pixels
     int n_env, n_cam, width, height, n_links, depth_mode, n_terrain;
     float far_plane;
@@ -133,5 +134,13 @@ hipError_t launch_post_batched(const PostLaunch& a, const rc_cam_desc* desc, int
                                hipStream_t s);
 
 void set_error(const std::string& msg);
+
+// Serving-loop helpers (api.hip): workspace bytes of a batched render whose
+// exact-pass list is sized for cap_rays rays, and its enqueue.
+size_t batched_ws_bytes(const rc_scene* scene, int64_t n_env, int64_t n_desc, int64_t cap_rays);
+rc_status enqueue_batched(const rc_scene* scene, const rc_batch_args* a, int64_t cap_rays, void* ws,
+                          size_t ws_bytes, hipStream_t s);
+int scene_links(const rc_scene* scene);
+bool scene_ready(const rc_scene* scene);
 
 }  // namespace rc

@@ -27,6 +27,9 @@ EXPORTED = [
     "rc_get_render_config", "rc_set_render_config", "rc_autotune",
     "rc_graph_capture_batched", "rc_graph_launch", "rc_graph_destroy",
     "rc_post_size_packed", "rc_post_create_packed", "rc_postprocess_batched",
+    "rc_server_arena_size", "rc_server_create", "rc_server_create_simulated", "rc_server_submit",
+    "rc_server_poll", "rc_server_next_result", "rc_server_release", "rc_server_stats_get",
+    "rc_server_destroy",
 ]
 
 import numpy as np  # noqa: E402
@@ -50,7 +53,8 @@ class RenderArgs(ctypes.Structure):
                 ("cam_pos", ctypes.c_void_p), ("cam_quat", ctypes.c_void_p),
                 ("intr", ctypes.c_void_p), ("far_plane", ctypes.c_float),
                 ("depth_mode", ctypes.c_int32), ("depth", ctypes.c_void_p),
-                ("inst", ctypes.c_void_p), ("tri", ctypes.c_void_p)]
+                ("inst", ctypes.c_void_p), ("tri", ctypes.c_void_p),
+                ("timing", ctypes.c_void_p)]
 
 
 class PostParams(ctypes.Structure):
@@ -67,7 +71,8 @@ class BatchArgs(ctypes.Structure):
                 ("desc", ctypes.c_void_p), ("n_pixels", ctypes.c_int64),
                 ("max_width", ctypes.c_int32), ("max_height", ctypes.c_int32),
                 ("far_plane", ctypes.c_float), ("depth_mode", ctypes.c_int32),
-                ("depth", ctypes.c_void_p), ("inst", ctypes.c_void_p), ("tri", ctypes.c_void_p)]
+                ("depth", ctypes.c_void_p), ("inst", ctypes.c_void_p), ("tri", ctypes.c_void_p),
+                ("timing", ctypes.c_void_p)]
 
 
 class RenderConfig(ctypes.Structure):
@@ -77,6 +82,33 @@ class RenderConfig(ctypes.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("n_streams", ctypes.c_int32), ("max_batch_rays", ctypes.c_int64),
+                ("out_pixels", ctypes.c_int64), ("far_plane", ctypes.c_float),
+                ("depth_mode", ctypes.c_int32)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("n_env", ctypes.c_int32), ("n_cam", ctypes.c_int32), ("width", ctypes.c_int32),
+                ("height", ctypes.c_int32), ("link_pos", ctypes.c_void_p),
+                ("link_quat", ctypes.c_void_p), ("cam_pos", ctypes.c_void_p),
+                ("cam_quat", ctypes.c_void_p), ("intr", ctypes.c_void_p)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_int64), ("status", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("n_pixels", ctypes.c_int64), ("depth", ctypes.c_void_p), ("inst", ctypes.c_void_p),
+                ("tri", ctypes.c_void_p), ("arrival_s", ctypes.c_double),
+                ("launch_s", ctypes.c_double), ("done_s", ctypes.c_double)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in ("submitted", "completed", "rejected", "queued",
+                                               "in_flight", "batches", "rays_completed")] + \
+               [(k, ctypes.c_double) for k in ("p50_s", "p99_s", "mean_s", "max_s",
+                                                "first_arrival_s", "last_done_s")]
 
 
 class BvhLayout(ctypes.Structure):
@@ -132,6 +164,17 @@ def lib():
         L.rc_post_create_packed.argtypes = [i64, i32, vp, sz, ctypes.POINTER(vp)]
         L.rc_postprocess_batched.argtypes = [vp, vp, vp, ctypes.POINTER(PostParams), ctypes.c_uint64,
                                              vp, i32, vp, vp, vp, vp]
+        L.rc_server_arena_size.argtypes = [ctypes.POINTER(ServerConfig), sz, ctypes.POINTER(sz)]
+        L.rc_server_create.argtypes = [vp, ctypes.POINTER(ServerConfig), vp, sz, ctypes.POINTER(vp)]
+        L.rc_server_create_simulated.argtypes = [ctypes.POINTER(ServerConfig), sz, ctypes.c_double,
+                                                 ctypes.c_double, ctypes.POINTER(vp)]
+        L.rc_server_submit.argtypes = [vp, ctypes.POINTER(Request), ctypes.c_double,
+                                       ctypes.POINTER(i64)]
+        L.rc_server_poll.argtypes = [vp, ctypes.c_double, ctypes.POINTER(i32)]
+        L.rc_server_next_result.argtypes = [vp, ctypes.POINTER(Result)]
+        L.rc_server_release.argtypes = [vp, i64]
+        L.rc_server_stats_get.argtypes = [vp, ctypes.POINTER(ServerStats)]
+        L.rc_server_destroy.argtypes = [vp]
         for name in EXPORTED:
             if name not in ("rc_version", "rc_status_string", "rc_last_error"):
                 getattr(L, name).restype = i32
@@ -151,6 +194,18 @@ def _ptr(t):
 def _stream(stream=None):
     s = stream if stream is not None else torch.cuda.current_stream()
     return ctypes.c_void_p(s.cuda_stream)
+
+
+def _events(timing):
+    """Host array of the two raw hipEvent_t handles of a pair of torch events."""
+    if timing is None:
+        return None
+    handles = []
+    for ev in timing:
+        if ev.cuda_event == 0:  # torch creates the event on its first record
+            ev.record()
+        handles.append(ev.cuda_event)
+    return (ctypes.c_void_p * 2)(*handles)
 
 
 def _dev_f32(t, shape, name):
@@ -231,7 +286,7 @@ class Scene:
         return c.value
 
     def _plain_args(self, cam_pos, cam_quat, intr, width, height, far_plane, link_pos, link_quat,
-                    depth_mode, out, ids):
+                    depth_mode, out, ids, timing=None):
         E, C = cam_pos.shape[0], cam_pos.shape[1]
         _dev_f32(cam_pos, (E, C, 3), "cam_pos")
         _dev_f32(cam_quat, (E, C, 4), "cam_quat")
@@ -245,16 +300,22 @@ class Scene:
             tri = torch.empty_like(depth, dtype=torch.int32) if ids else None
         else:
             depth, inst, tri = out
+        ev = _events(timing)
         a = RenderArgs(E, C, width, height, _ptr(link_pos) if self.n_links else None,
                        _ptr(link_quat) if self.n_links else None, _ptr(cam_pos), _ptr(cam_quat),
-                       _ptr(intr), float(far_plane), depth_mode, _ptr(depth), _ptr(inst), _ptr(tri))
+                       _ptr(intr), float(far_plane), depth_mode, _ptr(depth), _ptr(inst), _ptr(tri),
+                       ctypes.cast(ev, ctypes.c_void_p) if ev is not None else None)
+        a._ev = ev  # keep the event array alive with the argument block
         return a, (depth, inst, tri), self.render_workspace(E, C, width, height)
 
     def render(self, cam_pos, cam_quat, intr, width, height, far_plane, link_pos=None,
-               link_quat=None, depth_mode=RC_DEPTH_PLANAR, out=None, ids=True, stream=None):
-        """Returns (depth [E,C,H,W] f32, inst i32 or None, tri i32 or None)."""
+               link_quat=None, depth_mode=RC_DEPTH_PLANAR, out=None, ids=True, stream=None,
+               timing=None):
+        """Returns (depth [E,C,H,W] f32, inst i32 or None, tri i32 or None).
+        timing: optional pair of recorded torch.cuda.Event(enable_timing=True) placed
+        around the fast-pass kernel."""
         a, outs, ws = self._plain_args(cam_pos, cam_quat, intr, width, height, far_plane, link_pos,
-                                       link_quat, depth_mode, out, ids)
+                                       link_quat, depth_mode, out, ids, timing)
         check(lib().rc_render(self.handle, ctypes.byref(a), ctypes.c_void_p(ws.ptr), ws.nbytes,
                               _stream(stream)))
         return outs
@@ -281,7 +342,7 @@ class Scene:
         a = BatchArgs(E, n_desc, _ptr(link_pos) if self.n_links else None,
                       _ptr(link_quat) if self.n_links else None, _ptr(desc), int(n_pixels),
                       int(max_width), int(max_height), float(far_plane), depth_mode, _ptr(depth),
-                      _ptr(inst), _ptr(tri))
+                      _ptr(inst), _ptr(tri), None)
         key = ("batch", E, n_desc, int(n_pixels))
         ws = self._render_ws.get(key)
         if ws is None:
@@ -455,6 +516,89 @@ class Post:
     def close(self):
         if self.handle:
             lib().rc_post_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Serving loop over a resident scene (or, with simulated(), over a timing model).
+
+    submit() queues a request at the caller's clock time; poll() collects finished
+    batches and starts new ones; next_result() hands back finished requests whose
+    outputs stay valid until release()."""
+
+    def __init__(self, scene, n_streams=4, max_batch_rays=1 << 24, out_pixels=1 << 26,
+                 scratch_bytes=1 << 30, far_plane=3.0, depth_mode=RC_DEPTH_PLANAR, _sim=None):
+        L = lib()
+        self.cfg = ServerConfig(n_streams, int(max_batch_rays), int(out_pixels), float(far_plane),
+                                depth_mode)
+        size = ctypes.c_size_t()
+        check(L.rc_server_arena_size(ctypes.byref(self.cfg), int(scratch_bytes), ctypes.byref(size)))
+        h = ctypes.c_void_p()
+        self.arena = None
+        if _sim is None:
+            self.arena = Workspace(size.value, scene.device)
+            check(L.rc_server_create(scene.handle, ctypes.byref(self.cfg),
+                                     ctypes.c_void_p(self.arena.ptr), size.value, ctypes.byref(h)))
+        else:
+            check(L.rc_server_create_simulated(ctypes.byref(self.cfg), size.value, _sim[0], _sim[1],
+                                               ctypes.byref(h)))
+        self.handle = h
+        self.scene = scene
+        self._inputs = {}
+
+    @classmethod
+    def simulated(cls, launch_s, s_per_ray, **kw):
+        return cls(None, _sim=(float(launch_s), float(s_per_ray)), **kw)
+
+    def submit(self, now, n_env, n_cam, width, height, link_pos=None, link_quat=None,
+               cam_pos=None, cam_quat=None, intr=None):
+        r = Request(n_env, n_cam, width, height, _ptr(link_pos), _ptr(link_quat), _ptr(cam_pos),
+                    _ptr(cam_quat), _ptr(intr))
+        i = ctypes.c_int64()
+        check(lib().rc_server_submit(self.handle, ctypes.byref(r), float(now), ctypes.byref(i)))
+        self._inputs[i.value] = (link_pos, link_quat, cam_pos, cam_quat, intr)
+        return i.value
+
+    def poll(self, now):
+        n = ctypes.c_int32()
+        check(lib().rc_server_poll(self.handle, float(now), ctypes.byref(n)))
+        return n.value
+
+    def next_result(self):
+        r = Result()
+        if lib().rc_server_next_result(self.handle, ctypes.byref(r)) != RC_OK:
+            return None
+        return {k: getattr(r, k) for k, _ in Result._fields_}
+
+    def outputs(self, res, shape):
+        """(depth, inst, tri) tensor views of a result inside the arena."""
+        n = res["n_pixels"]
+        base = self.arena.ptr
+        views = []
+        for key, dt in (("depth", torch.float32), ("inst", torch.int32), ("tri", torch.int32)):
+            off = res[key] - base
+            views.append(self.arena.buf[self.arena.offset + off:self.arena.offset + off + 4 * n]
+                         .view(dt).view(shape))
+        return tuple(views)
+
+    def release(self, rid):
+        check(lib().rc_server_release(self.handle, int(rid)))
+        self._inputs.pop(rid, None)
+
+    def stats(self):
+        st = ServerStats()
+        check(lib().rc_server_stats_get(self.handle, ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in ServerStats._fields_}
+
+    def close(self):
+        if self.handle:
+            lib().rc_server_destroy(self.handle)
             self.handle = None
 
     def __del__(self):
