@@ -167,6 +167,100 @@ def bench_batched(sc, steps, warmup):
             "speedup_vs_plain_grouped": round(ms_p / ms_b, 3)}
 
 
+def bench_serving(sc, w_main, capacity_mrays, duration_s=6.0):
+    """Poisson request stream over the resident scene: requests of 16-1024 envs
+    (log-uniform), 1-4 cameras and sizes from 32x24..106x60; p50/p99 latency
+    from scheduled arrival to observed completion, served vs offered rays."""
+    import math
+    import numpy as np
+    import torch
+    import scenegen as sg
+    import paper_2602_03002_amd as rc
+    print("[bench] serving", file=sys.stderr, flush=True)
+    w = sg.robot_scene(20, 64, 2.5, 4, 64, 48, steps=1, label="serve4096",
+                       terrain=w_main["terrain_obj"], robot=w_main["robot"])
+    E = w["E"]
+    dev = "cuda"
+
+    def t(a):
+        return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+    lp, lq = t(w["link_pos"][0]), t(w["link_quat"][0])
+    cams = {k: (t(w["cam_pos"][:, :k]), t(w["cam_quat"][:, :k])) for k in range(1, 5)}
+    intr = {(res, k): t(np.broadcast_to(sg.intrinsics_from_fov(res[0], res[1], 87.0, 58.0),
+                                         (E, k, 4)).astype(np.float32))
+            for res in sg.RES_SET for k in range(1, 5)}
+    rng = np.random.default_rng(2000)
+
+    def draw():
+        n = int(math.exp(rng.uniform(math.log(16), math.log(1025))))
+        n = min(max(n, 16), 1024)
+        k = int(rng.integers(1, 5))
+        res = sg.RES_SET[int(rng.integers(0, 4))]
+        e0 = int(rng.integers(0, E - n + 1))
+        return n, k, res, e0
+
+    sample = [draw() for _ in range(20000)]
+    mean_rays = float(np.mean([n * k * r[0] * r[1] for n, k, r, _ in sample]))
+
+    def run(rate, seconds, n_streams=4, max_batch_rays=1 << 24):
+        srv = rc.Server(sc, n_streams=n_streams, max_batch_rays=max_batch_rays,
+                        out_pixels=1 << 26, scratch_bytes=1 << 30, far_plane=w["far"])
+        arrivals = np.cumsum(rng.exponential(1.0 / rate, int(rate * seconds * 1.5) + 16))
+        arrivals = arrivals[arrivals < seconds]
+        i = 0
+        submitted_rays = 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        deadline = seconds + 30.0
+        while True:
+            now = time.perf_counter() - t0
+            while i < len(arrivals) and arrivals[i] <= now:
+                n, k, res, e0 = draw()
+                srv.submit(arrivals[i], n, k, res[0], res[1], lp[e0:e0 + n], lq[e0:e0 + n],
+                           cams[k][0][e0:e0 + n], cams[k][1][e0:e0 + n], intr[(res, k)][e0:e0 + n])
+                submitted_rays += n * k * res[0] * res[1]
+                i += 1
+            srv.poll(now)
+            while True:
+                r = srv.next_result()
+                if r is None:
+                    break
+                srv.release(r["id"])
+            st = srv.stats()
+            if (i >= len(arrivals) and st["completed"] + st["rejected"] >= len(arrivals)) or now > deadline:
+                break
+        st = srv.stats()
+        srv.close()
+        span = max(st["last_done_s"] - st["first_arrival_s"], 1e-9)
+        return {"offered_req_per_s": round(rate, 1), "seconds": seconds,
+                "requests": int(st["submitted"]), "completed": int(st["completed"]),
+                "batches": int(st["batches"]),
+                "offered_mrays_s": round(submitted_rays / seconds / 1e6, 1),
+                "served_mrays_s": round(st["rays_completed"] / span / 1e6, 1),
+                "p50_ms": round(st["p50_s"] * 1e3, 3), "p99_ms": round(st["p99_s"] * 1e3, 3),
+                "mean_ms": round(st["mean_s"] * 1e3, 3), "streams": n_streams,
+                "max_batch_rays": max_batch_rays}
+
+    cap_rps = capacity_mrays * 1e6 / mean_rays
+    runs = []
+    for frac in (0.5, 0.8):
+        r = run(frac * cap_rps, duration_s)
+        r["load"] = f"{int(frac * 100)}% of the plain renderer's measured capacity"
+        runs.append(r)
+        print(f"[bench] serving {r}", file=sys.stderr, flush=True)
+    lit = run(2000.0, duration_s / 2)
+    lit["load"] = "2000 req/s (the stated stream)"
+    runs.append(lit)
+    print(f"[bench] serving {lit}", file=sys.stderr, flush=True)
+    base = run(2000.0, duration_s / 2, n_streams=1, max_batch_rays=1)
+    base["load"] = "2000 req/s, one request per launch on one stream (plain per-request)"
+    print(f"[bench] serving {base}", file=sys.stderr, flush=True)
+    return {"mean_rays_per_request": round(mean_rays), "runs": runs, "plain_per_request": base,
+            "speedup_served_vs_plain_per_request": round(lit["served_mrays_s"] /
+                                                         max(base["served_mrays_s"], 1e-9), 3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -178,6 +272,8 @@ def main():
                     help="run one plain device copy of this size first (HBM counter calibration)")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the uneven batched section")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving section")
+    ap.add_argument("--serve-seconds", type=float, default=6.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding "
@@ -276,9 +372,10 @@ def main():
                 "kernel_ms": round(r_ms, 4)}
 
     batched = None if args.no_batched else bench_batched(sc, args.steps, args.warmup)
+    serving = None if args.no_serving else bench_serving(sc, w, value, args.serve_seconds)
     cpu = None if args.no_cpu_baseline else cpu_baseline(w)
     out = {
-        "metric": "depth Mrays/s at 4096 envs x 2 cams 64x48 (plain batched renderer)",
+        "metric": "depth Mrays/s at 4096 envs x 2 cams 64x48 vs plain; p50/p99 request latency",
         "value": round(value, 1), "unit": "Mrays/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
@@ -288,7 +385,7 @@ def main():
                    "rays_per_step": rays, "wall_s": round(wall, 3),
                    "fast_pass_ms_median": round(statistics.median(fast_ms), 4),
                    "exact_pass_rays_last_step": exact_rays, "schedule": tuned},
-        "roofline": roof, "cpu_baseline": cpu, "batched": batched,
+        "roofline": roof, "cpu_baseline": cpu, "batched": batched, "serving": serving,
     }
     print(json.dumps(out), flush=True)
 
