@@ -8,6 +8,7 @@ timed region.  Prints one JSON line.
 """
 import argparse
 import json
+import math
 import os
 import statistics
 import sys
@@ -61,13 +62,13 @@ def measured_traffic():
     return int(float(kv["traffic_bytes_per_launch"]))
 
 
-def cpu_baseline(w, budget_s=15.0, seed=5):
-    """The FP64 oracle timed on host cores over a bounded ray sample of step 0."""
+def _oracle_rate(w, budget_s, seed):
+    """Rays per second of the oracle over growing random ray samples of step 0."""
     import numpy as np
     import oracle
     total = w["E"] * w["C"] * w["H"] * w["W"]
     rng = np.random.default_rng(seed)
-    n = 64
+    n = 16
     elapsed = 0.0
     done = 0
     while True:
@@ -76,12 +77,27 @@ def cpu_baseline(w, budget_s=15.0, seed=5):
         oracle.render(w["terrain"], w["link_tri"], w["link_off"], w["link_pos"][0],
                       w["link_quat"][0], w["cam_pos"], w["cam_quat"], w["intr"], w["W"], w["H"],
                       w["far"], rays=rays)
-        dt = time.perf_counter() - t0
-        elapsed += dt
+        elapsed += time.perf_counter() - t0
         done += n
         if elapsed > budget_s / 3:
-            break
+            return done, elapsed
         n *= 2
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(w, budget_s=15.0, seed=5):
+    """The FP64 oracle timed on the host's cores over a bounded ray sample of
+    step 0, then on one core."""
+    import oracle
     cores = os.cpu_count()
     try:
         cores = len(os.sched_getaffinity(0))
@@ -89,9 +105,65 @@ def cpu_baseline(w, budget_s=15.0, seed=5):
         pass
     omp = os.environ.get("OMP_NUM_THREADS")
     threads = min(int(omp), cores) if omp and omp.isdigit() else cores
+    oracle.set_threads(threads)
+    done, elapsed = _oracle_rate(w, budget_s, seed)
+    oracle.set_threads(1)
+    done1, elapsed1 = _oracle_rate(w, budget_s / 3, seed + 1)
+    oracle.set_threads(threads)
     return {"value": done / elapsed / 1e6, "unit": "Mrays/s", "cores": threads, "kind": "oracle",
             "sample": f"{done} random pixel rays of step 0 (all {w['terrain'].shape[0]} terrain "
-                      f"+ {w['link_tri'].shape[0]} link triangles each, FP64 brute force + band flags)"}
+                      f"+ {w['link_tri'].shape[0]} link triangles each, FP64 brute force + band flags)",
+            "single_core_value": done1 / elapsed1 / 1e6, "single_core_sample": f"{done1} rays",
+            "cpu_model": _cpu_model(),
+            "full_step_s_extrapolated": round(w["E"] * w["C"] * w["H"] * w["W"] / (done / elapsed), 1)}
+
+
+def traversal_report(sc, kw, ref):
+    """The GPU's own per-ray work on step 0 (rc_render_counts) and the
+    surface-area cost of its terrain hierarchy, beside the reference's."""
+    import torch
+    _, counts = sc.render_counts(**kw)
+    c = counts.view(-1, 4)[:, :3].double().mean(0).tolist()
+    lay = sc.bvh_layout(-1)
+    m = int(lay.n_nodes)
+    rec = sc.ws.view()[lay.node_offset:lay.node_offset + 64 * m].view(torch.float32).view(m, 16)
+    b = rec[:, :12].double().view(m, 2, 6)
+    ext = (b[..., 1::2] - b[..., 0::2]).clamp(min=0)
+    area = 2 * (ext[..., 0] * ext[..., 1] + ext[..., 1] * ext[..., 2] + ext[..., 2] * ext[..., 0])
+    e = torch.maximum(b[0, 0, 1::2], b[0, 1, 1::2]) - torch.minimum(b[0, 0, 0::2], b[0, 1, 0::2])
+    a_root = 2 * (e[0] * e[1] + e[1] * e[2] + e[2] * e[0])
+    # one triangle per leaf and C_trav = C_tri = 1: every child box weighs 1
+    sah = float((a_root + area.sum()) / a_root)
+    del counts, rec, b, ext, area
+    own = {"node": round(c[0], 3), "tri": round(c[1], 3), "inst": round(c[2], 3)}
+    own["bytes_per_ray"] = round(12 + 56 * c[0] + 36 * c[1] + 28 * c[2], 1)
+    out = {"own": own, "sah_cost_terrain_own": round(sah, 3)}
+    if ref is not None:
+        rc_ = ref["mean_counts"]
+        out["reference"] = {k: round(v, 3) for k, v in rc_.items()}
+        if "sah_cost_terrain" in ref:
+            out["sah_cost_terrain_reference"] = round(ref["sah_cost_terrain"], 3)
+            out["sah_cost_ratio"] = round(sah / ref["sah_cost_terrain"], 4)
+    return out
+
+
+def copy_bandwidth(mib=2048, reps=5):
+    """Achievable HBM bandwidth of a plain device copy (read + write bytes / time)."""
+    import torch
+    n = (mib << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    b.record()
+    torch.cuda.synchronize()
+    gbs = 2 * 4 * n * reps / (a.elapsed_time(b) / 1e3) / 1e9
+    del src, dst
+    return gbs
 
 
 def bench_batched(sc, steps, warmup):
@@ -341,27 +413,30 @@ def main():
 
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
            for _ in range(args.steps)]
+    marks = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     for a_, b_ in evs:  # create the events before the timed region
         a_.record(stream)
         b_.record(stream)
-    t_start = torch.cuda.Event(enable_timing=True)
-    t_end = torch.cuda.Event(enable_timing=True)
+    for m_ in marks:
+        m_.record(stream)
     torch.cuda.synchronize()
     w0 = time.perf_counter()
-    t_start.record(stream)
+    marks[0].record(stream)
     for k in range(args.steps):
         step(args.warmup + k, evs[k])
-    t_end.record(stream)
+        marks[k + 1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
-    gpu_ms = t_start.elapsed_time(t_end)
+    gpu_ms = marks[0].elapsed_time(marks[-1])
     ms_per_step = gpu_ms / args.steps
+    step_ms = sorted(marks[k].elapsed_time(marks[k + 1]) for k in range(args.steps))
     fast_ms = [a.elapsed_time(b) for a, b in evs]
     rays = E * C * H * W
     value = rays * args.steps / (gpu_ms / 1e3) / 1e6
 
     exact_rays = sc.exact_count(E, C, W, H)
     bpr, ref = bytes_per_ray()
+    copy_gbs = copy_bandwidth()
     roof = None
     if bpr is not None:
         r_ms = statistics.mean(fast_ms)
@@ -369,7 +444,19 @@ def main():
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
                 "kernel": "k_render (fast pass)", "bytes_per_ray": round(bpr, 1),
-                "kernel_ms": round(r_ms, 4)}
+                "kernel_ms": round(r_ms, 4), "copy_gbs": round(copy_gbs, 1),
+                "frac_of_copy": round(achieved / copy_gbs, 4)}
+    # bytes a step cannot avoid: the scene read once, top levels written and
+    # read, poses, render outputs, sensor-model traffic
+    lay = sc.bvh_layout(-1)
+    scene_bytes = 64 * lay.n_nodes + 40 * lay.n_prim + int(sc.robot_ws.nbytes if sc.robot_ws else 0)
+    tl_bytes = 2 * E * ((sc.n_links - 1) * 64 + sc.n_links * 48) + E * sc.n_links * 28
+    compulsory = scene_bytes + tl_bytes + rays * (12 + 13)
+    compulsory_frac = compulsory / (ms_per_step / 1e3) / (HBM_PEAK_GBS * 1e9)
+    trav = traversal_report(sc, dict(cam_pos=cp, cam_quat=cq, intr=K, width=W, height=H,
+                                     far_plane=w["far"], link_pos=lp_all[0], link_quat=lq_all[0]),
+                            ref)
+    print(f"[bench] traversal {trav}", file=sys.stderr, flush=True)
 
     batched = None if args.no_batched else bench_batched(sc, args.steps, args.warmup)
     serving = None if args.no_serving else bench_serving(sc, w, value, args.serve_seconds)
@@ -384,8 +471,13 @@ def main():
                                "per-step pose rebuild + noise/dropout/latency",
                    "rays_per_step": rays, "wall_s": round(wall, 3),
                    "fast_pass_ms_median": round(statistics.median(fast_ms), 4),
+                   "step_ms_median": round(statistics.median(step_ms), 4),
+                   "step_ms_p90": round(step_ms[max(0, math.ceil(0.9 * len(step_ms)) - 1)], 4),
+                   "compulsory_bytes_per_step": int(compulsory),
+                   "compulsory_frac": round(compulsory_frac, 4),
                    "exact_pass_rays_last_step": exact_rays, "schedule": tuned},
-        "roofline": roof, "cpu_baseline": cpu, "batched": batched, "serving": serving,
+        "roofline": roof, "cpu_baseline": cpu, "traversal": trav, "batched": batched,
+        "serving": serving,
     }
     print(json.dumps(out), flush=True)
 

@@ -148,6 +148,21 @@ rc_status rc_render_exact_count(const rc_scene* scene, int32_t n_env, int32_t n_
                                 int32_t width, int32_t height, const void* ws, int64_t* count,
                                 rc_stream stream);
 
+/* Diagnostic render: rc_render (same workspace, same outputs) whose fast
+ * pass also writes, per ray, the work it did as uint32 [n_env][n_cam]
+ * [height][width][4] = (node records whose child boxes the ray's lane
+ * tested, triangles tested, link instances entered, 0) into `counts`
+ * (device, 16-byte aligned, caller owned).  Node records read by a
+ * wavefront's shared top-level walk and terrain entry descent count once per
+ * lane.  The exact pass's re-casts are not counted.  The fast pass runs
+ * unrolled one tile per wavefront at 6 waves per SIMD with the scene's tile
+ * shape; it is slower than rc_render and meant for measurement of the
+ * traversal (the paper prices its kernel by the early-termination bound,
+ * Sec. 3.2.2).  Errors as rc_render, plus INVALID_ARG for a NULL or
+ * misaligned `counts`. */
+rc_status rc_render_counts(const rc_scene* scene, const rc_render_args* args, uint32_t* counts,
+                           void* ws, size_t ws_bytes, rc_stream stream);
+
 /* ---------------------------------------------------------------------
  * Batched uneven form: environments with different camera counts and image
  * sizes in one persistent launch (Algorithm 1 over a camera table; the

@@ -40,6 +40,15 @@ def lib():
     return _lib
 
 
+def set_threads(n):
+    """Host threads the oracle's parallel loops use (for timing it)."""
+    lib().oracle_set_threads(int(n))
+
+
+def get_threads():
+    return int(lib().oracle_get_threads())
+
+
 def _p(a):
     return a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
 

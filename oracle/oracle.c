@@ -37,6 +37,7 @@
  *    rounding allowance; such rays are in the EDGE band anyway).
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -224,6 +225,10 @@ static void render_ray(const scene_t* s, int64_t p, double* depth, int32_t* inst
  * cand [n][K][2] / cand_depth [n][K]: nearest candidates (any ray), -1/NaN pad.
  * Returns 0, or -1 on bad arguments.
  */
+/* Host threads of the parallel loops (timing of the oracle only). */
+void oracle_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+int oracle_get_threads(void) { return omp_get_max_threads(); }
+
 int oracle_render(const float* terrain, int64_t n_terrain,
                   const float* link_tri, const int64_t* link_off, int n_links,
                   const float* link_pos, const float* link_quat,

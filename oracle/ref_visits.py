@@ -28,6 +28,7 @@ def lib():
                            os.path.join(HERE, "refcount.c"), "-lm"])
     L = ctypes.CDLL(so)
     L.ref_counts.restype = ctypes.c_int
+    L.ref_sah_cost.restype = ctypes.c_double
     return L
 
 
@@ -48,6 +49,12 @@ def counts(w, rays):
     return out
 
 
+def sah_cost(tri):
+    """Surface-area cost of the reference hierarchy over these triangles."""
+    t = np.ascontiguousarray(tri, np.float32).reshape(-1, 9)
+    return float(lib().ref_sah_cost(t.ctypes.data_as(ctypes.c_void_p), ctypes.c_int64(t.shape[0])))
+
+
 def main():
     import scenegen as sg
     w = sg.robots_4096(steps=1)
@@ -64,6 +71,7 @@ def main():
         "mean_counts": {"node": float(m[0] + m[1]), "tri": float(m[2] + m[3]), "inst": float(m[4])},
         "split": {"robot_nodes": float(m[0]), "terrain_nodes": float(m[1]),
                   "link_tris": float(m[2]), "terrain_tris": float(m[3]), "hit_fraction": float(m[5])},
+        "sah_cost_terrain": sah_cost(w["terrain"]),
         "bytes_per_ray_formula": "12 + 13 + 56 node + 36 tri + 28 inst",
         "seconds": round(time.time() - t0, 1),
     }

@@ -248,6 +248,26 @@ static void trace(const rbvh_t* t, int kind, const float* tris, const double o[3
     }
 }
 
+/* Surface-area cost of a hierarchy (C_trav = C_tri = 1): sum over internal
+ * nodes of area / root area, plus sum over leaves of area x triangles /
+ * root area. */
+static double sah_rec(const rbvh_t* t, int ref, const box_t* b) {
+    if (ref < 0) return box_area(b) * t->leaves[~ref].count;
+    const rnode_t* N = &t->nodes[ref];
+    return box_area(b) + sah_rec(t, N->child[0], &N->b[0]) + sah_rec(t, N->child[1], &N->b[1]);
+}
+
+double ref_sah_cost(const float* tris, int64_t n) {
+    box_t* pb = (box_t*)malloc(sizeof(box_t) * (size_t)n);
+    for (int64_t i = 0; i < n; ++i) tri_box(tris + 9 * i, &pb[i]);
+    rbvh_t t;
+    rbvh_build(&t, pb, (int)n);
+    free(pb);
+    double c = sah_rec(&t, t.root_ref, &t.root) / box_area(&t.root);
+    rbvh_free(&t);
+    return c;
+}
+
 /*
  * ref_counts: per ray counts, out [n][6] = (robot nodes (top level + links),
  * terrain nodes, link triangles, terrain triangles, instances entered,

@@ -381,6 +381,19 @@ rc_status rc_render(const rc_scene* scene, const rc_render_args* a, void* ws, si
     return RC_OK;
 }
 
+rc_status rc_render_counts(const rc_scene* scene, const rc_render_args* a, uint32_t* counts,
+                           void* ws, size_t ws_bytes, rc_stream stream) {
+    if (!counts || !aligned(counts, 16))
+        return fail(RC_ERR_INVALID_ARG, "rc_render_counts: counts must be a 16-byte aligned device pointer");
+    RenderLaunch L;
+    rc_status st = prep_plain(scene, a, ws, ws_bytes, L, "rc_render_counts");
+    if (st != RC_OK) return st;
+    L.counts = counts;
+    hipError_t e = run_plain(scene, L, ws, scene->cfg, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "rc_render_counts: launch");
+    return RC_OK;
+}
+
 // ---- batched form ----
 
 static bool batch_dims_ok(int32_t n_env, int32_t n_desc, int64_t n_pixels) {

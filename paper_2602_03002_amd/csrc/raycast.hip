@@ -199,6 +199,23 @@ struct PixelRef {  // what the exact-decision path needs to rebuild the ray
     int x, y, e, n_links;
 };
 
+// Per-ray work counters of the diagnostic render (rc_render_counts): node
+// records whose child boxes a lane reads, triangles tested, link instances
+// entered.  NoCount compiles to nothing in the production kernels.
+struct NoCount {
+    static constexpr bool kOn = false;
+    __device__ __forceinline__ void node() {}
+    __device__ __forceinline__ void tri() {}
+    __device__ __forceinline__ void inst() {}
+};
+struct RayCount {
+    static constexpr bool kOn = true;
+    uint32_t n = 0, t = 0, i = 0;
+    __device__ __forceinline__ void node() { ++n; }
+    __device__ __forceinline__ void tri() { ++t; }
+    __device__ __forceinline__ void inst() { ++i; }
+};
+
 // Test one triangle (leaf-order record v) against the ray (origin o, shear m).
 // FP32 decides when all three edge functions clearly share a sign (hit) or
 // clearly disagree (miss).  Otherwise the fast pass only records the plane
@@ -261,9 +278,10 @@ __device__ __forceinline__ void tri_test(const float* __restrict__ v, int32_t tr
 // checked and the loop is bounded (a valid hierarchy needs fewer than
 // 2 n_nodes + 2 steps), so a corrupt hierarchy ends the ray instead of
 // faulting or spinning.
-template <typename Leaf>
+template <typename Cnt, typename Leaf>
 __device__ __forceinline__ void traverse(const Node* __restrict__ nodes, int n_nodes, int n_prim,
-                                         const Slab& r, Hit& h, Leaf&& leaf, int start = 0) {
+                                         const Slab& r, Hit& h, Cnt& cnt, Leaf&& leaf,
+                                         int start = 0) {
     uint64_t trail = 0;
     int cur = start;
     int budget = 2 * n_nodes + 2;
@@ -272,6 +290,7 @@ __device__ __forceinline__ void traverse(const Node* __restrict__ nodes, int n_n
         const float4* np = reinterpret_cast<const float4*>(nodes + cur);
         const float4 q0 = np[0], q1 = np[1], q2 = np[2];
         const int4 q3 = reinterpret_cast<const int4*>(np)[3];
+        cnt.node();
         float tn0, tn1;
         bool h0 = slab(q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, r, h.tmax, tn0);
         bool h1 = slab(q1.z, q1.w, q2.x, q2.y, q2.z, q2.w, r, h.tmax, tn1);
@@ -324,10 +343,11 @@ __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlan
 
 // Enter link b of env e: take the ray to the link frame (o_b = R_b^T (o - t_b),
 // d_b = R_b^T d) and traverse the link's hierarchy under the current bound.
-template <bool EXACT>
+template <bool EXACT, typename Cnt>
 __device__ __forceinline__ void enter_link(const RenderLaunch& a, int e, int b, float ox, float oy,
                                            float oz, float dx, float dy, float dz, Hit& h,
-                                           const PixelRef& px) {
+                                           const PixelRef& px, Cnt& cnt) {
+    cnt.inst();
     const InstXform X = a.xf[(int64_t)e * a.n_links + b];
     const float px_ = ox - X.t[0], py_ = oy - X.t[1], pz_ = oz - X.t[2];
     const float lox = __fmaf_rn(X.m[2], pz_, __fmaf_rn(X.m[1], py_, X.m[0] * px_));
@@ -341,7 +361,8 @@ __device__ __forceinline__ void enter_link(const RenderLaunch& a, int e, int b, 
     const LinkMeta M = a.link_meta[b];
     const float* __restrict__ tris = a.link_tris + M.tri_base;
     const int32_t* __restrict__ ids = a.link_tri_id + M.id_base;
-    traverse(a.link_nodes + M.node_base, M.n_tri > 1 ? M.n_tri - 1 : 1, M.n_tri, ls, h, [&](int i) {
+    traverse(a.link_nodes + M.node_base, M.n_tri > 1 ? M.n_tri - 1 : 1, M.n_tri, ls, h, cnt, [&](int i) {
+        cnt.tri();
         tri_test<EXACT>(tris + 9 * (int64_t)i, ids[i], (uint32_t)b, lox, loy, loz, lm, kLinkKappa, h,
                         px, b);
     });
@@ -353,9 +374,9 @@ __device__ __forceinline__ void enter_link(const RenderLaunch& a, int e, int b, 
 // wave-uniform, in scalar registers; a node is entered if any lane's ray hits
 // it, a link only by the lanes whose rays hit its box).  Otherwise each lane
 // walks the top level alone.
-template <bool EXACT, bool WAVE>
+template <bool EXACT, bool WAVE, typename Cnt>
 __device__ __forceinline__ Hit cast_ray(const RenderLaunch& a, const CamRef& cam, int e, int x, int y,
-                                        double& scale, float bound) {
+                                        double& scale, float bound, Cnt& cnt) {
     double o64[3], d64[3], rx, ry;
     pixel_ray64(cam, x, y, o64, d64, rx, ry);
     const float ox = (float)o64[0], oy = (float)o64[1], oz = (float)o64[2];
@@ -372,8 +393,8 @@ __device__ __forceinline__ Hit cast_ray(const RenderLaunch& a, const CamRef& cam
         const Node* __restrict__ tl = a.tlas + (int64_t)e * n_rec;
         if (!WAVE) {
             const Slab ws = make_slab(ox, oy, oz, dx, dy, dz);
-            traverse(tl, n_rec, a.n_links, ws, h, [&](int b) {
-                enter_link<EXACT>(a, e, b, ox, oy, oz, dx, dy, dz, h, px);
+            traverse(tl, n_rec, a.n_links, ws, h, cnt, [&](int b) {
+                enter_link<EXACT>(a, e, b, ox, oy, oz, dx, dy, dz, h, px, cnt);
             });
         } else {
             uint32_t trail = 0;
@@ -383,6 +404,7 @@ __device__ __forceinline__ Hit cast_ray(const RenderLaunch& a, const CamRef& cam
                 cur = uni(cur);
                 if ((unsigned)cur >= (unsigned)n_rec || --budget < 0) break;
                 const Node N = tl[cur];
+                cnt.node();
                 const Slab ws = make_slab(ox, oy, oz, dx, dy, dz);
                 float tn0, tn1;
                 bool h0 = slab(N.b0[0], N.b0[1], N.b0[2], N.b0[3], N.b0[4], N.b0[5], ws, h.tmax, tn0);
@@ -394,7 +416,7 @@ __device__ __forceinline__ Hit cast_ray(const RenderLaunch& a, const CamRef& cam
                     const int c = k == 0 ? c0 : c1;
                     const bool hk = k == 0 ? h0 : h1;
                     if (c >= 0 || __ballot(hk) == 0ull) continue;
-                    if (hk) enter_link<EXACT>(a, e, ~c, ox, oy, oz, dx, dy, dz, h, px);
+                    if (hk) enter_link<EXACT>(a, e, ~c, ox, oy, oz, dx, dy, dz, h, px, cnt);
                 }
                 const bool g0 = c0 >= 0 && h0 && tn0 <= h.tmax;
                 const bool g1 = c1 >= 0 && h1 && tn1 <= h.tmax;
@@ -446,6 +468,7 @@ __device__ __forceinline__ Hit cast_ray(const RenderLaunch& a, const CamRef& cam
                 f[k] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(f[k])));
             for (int guard = 0; guard < 64; ++guard) {
                 const Node& N = a.terrain_nodes[entry];
+                cnt.node();
                 const bool o0 = N.b0[0] <= f[1] && N.b0[1] >= f[0] && N.b0[2] <= f[3] &&
                                 N.b0[3] >= f[2] && N.b0[4] <= f[5] && N.b0[5] >= f[4];
                 const bool o1 = N.b1[0] <= f[1] && N.b1[1] >= f[0] && N.b1[2] <= f[3] &&
@@ -460,8 +483,9 @@ __device__ __forceinline__ Hit cast_ray(const RenderLaunch& a, const CamRef& cam
         if (reach) {
             const Slab ws = make_slab(ox, oy, oz, dx, dy, dz);
             const Shear wm = make_shear(dx, dy, dz);
-            traverse(a.terrain_nodes, a.n_terrain > 1 ? a.n_terrain - 1 : 1, a.n_terrain, ws, h,
+            traverse(a.terrain_nodes, a.n_terrain > 1 ? a.n_terrain - 1 : 1, a.n_terrain, ws, h, cnt,
                      [&](int i) {
+                         cnt.tri();
                          tri_test<EXACT>(a.terrain_tris + 9 * (int64_t)i, a.terrain_tri_id[i],
                                          (uint32_t)a.n_links, ox, oy, oz, wm, kTerrainKappa, h, px,
                                          -1);
@@ -494,7 +518,7 @@ __device__ __forceinline__ CamRef desc_cam(const rc_cam_desc* d) {
 // see only real rays) and write nothing.  Rays whose closest hit could hinge
 // on an FP32-undecided triangle go to the exact pass's list, with the certain
 // hit found here as their starting bound.
-template <int RPL>
+template <int RPL, typename Cnt = NoCount>
 __device__ __forceinline__ void cast_tile(const RenderLaunch& a, const TileCfg& c, const CamRef& cam,
                                           int e, uint32_t cam_index, int width, int height,
                                           int64_t out0, int tx, int ty) {
@@ -510,10 +534,13 @@ __device__ __forceinline__ void cast_tile(const RenderLaunch& a, const TileCfg& 
         const int x = xt < width ? xt : width - 1;
         const int y = yt < height ? yt : height - 1;
         double scale;
-        const Hit h = cast_ray<false, true>(a, cam, e, x, y, scale, INFINITY);
+        Cnt cnt;
+        const Hit h = cast_ray<false, true>(a, cam, e, x, y, scale, INFINITY, cnt);
         if (!valid) continue;
         const int64_t p = out0 + (int64_t)y * width + x;
         write_out(a, p, h, scale);
+        if constexpr (Cnt::kOn)
+            reinterpret_cast<uint4*>(a.counts)[p] = make_uint4(cnt.n, cnt.t, cnt.i, 0u);
         if (h.tu <= h.tmax * (1.0f + 1.0f / 1024.0f)) {
             const uint32_t slot = atomicAdd(a.exact_count, 1u);
             if ((int64_t)slot < a.exact_cap)
@@ -527,7 +554,7 @@ __device__ __forceinline__ void cast_tile(const RenderLaunch& a, const TileCfg& 
 // Fast pass over the plain [env][cam][H][W] layout.  WAVES asks the compiler
 // for at least that many resident wavefronts per SIMD (fewer registers per
 // lane, maybe a few spills); the autotuner picks it and the tile schedule.
-template <int WAVES, int RPL>
+template <int WAVES, int RPL, typename Cnt = NoCount>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES, 8)))
 k_render(RenderLaunch a, TileCfg c, int64_t n_logical, int64_t per_xcd) {
     // XCD-aware order: hardware deals blocks round-robin over the 8 XCDs, so
@@ -544,7 +571,7 @@ k_render(RenderLaunch a, TileCfg c, int64_t n_logical, int64_t per_xcd) {
     const int64_t ec = tile / tiles_img;
     if (ec >= (int64_t)a.n_env * a.n_cam) return;
     const int tin = (int)(tile - ec * tiles_img);
-    cast_tile<RPL>(a, c, plain_cam(a, ec), (int)(ec / a.n_cam), (uint32_t)ec, a.width, a.height,
+    cast_tile<RPL, Cnt>(a, c, plain_cam(a, ec), (int)(ec / a.n_cam), (uint32_t)ec, a.width, a.height,
                    ec * (int64_t)a.width * a.height, tin % tiles_x, tin / tiles_x);
 }
 
@@ -669,7 +696,8 @@ __device__ __forceinline__ void exact_one(const RenderLaunch& a, int64_t p, uint
         e = (int)(cam_index / (uint32_t)a.n_cam);
     }
     double scale;
-    const Hit h = cast_ray<true, false>(a, cam, e, x, y, scale, bound);
+    NoCount none;
+    const Hit h = cast_ray<true, false>(a, cam, e, x, y, scale, bound, none);
     write_out(a, p, h, scale);
 }
 
@@ -709,7 +737,8 @@ __global__ void __launch_bounds__(64) k_render_exact(RenderLaunch a, const uint3
 }  // namespace
 
 hipError_t launch_render(const RenderLaunch& a, const RenderCfg& cfg, hipStream_t s) {
-    TileCfg c{cfg.tile_w, cfg.tile_h, cfg.rays_per_lane};
+    // the counting variant casts one tile per wavefront
+    TileCfg c{cfg.tile_w, cfg.tile_h, a.counts ? 1 : cfg.rays_per_lane};
     const int span_h = c.th * c.rpl;
     const int tiles_x = (a.width + c.tw - 1) / c.tw;
     const int tiles_y = (a.height + span_h - 1) / span_h;
@@ -720,8 +749,11 @@ hipError_t launch_render(const RenderLaunch& a, const RenderCfg& cfg, hipStream_
     hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(1), 0, s, a.exact_count);
     if (a.ev_begin) hipEventRecord(a.ev_begin, s);
 #define RC_PLAIN(W, R) hipLaunchKernelGGL((k_render<W, R>), grid, block, 0, s, a, c, n_logical, per_xcd)
-    const int v = 10 * cfg.waves + c.rpl;
+    const int v = a.counts ? 0 : 10 * cfg.waves + c.rpl;
     switch (v) {
+        case 0:
+            hipLaunchKernelGGL((k_render<6, 1, RayCount>), grid, block, 0, s, a, c, n_logical, per_xcd);
+            break;
         case 71: RC_PLAIN(7, 1); break;
         case 72: RC_PLAIN(7, 2); break;
         case 81: RC_PLAIN(8, 1); break;

@@ -96,6 +96,7 @@ struct RenderLaunch {
     int max_width, max_height;  // batched form: largest image a descriptor may have
     hipEvent_t ev_begin, ev_end;  // optional events around the fast-pass kernel
     int64_t n_pixels;         // output pixels
+    uint32_t* counts = nullptr;  // diagnostic: per-ray (nodes, triangles, instances, 0), uint4
     int n_env, n_cam, width, height, n_links, depth_mode, n_terrain;
     float far_plane;
 };

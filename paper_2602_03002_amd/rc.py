@@ -20,7 +20,7 @@ EXPORTED = [
     "rc_version", "rc_status_string", "rc_last_error",
     "rc_scene_size", "rc_scene_create", "rc_scene_destroy",
     "rc_robot_size", "rc_robot_meshes",
-    "rc_render_size", "rc_render", "rc_render_exact_count",
+    "rc_render_size", "rc_render", "rc_render_exact_count", "rc_render_counts",
     "rc_post_size", "rc_post_create", "rc_post_reset", "rc_postprocess", "rc_post_destroy",
     "rc_bvh_layout_of",
     "rc_render_batched_size", "rc_render_batched", "rc_render_batched_status",
@@ -141,6 +141,7 @@ def lib():
         L.rc_render_size.argtypes = [vp, i32, i32, i32, i32, ctypes.POINTER(sz)]
         L.rc_render_exact_count.argtypes = [vp, i32, i32, i32, i32, vp, ctypes.POINTER(i64), vp]
         L.rc_render.argtypes = [vp, ctypes.POINTER(RenderArgs), vp, sz, vp]
+        L.rc_render_counts.argtypes = [vp, ctypes.POINTER(RenderArgs), vp, vp, sz, vp]
         L.rc_post_size.argtypes = [i32, i32, i32, i32, i32, ctypes.POINTER(sz)]
         L.rc_post_create.argtypes = [i32, i32, i32, i32, i32, vp, sz, ctypes.POINTER(vp)]
         L.rc_post_reset.argtypes = [vp]
@@ -319,6 +320,18 @@ class Scene:
         check(lib().rc_render(self.handle, ctypes.byref(a), ctypes.c_void_p(ws.ptr), ws.nbytes,
                               _stream(stream)))
         return outs
+
+    def render_counts(self, cam_pos, cam_quat, intr, width, height, far_plane, link_pos=None,
+                      link_quat=None, depth_mode=RC_DEPTH_PLANAR, out=None, stream=None):
+        """rc_render plus per-ray work counts.  Returns ((depth, inst, tri),
+        counts int32 [E,C,H,W,4] = (node records, triangles, instances, 0))."""
+        a, outs, ws = self._plain_args(cam_pos, cam_quat, intr, width, height, far_plane, link_pos,
+                                       link_quat, depth_mode, out, True)
+        counts = torch.empty((cam_pos.shape[0], cam_pos.shape[1], height, width, 4),
+                             dtype=torch.int32, device=self.device)
+        check(lib().rc_render_counts(self.handle, ctypes.byref(a), _ptr(counts),
+                                     ctypes.c_void_p(ws.ptr), ws.nbytes, _stream(stream)))
+        return outs, counts
 
     # -- batched uneven form -------------------------------------------------
 

@@ -1,4 +1,6 @@
 """GPU parity: librc (through its C-ABI) against the FP64 oracle and the CPU LBVH model."""
+import ctypes
+
 import numpy as np
 import pytest
 import torch
@@ -159,6 +161,34 @@ def test_render_is_deterministic():
     b = render(sc, w)
     for x, y in zip(a, b):
         assert np.array_equal(x, y)
+
+
+def test_render_counts_matches_render():
+    say("[render] diagnostic work counts: same outputs as rc_render, plausible counts")
+    w = sg.robot_scene(2, 2, 4.0, 2, 37, 29, steps=1, label="counts")
+    sc = make_scene(w)
+    ref = render(sc, w)
+    args = (dev(w["cam_pos"]), dev(w["cam_quat"]), dev(w["intr"]), w["W"], w["H"], w["far"])
+    kw = dict(link_pos=dev(w["link_pos"][0]), link_quat=dev(w["link_quat"][0]))
+    outs, counts = sc.render_counts(*args, **kw)
+    torch.cuda.synchronize()
+    for g, r in zip(outs, ref):
+        assert np.array_equal(g.cpu().numpy(), r)
+    c = counts.cpu().numpy().reshape(-1, 4)
+    inst = ref[1].ravel()
+    assert np.all(c[:, 3] == 0)
+    assert np.all(c[:, 0] >= 1), "every ray reads at least one node record"
+    assert np.all(c[:, 2] <= sc.n_links), "a link is entered at most once per ray"
+    assert np.all(c[inst >= 0, 1] >= 1), "a hit needs a triangle test"
+    assert np.all(c[(inst >= 0) & (inst < sc.n_links), 2] >= 1), "a link hit needs its instance"
+    _, again = sc.render_counts(*args, **kw)
+    torch.cuda.synchronize()
+    assert np.array_equal(again.cpu().numpy().reshape(-1, 4), c)
+    m = rc()
+    a, _, ws = sc._plain_args(*args, kw["link_pos"], kw["link_quat"], 0, None, True)
+    st = m.lib().rc_render_counts(sc.handle, ctypes.byref(a), None, ctypes.c_void_p(ws.ptr),
+                                  ws.nbytes, None)
+    assert st == -1
 
 
 def sampled(w, n, seed):
