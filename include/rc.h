@@ -132,21 +132,23 @@ rc_status rc_render_size(const rc_scene* scene, int32_t n_env, int32_t n_cam, in
 /* Rebuild every environment's top-level hierarchy from its link poses, then
  * cast one ray per (env, cam, pixel): link hits first, then the terrain under
  * the shrunken bound, closest hit kept (ties: lower inst, then lower tri).
- * A hit counts when 0 < depth <= far_plane.  Hit decisions are exact: a ray
- * whose closest hit could hinge on a triangle edge test FP32 cannot decide
- * is re-cast by a second pass that repeats such tests in FP64.  Errors:
+ * A hit counts when 0 < depth <= far_plane.  Hit decisions are exact: when
+ * a ray's closest hit could hinge on triangle edge tests FP32 cannot decide,
+ * a second pass repeats those tests in FP64 (for up to two such triangles
+ * per ray) or re-casts the ray with FP64 decisions (more).  Errors:
  * INVALID_ARG (sizes < 1, width or height > 65535, more than 2^32 - 1 rays,
  * NULL required pointers, bad mode), WORKSPACE, STATE (no terrain), DEVICE.
  * The workspace's first bytes after the top level hold the exact-pass ray
- * count (uint32) of the last call; see rc_render_exact_count. */
+ * counts (two uint32) of the last call; see rc_render_exact_count. */
 rc_status rc_render(const rc_scene* scene, const rc_render_args* args, void* ws,
                     size_t ws_bytes, rc_stream stream);
 
 /* Number of rays the last rc_render on this workspace sent to the exact pass
- * (a diagnostic).  Synchronises `stream`. */
+ * (a diagnostic), and how many of them it re-cast in full (`recast`, may be
+ * NULL).  Synchronises `stream`. */
 rc_status rc_render_exact_count(const rc_scene* scene, int32_t n_env, int32_t n_cam,
                                 int32_t width, int32_t height, const void* ws, int64_t* count,
-                                rc_stream stream);
+                                int64_t* recast, rc_stream stream);
 
 /* Diagnostic render: rc_render (same workspace, same outputs) whose fast
  * pass also writes, per ray, the work it did as uint32 [n_env][n_cam]

@@ -263,14 +263,14 @@ static RenderWs render_layout(int64_t n_env, int64_t n_pixels, int32_t n_links, 
     } else {
         L.xf = 0;
     }
-    L.count = o;
-    o = align_up(o + 4);
-    // a bounded list (a pixel in 16 typically suffices by far); on overflow the
-    // exact pass re-casts every pixel
+    L.count = o;  // two uint32 counters
+    o = align_up(o + 8);
+    // a bounded list of 32-byte entries (a pixel in 16 typically suffices by
+    // far); on overflow the exact pass re-casts every pixel
     const int64_t basis = cap_rays >= 0 ? cap_rays : n_pixels;
     L.cap = basis / 16 > 4096 ? basis / 16 : 4096;
     L.list = o;
-    o = align_up(o + (size_t)L.cap * 16);
+    o = align_up(o + (size_t)L.cap * 32);
     L.tiles = o;
     o = align_up(o + (size_t)(n_desc > 0 ? n_desc + 1 : 1) * 4);
     L.queues = o;
@@ -505,14 +505,14 @@ rc_status rc_render_batched_status(const rc_scene* scene, const rc_batch_args* a
     if (!batch_dims_ok(a->n_env, a->n_desc, a->n_pixels))
         return fail(RC_ERR_INVALID_ARG, "rc_render_batched_status: bad sizes");
     const RenderWs W = render_layout(a->n_env, a->n_pixels, scene->n_links, a->n_desc);
-    uint32_t v[2] = {0, 0};
+    uint32_t v[3] = {0, 0, 0};
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = hipMemcpyAsync(&v[0], (const char*)ws + W.status, 4, hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(&v[1], (const char*)ws + W.count, 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(&v[1], (const char*)ws + W.count, 8, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "rc_render_batched_status");
     *status = v[0];
-    if (exact_rays) *exact_rays = v[1];
+    if (exact_rays) *exact_rays = (int64_t)v[1] + v[2];
     return RC_OK;
 }
 
@@ -647,17 +647,18 @@ rc_status rc_graph_destroy(rc_graph* graph) {
 
 rc_status rc_render_exact_count(const rc_scene* scene, int32_t n_env, int32_t n_cam,
                                 int32_t width, int32_t height, const void* ws, int64_t* count,
-                                rc_stream stream) {
+                                int64_t* recast, rc_stream stream) {
     if (!scene || !ws || !count) return fail(RC_ERR_INVALID_ARG, "rc_render_exact_count: NULL pointer");
     if (!render_dims_ok(n_env, n_cam, width, height))
         return fail(RC_ERR_INVALID_ARG, "rc_render_exact_count: bad sizes");
     const RenderWs W = render_layout(n_env, (int64_t)n_env * n_cam * width * height, scene->n_links, 0);
-    uint32_t c = 0;
-    hipError_t e = hipMemcpyAsync(&c, (const char*)ws + W.count, 4, hipMemcpyDeviceToHost,
+    uint32_t c[2] = {0, 0};
+    hipError_t e = hipMemcpyAsync(c, (const char*)ws + W.count, 8, hipMemcpyDeviceToHost,
                                   (hipStream_t)stream);
     if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "rc_render_exact_count");
-    *count = c;
+    *count = (int64_t)c[0] + c[1];
+    if (recast) *recast = c[1];
     return RC_OK;
 }
 

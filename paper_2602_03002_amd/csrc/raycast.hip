@@ -197,7 +197,20 @@ struct PixelRef {  // what the exact-decision path needs to rebuild the ray
     const float* link_pos;
     const float* link_quat;
     int x, y, e, n_links;
+    uint2* cand;  // fast pass: this lane's two LDS slots for FP32-undecided triangles
 };
+
+// FP32-undecided triangles the fast pass keeps per ray (in LDS), for the exact
+// pass to decide in FP64 without re-casting the ray.  A slot holds
+// (id, bits of the plane distance); id = (link + 1) << kLeafBits | leaf, link
+// + 1 = 0 for the terrain.  A ray with more undecided triangles near its hit
+// than slots is re-cast in full.
+constexpr uint32_t kNoCand = 0xFFFFFFFFu;
+constexpr int kLeafBits = 25;
+constexpr int kCandSlots = 2;
+// an undecided plane farther than the bound times this cannot matter (covers
+// the FP32 error of its distance)
+constexpr float kUndecidedSlack = 1.0f + 1.0f / 1024.0f;
 
 // Per-ray work counters of the diagnostic render (rc_render_counts): node
 // records whose child boxes a lane reads, triangles tested, link instances
@@ -224,7 +237,7 @@ struct RayCount {
 template <bool EXACT>
 __device__ __forceinline__ void tri_test(const float* __restrict__ v, int32_t tri_id, uint32_t inst,
                                          float ox, float oy, float oz, const Shear& m, float kappa,
-                                         Hit& h, const PixelRef& px, int link) {
+                                         Hit& h, const PixelRef& px, int link, int leaf) {
     const float p0x = v[0] - ox, p0y = v[1] - oy, p0z = v[2] - oz;
     const float p1x = v[3] - ox, p1y = v[4] - oy, p1z = v[5] - oz;
     const float p2x = v[6] - ox, p2y = v[7] - oy, p2z = v[8] - oz;
@@ -252,10 +265,24 @@ __device__ __forceinline__ void tri_test(const float* __restrict__ v, int32_t tr
         const float T = __fmaf_rn(W, Cz, __fmaf_rn(V, Bz, U * Az));
         t = T / det;
         if (!EXACT && !sure) {
-            // undecided in FP32: remember how near it could be; a plane behind
-            // the origin (well conditioned) cannot matter
+            // undecided in FP32: keep the triangle for the exact pass unless its
+            // plane is behind the origin (well conditioned) or beyond the bound
             const bool cond = fabsf(det) > thr;
-            if (!(cond && t < -1e-3f)) h.tu = fminf(h.tu, (cond && t > 0.0f) ? t : 0.0f);
+            if (cond && t < -1e-3f) return;
+            const float tu = (cond && t > 0.0f) ? t : 0.0f;
+            const float lim = h.tmax * kUndecidedSlack;
+            if (tu > lim) return;
+            if ((uint32_t)leaf < (1u << kLeafBits)) {
+                const uint32_t id = ((uint32_t)(link + 1) << kLeafBits) | (uint32_t)leaf;
+                for (int k = 0; k < kCandSlots; ++k) {
+                    const uint2 c = px.cand[k];  // a slot is free if empty or out of reach now
+                    if (c.x == kNoCand || __uint_as_float(c.y) > lim) {
+                        px.cand[k] = make_uint2(id, __float_as_uint(tu));
+                        return;
+                    }
+                }
+            }
+            h.tu = fminf(h.tu, tu);  // no free slot: the ray will be re-cast in full
             return;
         }
     } else {
@@ -364,7 +391,7 @@ __device__ __forceinline__ void enter_link(const RenderLaunch& a, int e, int b, 
     traverse(a.link_nodes + M.node_base, M.n_tri > 1 ? M.n_tri - 1 : 1, M.n_tri, ls, h, cnt, [&](int i) {
         cnt.tri();
         tri_test<EXACT>(tris + 9 * (int64_t)i, ids[i], (uint32_t)b, lox, loy, loz, lm, kLinkKappa, h,
-                        px, b);
+                        px, b, i);
     });
 }
 
@@ -376,7 +403,7 @@ __device__ __forceinline__ void enter_link(const RenderLaunch& a, int e, int b, 
 // walks the top level alone.
 template <bool EXACT, bool WAVE, typename Cnt>
 __device__ __forceinline__ Hit cast_ray(const RenderLaunch& a, const CamRef& cam, int e, int x, int y,
-                                        double& scale, float bound, Cnt& cnt) {
+                                        double& scale, float bound, uint2* cand, Cnt& cnt) {
     double o64[3], d64[3], rx, ry;
     pixel_ray64(cam, x, y, o64, d64, rx, ry);
     const float ox = (float)o64[0], oy = (float)o64[1], oz = (float)o64[2];
@@ -386,7 +413,7 @@ __device__ __forceinline__ Hit cast_ray(const RenderLaunch& a, const CamRef& cam
     h.tmax = fminf((float)((double)a.far_plane / scale), bound);
     h.key = ~0ull;
     h.tu = INFINITY;
-    const PixelRef px{cam, a.link_pos, a.link_quat, x, y, e, a.n_links};
+    const PixelRef px{cam, a.link_pos, a.link_quat, x, y, e, a.n_links, cand};
 
     if (a.n_links > 0) {
         const int n_rec = a.n_links > 1 ? a.n_links - 1 : 1;
@@ -488,7 +515,7 @@ __device__ __forceinline__ Hit cast_ray(const RenderLaunch& a, const CamRef& cam
                          cnt.tri();
                          tri_test<EXACT>(a.terrain_tris + 9 * (int64_t)i, a.terrain_tri_id[i],
                                          (uint32_t)a.n_links, ox, oy, oz, wm, kTerrainKappa, h, px,
-                                         -1);
+                                         -1, i);
                      },
                      entry);
         }
@@ -516,8 +543,10 @@ __device__ __forceinline__ CamRef desc_cam(const rc_cam_desc* d) {
 // (width x height, env e, camera `cam`, output pixels from `out0`); lanes
 // past the image edge trace a copy of an edge pixel (so wave-wide reductions
 // see only real rays) and write nothing.  Rays whose closest hit could hinge
-// on an FP32-undecided triangle go to the exact pass's list, with the certain
-// hit found here as their starting bound.
+// on FP32-undecided triangles go to the exact pass: with the certain hit
+// found here and the (at most two) undecided triangles to decide in FP64 at
+// the front of its list, or, with more, to be re-cast in full (from the back
+// of the list, starting from the certain hit's bound).
 template <int RPL, typename Cnt = NoCount>
 __device__ __forceinline__ void cast_tile(const RenderLaunch& a, const TileCfg& c, const CamRef& cam,
                                           int e, uint32_t cam_index, int width, int height,
@@ -525,6 +554,8 @@ __device__ __forceinline__ void cast_tile(const RenderLaunch& a, const TileCfg& 
     const int lane = threadIdx.x & 63;
     const int span_h = c.th * RPL;
     const int xt = tx * c.tw + (lane % c.tw);
+    __shared__ uint2 s_cand[64 * kWavesPerBlock * kCandSlots];
+    uint2* cand = s_cand + kCandSlots * threadIdx.x;
 #pragma unroll
     for (int r = 0; r < RPL; ++r) {
         const int y0 = ty * span_h + r * c.th;
@@ -535,18 +566,31 @@ __device__ __forceinline__ void cast_tile(const RenderLaunch& a, const TileCfg& 
         const int y = yt < height ? yt : height - 1;
         double scale;
         Cnt cnt;
-        const Hit h = cast_ray<false, true>(a, cam, e, x, y, scale, INFINITY, cnt);
+        for (int k = 0; k < kCandSlots; ++k) cand[k].x = kNoCand;
+        const Hit h = cast_ray<false, true>(a, cam, e, x, y, scale, INFINITY, cand, cnt);
         if (!valid) continue;
         const int64_t p = out0 + (int64_t)y * width + x;
         write_out(a, p, h, scale);
         if constexpr (Cnt::kOn)
             reinterpret_cast<uint4*>(a.counts)[p] = make_uint4(cnt.n, cnt.t, cnt.i, 0u);
-        if (h.tu <= h.tmax * (1.0f + 1.0f / 1024.0f)) {
-            const uint32_t slot = atomicAdd(a.exact_count, 1u);
-            if ((int64_t)slot < a.exact_cap)
-                a.exact_list[slot] = make_uint4((uint32_t)p, cam_index,
-                                                (uint32_t)x | ((uint32_t)y << 16),
-                                                __float_as_uint(h.tmax));
+        const float lim = h.tmax * kUndecidedSlack;
+        const uint4 head = make_uint4((uint32_t)p, cam_index, (uint32_t)x | ((uint32_t)y << 16),
+                                      __float_as_uint(h.tmax));
+        if (h.tu <= lim) {  // re-cast in full
+            const uint32_t slot = atomicAdd(a.exact_count + 1, 1u);
+            if ((int64_t)slot < a.exact_cap) a.exact_list[2 * (a.exact_cap - 1 - slot)] = head;
+        } else {
+            const uint2 c0 = cand[0], c1 = cand[1];
+            const uint32_t i0 = (c0.x != kNoCand && __uint_as_float(c0.y) <= lim) ? c0.x : kNoCand;
+            const uint32_t i1 = (c1.x != kNoCand && __uint_as_float(c1.y) <= lim) ? c1.x : kNoCand;
+            if (i0 != kNoCand || i1 != kNoCand) {
+                const uint32_t slot = atomicAdd(a.exact_count, 1u);
+                if ((int64_t)slot < a.exact_cap) {
+                    a.exact_list[2 * (int64_t)slot] = head;
+                    a.exact_list[2 * (int64_t)slot + 1] =
+                        make_uint4((uint32_t)h.key, (uint32_t)(h.key >> 32), i0, i1);
+                }
+            }
         }
     }
 }
@@ -617,7 +661,7 @@ __global__ void __launch_bounds__(1024) k_batch_prep(RenderLaunch a, TileCfg c, 
     }
     if (threadIdx.x == 1023) tile_start[n] = sums[1023];
     if (threadIdx.x == 0) queues[0] = 0u;
-    if (threadIdx.x == 0) *a.exact_count = 0u;
+    if (threadIdx.x == 0) a.exact_count[0] = a.exact_count[1] = 0u;
     if (bad) atomicOr(status, 1u);
 }
 
@@ -680,13 +724,9 @@ k_render_flat(RenderLaunch a, TileCfg c, const uint32_t* __restrict__ tile_start
                    k % tiles_x, k / tiles_x);
 }
 
-// Exact pass: the rays the fast pass listed, each lane on its own, with FP64
-// decisions for undecided triangles.  Small blocks spread the few rays over
-// all compute units.  If the list overflowed, every pixel is re-cast.
-__device__ __forceinline__ void exact_one(const RenderLaunch& a, int64_t p, uint32_t cam_index, int x,
-                                          int y, float bound) {
-    CamRef cam;
-    int e;
+// Exact pass.  If the list overflowed, every pixel is re-cast.
+__device__ __forceinline__ void entry_cam(const RenderLaunch& a, uint32_t cam_index, CamRef& cam,
+                                          int& e) {
     if (a.desc) {
         const rc_cam_desc* D = a.desc + cam_index;
         cam = desc_cam(D);
@@ -695,22 +735,88 @@ __device__ __forceinline__ void exact_one(const RenderLaunch& a, int64_t p, uint
         cam = plain_cam(a, cam_index);
         e = (int)(cam_index / (uint32_t)a.n_cam);
     }
+}
+
+// Full re-cast of one ray with FP64 decisions for undecided triangles.
+__device__ __forceinline__ void exact_one(const RenderLaunch& a, int64_t p, uint32_t cam_index, int x,
+                                          int y, float bound) {
+    CamRef cam;
+    int e;
+    entry_cam(a, cam_index, cam, e);
     double scale;
     NoCount none;
-    const Hit h = cast_ray<true, false>(a, cam, e, x, y, scale, bound, none);
+    const Hit h = cast_ray<true, false>(a, cam, e, x, y, scale, bound, nullptr, none);
     write_out(a, p, h, scale);
 }
 
-__global__ void k_zero_count(uint32_t* c) { *c = 0u; }
+// Decide a listed ray's undecided triangles in FP64 and merge them with the
+// fast pass's certain hit (same order as the traversal: ray parameter, then
+// (inst, tri)).
+__device__ __forceinline__ void resolve_one(const RenderLaunch& a, const uint4 head, const uint4 rest) {
+    CamRef cam;
+    int e;
+    entry_cam(a, head.y, cam, e);
+    const int x = (int)(head.z & 0xFFFFu), y = (int)(head.z >> 16);
+    double o[3], d[3], rx, ry;
+    pixel_ray64(cam, x, y, o, d, rx, ry);
+    const double scale = a.depth_mode == RC_DEPTH_RANGE ? sqrt(rx * rx + ry * ry + 1.0) : 1.0;
+    Hit h;
+    h.tmax = __uint_as_float(head.w);
+    h.key = ((uint64_t)rest.y << 32) | rest.x;
+    h.tu = INFINITY;
+    for (int k = 0; k < kCandSlots; ++k) {
+        const uint32_t id = k == 0 ? rest.z : rest.w;
+        if (id == kNoCand) continue;
+        const int link = (int)(id >> kLeafBits) - 1;
+        const int leaf = (int)(id & ((1u << kLeafBits) - 1u));
+        const float* v;
+        int32_t tri_id;
+        uint32_t inst;
+        if (link < 0) {
+            if (leaf >= a.n_terrain) continue;
+            v = a.terrain_tris + 9 * (int64_t)leaf;
+            tri_id = a.terrain_tri_id[leaf];
+            inst = (uint32_t)a.n_links;
+        } else {
+            if (link >= a.n_links) continue;
+            const LinkMeta M = a.link_meta[link];
+            if (leaf >= M.n_tri) continue;
+            v = a.link_tris + M.tri_base + 9 * (int64_t)leaf;
+            tri_id = a.link_tri_id[M.id_base + leaf];
+            inst = (uint32_t)link;
+        }
+        double t64;
+        if (!refine(v, cam.pos, cam.quat, cam.intr, x, y, link, e, a.n_links, a.link_pos,
+                    a.link_quat, &t64))
+            continue;
+        const float t = (float)t64;
+        if (!(t > 0.0f) || t > h.tmax) continue;
+        const uint64_t key = ((uint64_t)inst << 32) | (uint32_t)tri_id;
+        if (t < h.tmax || key < h.key) {
+            h.tmax = t;
+            h.key = key;
+        }
+    }
+    write_out(a, head.x, h, scale);
+}
+
+__global__ void k_zero_count(uint32_t* c) { c[0] = c[1] = 0u; }
 
 __global__ void __launch_bounds__(64) k_render_exact(RenderLaunch a, const uint32_t* tile_start) {
-    const uint32_t n = *a.exact_count;
+    const uint32_t n_res = a.exact_count[0], n_full = a.exact_count[1];
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if ((int64_t)n <= a.exact_cap) {
-        for (int64_t i = gid; i < (int64_t)n; i += stride) {
-            const uint4 it = a.exact_list[i];
-            exact_one(a, it.x, it.y, (int)(it.z & 0xFFFFu), (int)(it.z >> 16), __uint_as_float(it.w));
+    if ((int64_t)n_res + n_full <= a.exact_cap) {
+        for (int64_t i = gid; i < (int64_t)n_res; i += stride)
+            resolve_one(a, a.exact_list[2 * i], a.exact_list[2 * i + 1]);
+        // full re-casts: one ray per wavefront, so no wavefront waits on the
+        // slowest of many divergent traversals
+        if ((threadIdx.x & 63) == 0) {
+            for (int64_t j = gid >> 6; j < (int64_t)n_full; j += stride >> 6) {
+                const uint4 it = a.exact_list[2 * (a.exact_cap - 1 - j)];
+                exact_one(a, it.x, it.y, (int)(it.z & 0xFFFFu), (int)(it.z >> 16),
+                          __uint_as_float(it.w));
+            }
         }
         return;
     }

@@ -88,9 +88,14 @@ struct RenderLaunch {
     float* depth;
     int32_t* inst;
     int32_t* tri;
-    uint32_t* exact_count;  // rays the fast pass hands to the exact pass
-    uint4* exact_list;      // (pixel, camera index, x | y << 16, bits of the fast pass's bound)
-    int64_t exact_cap;
+    // Rays the fast pass hands to the exact pass: [0] rays whose undecided
+    // triangles are listed (entries from the front), [1] rays to re-cast in
+    // full (entries from the back).  An entry is two uint4: (pixel, camera
+    // index, x | y << 16, bits of the fast pass's bound) and, for the first
+    // kind, (certain hit key low, high, two triangle ids or ~0).
+    uint32_t* exact_count;
+    uint4* exact_list;
+    int64_t exact_cap;  // entries
     const rc_cam_desc* desc;  // batched form: camera descriptors (NULL: plain layout)
     int n_desc;
     int max_width, max_height;  // batched form: largest image a descriptor may have

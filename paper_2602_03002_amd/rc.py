@@ -139,7 +139,8 @@ def lib():
         L.rc_robot_size.argtypes = [vp, i32, ctypes.POINTER(sz)]
         L.rc_robot_meshes.argtypes = [vp, vp, vp, i32, vp, sz, vp]
         L.rc_render_size.argtypes = [vp, i32, i32, i32, i32, ctypes.POINTER(sz)]
-        L.rc_render_exact_count.argtypes = [vp, i32, i32, i32, i32, vp, ctypes.POINTER(i64), vp]
+        L.rc_render_exact_count.argtypes = [vp, i32, i32, i32, i32, vp, ctypes.POINTER(i64),
+                                            ctypes.POINTER(i64), vp]
         L.rc_render.argtypes = [vp, ctypes.POINTER(RenderArgs), vp, sz, vp]
         L.rc_render_counts.argtypes = [vp, ctypes.POINTER(RenderArgs), vp, vp, sz, vp]
         L.rc_post_size.argtypes = [i32, i32, i32, i32, i32, ctypes.POINTER(sz)]
@@ -278,13 +279,16 @@ class Scene:
             self._render_ws[key] = ws
         return ws
 
-    def exact_count(self, n_env, n_cam, width, height, stream=None):
-        """Rays the last render with these sizes sent to the exact pass."""
+    def exact_count(self, n_env, n_cam, width, height, stream=None, recast=False):
+        """Rays the last render with these sizes sent to the exact pass (and, with
+        recast=True, also how many of them it re-cast in full)."""
         ws = self.render_workspace(n_env, n_cam, width, height)
         c = ctypes.c_int64()
+        r = ctypes.c_int64()
         check(lib().rc_render_exact_count(self.handle, n_env, n_cam, width, height,
-                                          ctypes.c_void_p(ws.ptr), ctypes.byref(c), _stream(stream)))
-        return c.value
+                                          ctypes.c_void_p(ws.ptr), ctypes.byref(c), ctypes.byref(r),
+                                          _stream(stream)))
+        return (c.value, r.value) if recast else c.value
 
     def _plain_args(self, cam_pos, cam_quat, intr, width, height, far_plane, link_pos, link_quat,
                     depth_mode, out, ids, timing=None):

@@ -313,11 +313,9 @@ def look_quat(direction):
     return Rotation.from_matrix(np.stack([x, np.cross(z, x), z], 1)).as_quat()
 
 
-@pytest.mark.parametrize("as_link", [False, True])
-def test_watertight_vertices_and_edges(as_link):
+def watertight_scene(as_link, repeat=1):
     """Rays aimed exactly at every vertex and edge midpoint of a closed convex
-    mesh (decisions FP32 cannot make: the exact pass must take them) hit it."""
-    say(f"[render] watertight vertex/edge rays, mesh as {'link' if as_link else 'terrain'}")
+    mesh (one 1x1 camera per ray), the set repeated `repeat` times."""
     V, T = sg.octasphere(3)
     mesh = (V[T] * 0.3).astype(np.float32)
     centre = np.array([5.0, -3.0, 1.5])
@@ -325,7 +323,7 @@ def test_watertight_vertices_and_edges(as_link):
     for t in mesh.astype(np.float64):
         for i in range(3):
             pts.add(tuple(0.5 * (t[i] + t[(i + 1) % 3])))
-    pts = np.array(sorted(pts))
+    pts = np.tile(np.array(sorted(pts)), (repeat, 1))
     E = pts.shape[0]
     dirs = pts / np.linalg.norm(pts, axis=1, keepdims=True)
     cam_pos = (centre + 2.0 * dirs)[:, None, :].astype(np.float32)
@@ -336,18 +334,40 @@ def test_watertight_vertices_and_edges(as_link):
         w = dict(terrain=far_tri, link_tri=mesh, link_off=np.array([0, mesh.shape[0]], np.int64),
                  link_pos=np.tile(centre.astype(np.float32), (1, E, 1, 1)),
                  link_quat=np.tile(np.float32([0, 0, 0, 1]), (1, E, 1, 1)))
-        inst_expect = 0
     else:
         w = dict(terrain=(mesh + centre).astype(np.float32), link_tri=np.zeros((0, 3, 3), np.float32),
                  link_off=np.zeros(1, np.int64), link_pos=np.zeros((1, E, 0, 3), np.float32),
                  link_quat=np.zeros((1, E, 0, 4), np.float32))
-        inst_expect = 0
     w.update(E=E, C=1, W=1, H=1, cam_pos=cam_pos, cam_quat=cam_quat, intr=intr, far=10.0)
+    return w
+
+
+@pytest.mark.parametrize("as_link", [False, True])
+def test_watertight_vertices_and_edges(as_link):
+    """Decisions FP32 cannot make: the exact pass must take them (edge rays by
+    deciding the two undecided triangles, vertex rays by a full re-cast)."""
+    say(f"[render] watertight vertex/edge rays, mesh as {'link' if as_link else 'terrain'}")
+    w = watertight_scene(as_link)
     sc = make_scene(w)
     d, i, t = render(sc, w)
-    n_exact = sc.exact_count(E, 1, 1, 1)
-    say(f"  {E} rays, {n_exact} re-cast by the exact pass")
-    assert np.all(i.ravel() == inst_expect), "a ray slipped through an edge or vertex"
+    n_exact, n_full = sc.exact_count(w["E"], 1, 1, 1, recast=True)
+    say(f"  {w['E']} rays, {n_exact} sent to the exact pass, {n_full} of them re-cast in full")
+    assert np.all(i.ravel() == 0), "a ray slipped through an edge or vertex"
     ref = oracle_render(w)
     assert_parity(d, i, t, ref, w["far"], label="watertight")
-    assert n_exact > 0
+    assert n_full > 0 and n_exact - n_full > 0
+
+
+def test_exact_list_overflow_recasts_everything():
+    """More listed rays than the exact pass's list holds (4096 entries here):
+    every pixel is re-cast, with the same results."""
+    say("[render] exact-pass list overflow")
+    w = watertight_scene(False, repeat=5)
+    sc = make_scene(w)
+    d, i, t = render(sc, w)
+    n_exact = sc.exact_count(w["E"], 1, 1, 1)
+    say(f"  {w['E']} rays, {n_exact} listed")
+    assert n_exact > 4096
+    assert np.all(i.ravel() == 0)
+    ref = oracle_render(w)
+    assert_parity(d, i, t, ref, w["far"], label="overflow")
