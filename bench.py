@@ -343,6 +343,9 @@ def main():
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one plain device copy of this size first (HBM counter calibration)")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--schedule", default=None,
+                    help="fix the plain fast-pass schedule tile_w,tile_h,rays_per_lane,waves "
+                         "(no autotuning), e.g. to profile the schedule a full run chose")
     ap.add_argument("--no-batched", action="store_true", help="skip the uneven batched section")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving section")
     ap.add_argument("--serve-seconds", type=float, default=6.0)
@@ -400,7 +403,11 @@ def main():
         post.process(depth, inst, p, k, out=(pout, drop, lat))
 
     tuned = None
-    if not args.no_autotune:
+    if args.schedule:
+        tw, th, rpl, wv = (int(v) for v in args.schedule.split(","))
+        sc.set_config(batched=False, tile_w=tw, tile_h=th, rays_per_lane=rpl, waves=wv)
+        tuned = sc.config(batched=False)
+    elif not args.no_autotune:
         tuned, tuned_ms = sc.autotune(reps=2, cam_pos=cp, cam_quat=cq, intr=K, width=W, height=H,
                                       far_plane=w["far"], link_pos=lp_all[0], link_quat=lq_all[0],
                                       out=(depth, inst, tri))

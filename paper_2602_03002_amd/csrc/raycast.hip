@@ -595,12 +595,10 @@ __device__ __forceinline__ void cast_tile(const RenderLaunch& a, const TileCfg& 
     }
 }
 
-// Fast pass over the plain [env][cam][H][W] layout.  WAVES asks the compiler
-// for at least that many resident wavefronts per SIMD (fewer registers per
-// lane, maybe a few spills); the autotuner picks it and the tile schedule.
-template <int WAVES, int RPL, typename Cnt = NoCount>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES, 8)))
-k_render(RenderLaunch a, TileCfg c, int64_t n_logical, int64_t per_xcd) {
+// Fast pass over the plain [env][cam][H][W] layout, one wavefront tile.
+template <int RPL, typename Cnt>
+__device__ __forceinline__ void plain_tile(const RenderLaunch& a, const TileCfg& c, int64_t n_logical,
+                                           int64_t per_xcd) {
     // XCD-aware order: hardware deals blocks round-robin over the 8 XCDs, so
     // give each XCD a contiguous run of tiles (neighbouring environments share
     // terrain nodes in that XCD's L2).
@@ -616,7 +614,22 @@ k_render(RenderLaunch a, TileCfg c, int64_t n_logical, int64_t per_xcd) {
     if (ec >= (int64_t)a.n_env * a.n_cam) return;
     const int tin = (int)(tile - ec * tiles_img);
     cast_tile<RPL, Cnt>(a, c, plain_cam(a, ec), (int)(ec / a.n_cam), (uint32_t)ec, a.width, a.height,
-                   ec * (int64_t)a.width * a.height, tin % tiles_x, tin / tiles_x);
+                        ec * (int64_t)a.width * a.height, tin % tiles_x, tin / tiles_x);
+}
+
+// Fast pass.  WAVES asks the compiler for at least that many resident
+// wavefronts per SIMD (fewer registers per lane, maybe a few spills); the
+// autotuner picks it and the tile schedule.
+template <int WAVES, int RPL>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES, 8)))
+k_render(RenderLaunch a, TileCfg c, int64_t n_logical, int64_t per_xcd) {
+    plain_tile<RPL, NoCount>(a, c, n_logical, per_xcd);
+}
+
+// The fast pass with per-ray work counters (diagnostic render).
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8)))
+k_render_counts(RenderLaunch a, TileCfg c, int64_t n_logical, int64_t per_xcd) {
+    plain_tile<1, RayCount>(a, c, n_logical, per_xcd);
 }
 
 // Batched uneven form, setup: validate each camera descriptor, count its
@@ -858,7 +871,7 @@ hipError_t launch_render(const RenderLaunch& a, const RenderCfg& cfg, hipStream_
     const int v = a.counts ? 0 : 10 * cfg.waves + c.rpl;
     switch (v) {
         case 0:
-            hipLaunchKernelGGL((k_render<6, 1, RayCount>), grid, block, 0, s, a, c, n_logical, per_xcd);
+            hipLaunchKernelGGL(k_render_counts, grid, block, 0, s, a, c, n_logical, per_xcd);
             break;
         case 71: RC_PLAIN(7, 1); break;
         case 72: RC_PLAIN(7, 2); break;
