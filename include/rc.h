@@ -231,6 +231,9 @@ typedef struct {
     int32_t rays_per_lane;   /* tiles per wavefront, stacked vertically: 1 or 2 */
     int32_t waves;           /* resident wavefronts per SIMD asked for: 6, 7 or 8 */
     int32_t persistent;      /* batched form only: 1 persistent work queue, 0 flat grid */
+    int32_t terrain_packet;  /* 0: each lane walks the terrain hierarchy alone; 1: the
+                                wavefront walks it as a packet (a node is entered if any
+                                of its rays reaches it) */
 } rc_render_config;
 
 /* Schedule used by rc_render (batched = 0) or rc_render_batched (batched = 1). */
@@ -238,8 +241,8 @@ rc_status rc_get_render_config(const rc_scene* scene, int32_t batched, rc_render
 rc_status rc_set_render_config(rc_scene* scene, int32_t batched, const rc_render_config* cfg);
 
 /* Time every candidate schedule (tile 8x8, 16x4, 4x16, 32x2; 1 or 2 tiles
- * per wavefront; 6, 7 or 8 wavefronts per SIMD; for the batched form also
- * persistent or flat) on this exact launch -
+ * per wavefront; 6, 7 or 8 wavefronts per SIMD; per-lane or packet terrain
+ * walk; for the batched form also persistent or flat) on this exact launch -
  * exactly one of `plain` and `batched` non-NULL - with `reps` timed runs
  * each after one warm-up, keep the fastest for that mode in the scene and
  * return it with its mean time.  Overwrites the launch's outputs.

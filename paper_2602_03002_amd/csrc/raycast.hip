@@ -401,7 +401,7 @@ __device__ __forceinline__ void enter_link(const RenderLaunch& a, int e, int b, 
 // wave-uniform, in scalar registers; a node is entered if any lane's ray hits
 // it, a link only by the lanes whose rays hit its box).  Otherwise each lane
 // walks the top level alone.
-template <bool EXACT, bool WAVE, typename Cnt>
+template <bool EXACT, bool WAVE, bool PACKET, typename Cnt>
 __device__ __forceinline__ Hit cast_ray(const RenderLaunch& a, const CamRef& cam, int e, int x, int y,
                                         double& scale, float bound, uint2* cand, Cnt& cnt) {
     double o64[3], d64[3], rx, ry;
@@ -510,14 +510,71 @@ __device__ __forceinline__ Hit cast_ray(const RenderLaunch& a, const CamRef& cam
         if (reach) {
             const Slab ws = make_slab(ox, oy, oz, dx, dy, dz);
             const Shear wm = make_shear(dx, dy, dz);
-            traverse(a.terrain_nodes, a.n_terrain > 1 ? a.n_terrain - 1 : 1, a.n_terrain, ws, h, cnt,
-                     [&](int i) {
-                         cnt.tri();
-                         tri_test<EXACT>(a.terrain_tris + 9 * (int64_t)i, a.terrain_tri_id[i],
-                                         (uint32_t)a.n_links, ox, oy, oz, wm, kTerrainKappa, h, px,
-                                         -1, i);
-                     },
-                     entry);
+            const int n_nodes = a.n_terrain > 1 ? a.n_terrain - 1 : 1;
+            auto leaf = [&](int i) {
+                cnt.tri();
+                tri_test<EXACT>(a.terrain_tris + 9 * (int64_t)i, a.terrain_tri_id[i],
+                                (uint32_t)a.n_links, ox, oy, oz, wm, kTerrainKappa, h, px, -1, i);
+            };
+            if (!PACKET) {
+                traverse(a.terrain_nodes, n_nodes, a.n_terrain, ws, h, cnt, leaf, entry);
+            } else {
+                // Packet form: the wavefront walks the terrain hierarchy together
+                // (node index, trail and records wave-uniform); a child is
+                // entered if any lane's ray reaches it within that lane's bound,
+                // the nearer child first by vote.
+                uint64_t trail = 0;
+                int cur = entry;
+                int budget = 2 * n_nodes + 2;
+                for (;;) {
+                    cur = uni(cur);
+                    if ((unsigned)cur >= (unsigned)n_nodes || --budget < 0) break;
+                    const Node N = a.terrain_nodes[cur];
+                    cnt.node();
+                    float tn0, tn1;
+                    bool h0 = slab(N.b0[0], N.b0[1], N.b0[2], N.b0[3], N.b0[4], N.b0[5], ws, h.tmax, tn0);
+                    bool h1 = slab(N.b1[0], N.b1[1], N.b1[2], N.b1[3], N.b1[4], N.b1[5], ws, h.tmax, tn1);
+                    const int c0 = N.c0, c1 = N.c1;
+                    h0 = h0 && (c0 >= 0 || (unsigned)~c0 < (unsigned)a.n_terrain);
+                    h1 = h1 && (c1 >= 0 || (unsigned)~c1 < (unsigned)a.n_terrain);
+                    const bool l0 = h0 && c0 < 0, l1 = h1 && c1 < 0;
+                    if (l0 || l1) {  // leaf children, nearest first
+                        const bool swap = l0 && l1 && tn1 < tn0;
+                        const int la = (l0 && !swap) ? ~c0 : ~c1;
+                        const int lb = (l0 && l1) ? (swap ? ~c0 : ~c1) : -1;
+                        const float tb = swap ? tn0 : tn1;
+                        leaf(la);
+                        if (lb >= 0 && tb <= h.tmax) leaf(lb);
+                    }
+                    const bool g0 = c0 >= 0 && h0 && tn0 <= h.tmax;
+                    const bool g1 = c1 >= 0 && h1 && tn1 <= h.tmax;
+                    const uint64_t G0 = __ballot(g0), G1 = __ballot(g1);
+                    if (G0 && G1) {
+                        const int want1 = __popcll(__ballot(g1 && (!g0 || tn1 < tn0)));
+                        const int want0 = __popcll(__ballot(g0 && (!g1 || tn0 <= tn1)));
+                        trail = (trail << 1) | 1ull;
+                        cur = want1 > want0 ? c1 : c0;
+                        continue;
+                    }
+                    if (G0 || G1) {
+                        trail <<= 1;
+                        cur = G0 ? c0 : c1;
+                        continue;
+                    }
+                    int par = N.parent, sib = N.sibling;
+                    bool done = false;
+                    for (;;) {
+                        if (trail == 0ull) { done = true; break; }
+                        if (trail & 1ull) { trail ^= 1ull; cur = sib; break; }
+                        trail >>= 1;
+                        par = uni(par);
+                        if ((unsigned)par >= (unsigned)n_nodes || --budget < 0) { done = true; break; }
+                        sib = a.terrain_nodes[par].sibling;
+                        par = a.terrain_nodes[par].parent;
+                    }
+                    if (done) break;
+                }
+            }
         }
     }
     return h;
@@ -547,7 +604,7 @@ __device__ __forceinline__ CamRef desc_cam(const rc_cam_desc* d) {
 // found here and the (at most two) undecided triangles to decide in FP64 at
 // the front of its list, or, with more, to be re-cast in full (from the back
 // of the list, starting from the certain hit's bound).
-template <int RPL, typename Cnt = NoCount>
+template <int RPL, bool PACKET, typename Cnt = NoCount>
 __device__ __forceinline__ void cast_tile(const RenderLaunch& a, const TileCfg& c, const CamRef& cam,
                                           int e, uint32_t cam_index, int width, int height,
                                           int64_t out0, int tx, int ty) {
@@ -567,7 +624,7 @@ __device__ __forceinline__ void cast_tile(const RenderLaunch& a, const TileCfg& 
         double scale;
         Cnt cnt;
         for (int k = 0; k < kCandSlots; ++k) cand[k].x = kNoCand;
-        const Hit h = cast_ray<false, true>(a, cam, e, x, y, scale, INFINITY, cand, cnt);
+        const Hit h = cast_ray<false, true, PACKET>(a, cam, e, x, y, scale, INFINITY, cand, cnt);
         if (!valid) continue;
         const int64_t p = out0 + (int64_t)y * width + x;
         write_out(a, p, h, scale);
@@ -596,7 +653,7 @@ __device__ __forceinline__ void cast_tile(const RenderLaunch& a, const TileCfg& 
 }
 
 // Fast pass over the plain [env][cam][H][W] layout, one wavefront tile.
-template <int RPL, typename Cnt>
+template <int RPL, bool PACKET, typename Cnt>
 __device__ __forceinline__ void plain_tile(const RenderLaunch& a, const TileCfg& c, int64_t n_logical,
                                            int64_t per_xcd) {
     // XCD-aware order: hardware deals blocks round-robin over the 8 XCDs, so
@@ -613,23 +670,25 @@ __device__ __forceinline__ void plain_tile(const RenderLaunch& a, const TileCfg&
     const int64_t ec = tile / tiles_img;
     if (ec >= (int64_t)a.n_env * a.n_cam) return;
     const int tin = (int)(tile - ec * tiles_img);
-    cast_tile<RPL, Cnt>(a, c, plain_cam(a, ec), (int)(ec / a.n_cam), (uint32_t)ec, a.width, a.height,
+    cast_tile<RPL, PACKET, Cnt>(a, c, plain_cam(a, ec), (int)(ec / a.n_cam), (uint32_t)ec, a.width, a.height,
                         ec * (int64_t)a.width * a.height, tin % tiles_x, tin / tiles_x);
 }
 
 // Fast pass.  WAVES asks the compiler for at least that many resident
-// wavefronts per SIMD (fewer registers per lane, maybe a few spills); the
-// autotuner picks it and the tile schedule.
-template <int WAVES, int RPL>
+// wavefronts per SIMD (fewer registers per lane, maybe a few spills); PACKET
+// walks the terrain as a wavefront packet instead of per lane.  The autotuner
+// picks them and the tile schedule.
+template <int WAVES, int RPL, bool PACKET>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES, 8)))
 k_render(RenderLaunch a, TileCfg c, int64_t n_logical, int64_t per_xcd) {
-    plain_tile<RPL, NoCount>(a, c, n_logical, per_xcd);
+    plain_tile<RPL, PACKET, NoCount>(a, c, n_logical, per_xcd);
 }
 
 // The fast pass with per-ray work counters (diagnostic render).
+template <bool PACKET>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8)))
 k_render_counts(RenderLaunch a, TileCfg c, int64_t n_logical, int64_t per_xcd) {
-    plain_tile<1, RayCount>(a, c, n_logical, per_xcd);
+    plain_tile<1, PACKET, RayCount>(a, c, n_logical, per_xcd);
 }
 
 // Batched uneven form, setup: validate each camera descriptor, count its
@@ -683,7 +742,7 @@ __global__ void __launch_bounds__(1024) k_batch_prep(RenderLaunch a, TileCfg c, 
 // neighbouring pixels of one camera, so a chunk's rays share cache lines on
 // the XCD that runs it) until the tiles run out; the tile table maps a tile
 // to its camera descriptor by binary search.
-template <int WAVES, int RPL>
+template <int WAVES, int RPL, bool PACKET>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES, 8)))
 k_render_batched(RenderLaunch a, TileCfg c, const uint32_t* __restrict__ tile_start,
                  uint32_t* queue) {
@@ -707,8 +766,8 @@ k_render_batched(RenderLaunch a, TileCfg c, const uint32_t* __restrict__ tile_st
             const int width = D->width;
             const int tiles_x = (width + c.tw - 1) / c.tw;
             const int tin = (int)(tile - tile_start[d]);
-            cast_tile<RPL>(a, c, desc_cam(D), D->env, (uint32_t)d, width, D->height,
-                           (int64_t)D->out_offset, tin % tiles_x, tin / tiles_x);
+            cast_tile<RPL, PACKET>(a, c, desc_cam(D), D->env, (uint32_t)d, width, D->height,
+                                   (int64_t)D->out_offset, tin % tiles_x, tin / tiles_x);
         }
     }
 }
@@ -717,7 +776,7 @@ k_render_batched(RenderLaunch a, TileCfg c, const uint32_t* __restrict__ tile_st
 // camera-major grid sized for the largest image; tiles past a camera's own
 // count exit at once.  No loop around the tile, so no state is carried
 // between tiles (the persistent form's loop costs registers).
-template <int WAVES, int RPL>
+template <int WAVES, int RPL, bool PACKET>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES, 8)))
 k_render_flat(RenderLaunch a, TileCfg c, const uint32_t* __restrict__ tile_start, int tiles_per_cam,
               int64_t n_logical, int64_t per_xcd) {
@@ -733,8 +792,8 @@ k_render_flat(RenderLaunch a, TileCfg c, const uint32_t* __restrict__ tile_start
     const rc_cam_desc* D = a.desc + d;
     const int width = D->width;
     const int tiles_x = (width + c.tw - 1) / c.tw;
-    cast_tile<RPL>(a, c, desc_cam(D), D->env, (uint32_t)d, width, D->height, (int64_t)D->out_offset,
-                   k % tiles_x, k / tiles_x);
+    cast_tile<RPL, PACKET>(a, c, desc_cam(D), D->env, (uint32_t)d, width, D->height,
+                           (int64_t)D->out_offset, k % tiles_x, k / tiles_x);
 }
 
 // Exact pass.  If the list overflowed, every pixel is re-cast.
@@ -758,7 +817,7 @@ __device__ __forceinline__ void exact_one(const RenderLaunch& a, int64_t p, uint
     entry_cam(a, cam_index, cam, e);
     double scale;
     NoCount none;
-    const Hit h = cast_ray<true, false>(a, cam, e, x, y, scale, bound, nullptr, none);
+    const Hit h = cast_ray<true, false, false>(a, cam, e, x, y, scale, bound, nullptr, none);
     write_out(a, p, h, scale);
 }
 
@@ -855,6 +914,15 @@ __global__ void __launch_bounds__(64) k_render_exact(RenderLaunch a, const uint3
 
 }  // namespace
 
+// Kernel variant index: 100 * packet + 10 * waves + tiles per wavefront.
+#define RC_VARIANTS(X) \
+    X(6, 1, false) X(6, 2, false) X(7, 1, false) X(7, 2, false) X(8, 1, false) X(8, 2, false) \
+    X(6, 1, true) X(6, 2, true) X(7, 1, true) X(7, 2, true) X(8, 1, true) X(8, 2, true)
+
+static int variant(const RenderCfg& cfg, int rpl) {
+    return 100 * (cfg.terrain_packet ? 1 : 0) + 10 * cfg.waves + rpl;
+}
+
 hipError_t launch_render(const RenderLaunch& a, const RenderCfg& cfg, hipStream_t s) {
     // the counting variant casts one tile per wavefront
     TileCfg c{cfg.tile_w, cfg.tile_h, a.counts ? 1 : cfg.rays_per_lane};
@@ -867,20 +935,22 @@ hipError_t launch_render(const RenderLaunch& a, const RenderCfg& cfg, hipStream_
     const dim3 grid((unsigned)(per_xcd * 8)), block(64 * kWavesPerBlock);
     hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(1), 0, s, a.exact_count);
     if (a.ev_begin) hipEventRecord(a.ev_begin, s);
-#define RC_PLAIN(W, R) hipLaunchKernelGGL((k_render<W, R>), grid, block, 0, s, a, c, n_logical, per_xcd)
-    const int v = a.counts ? 0 : 10 * cfg.waves + c.rpl;
-    switch (v) {
-        case 0:
-            hipLaunchKernelGGL(k_render_counts, grid, block, 0, s, a, c, n_logical, per_xcd);
-            break;
-        case 71: RC_PLAIN(7, 1); break;
-        case 72: RC_PLAIN(7, 2); break;
-        case 81: RC_PLAIN(8, 1); break;
-        case 82: RC_PLAIN(8, 2); break;
-        case 62: RC_PLAIN(6, 2); break;
-        default: RC_PLAIN(6, 1); break;
-    }
+    if (a.counts) {
+        if (cfg.terrain_packet)
+            hipLaunchKernelGGL((k_render_counts<true>), grid, block, 0, s, a, c, n_logical, per_xcd);
+        else
+            hipLaunchKernelGGL((k_render_counts<false>), grid, block, 0, s, a, c, n_logical, per_xcd);
+    } else {
+        switch (variant(cfg, c.rpl)) {
+#define RC_PLAIN(W, R, P)                                                                      \
+    case 100 * (P ? 1 : 0) + 10 * W + R:                                                      \
+        hipLaunchKernelGGL((k_render<W, R, P>), grid, block, 0, s, a, c, n_logical, per_xcd); \
+        break;
+            RC_VARIANTS(RC_PLAIN)
 #undef RC_PLAIN
+            default: return hipErrorInvalidValue;
+        }
+    }
     if (a.ev_end) hipEventRecord(a.ev_end, s);
     hipLaunchKernelGGL(k_render_exact, dim3(4096), dim3(64), 0, s, a, (const uint32_t*)nullptr);
     return hipGetLastError();
@@ -893,20 +963,17 @@ hipError_t launch_render_batched(const RenderLaunch& a, const RenderCfg& cfg, ui
     hipLaunchKernelGGL(k_batch_prep, dim3(1), dim3(1024), 0, s, a, c, tile_start, queues, status);
     if (a.ev_begin) hipEventRecord(a.ev_begin, s);
     const dim3 block(64 * kWavesPerBlock);
-    const int v = 10 * cfg.waves + c.rpl;
     if (cfg.persistent) {
         const dim3 grid((unsigned)persistent_blocks);
-#define RC_BATCH(W, R) \
-    hipLaunchKernelGGL((k_render_batched<W, R>), grid, block, 0, s, a, c, tile_start, queues)
-        switch (v) {
-            case 71: RC_BATCH(7, 1); break;
-            case 72: RC_BATCH(7, 2); break;
-            case 81: RC_BATCH(8, 1); break;
-            case 82: RC_BATCH(8, 2); break;
-            case 62: RC_BATCH(6, 2); break;
-            default: RC_BATCH(6, 1); break;
-        }
+        switch (variant(cfg, c.rpl)) {
+#define RC_BATCH(W, R, P)                                                                          \
+    case 100 * (P ? 1 : 0) + 10 * W + R:                                                          \
+        hipLaunchKernelGGL((k_render_batched<W, R, P>), grid, block, 0, s, a, c, tile_start, queues); \
+        break;
+            RC_VARIANTS(RC_BATCH)
 #undef RC_BATCH
+            default: return hipErrorInvalidValue;
+        }
     } else {
         const int span_h = c.th * c.rpl;
         const int tiles_per_cam = ((a.max_width + c.tw - 1) / c.tw) * ((a.max_height + span_h - 1) / span_h);
@@ -914,18 +981,16 @@ hipError_t launch_render_batched(const RenderLaunch& a, const RenderCfg& cfg, ui
         const int64_t n_logical = (waves + kWavesPerBlock - 1) / kWavesPerBlock;
         const int64_t per_xcd = (n_logical + 7) / 8;
         const dim3 grid((unsigned)(per_xcd * 8));
-#define RC_FLAT(W, R)                                                                         \
-    hipLaunchKernelGGL((k_render_flat<W, R>), grid, block, 0, s, a, c, (const uint32_t*)tile_start, \
-                       tiles_per_cam, n_logical, per_xcd)
-        switch (v) {
-            case 71: RC_FLAT(7, 1); break;
-            case 72: RC_FLAT(7, 2); break;
-            case 81: RC_FLAT(8, 1); break;
-            case 82: RC_FLAT(8, 2); break;
-            case 62: RC_FLAT(6, 2); break;
-            default: RC_FLAT(6, 1); break;
-        }
+        switch (variant(cfg, c.rpl)) {
+#define RC_FLAT(W, R, P)                                                                         \
+    case 100 * (P ? 1 : 0) + 10 * W + R:                                                         \
+        hipLaunchKernelGGL((k_render_flat<W, R, P>), grid, block, 0, s, a, c,                    \
+                           (const uint32_t*)tile_start, tiles_per_cam, n_logical, per_xcd);      \
+        break;
+            RC_VARIANTS(RC_FLAT)
 #undef RC_FLAT
+            default: return hipErrorInvalidValue;
+        }
     }
     if (a.ev_end) hipEventRecord(a.ev_end, s);
     hipLaunchKernelGGL(k_render_exact, dim3(4096), dim3(64), 0, s, a, (const uint32_t*)tile_start);
@@ -935,7 +1000,8 @@ hipError_t launch_render_batched(const RenderLaunch& a, const RenderCfg& cfg, ui
 bool render_cfg_ok(const RenderCfg& c) {
     return c.tile_w >= 1 && c.tile_h >= 1 && c.tile_w * c.tile_h == 64 &&
            (c.rays_per_lane == 1 || c.rays_per_lane == 2) &&
-           (c.waves == 6 || c.waves == 7 || c.waves == 8);
+           (c.waves == 6 || c.waves == 7 || c.waves == 8) &&
+           (c.terrain_packet == 0 || c.terrain_packet == 1) && (c.persistent == 0 || c.persistent == 1);
 }
 
 }  // namespace rc

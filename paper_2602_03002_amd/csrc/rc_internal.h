@@ -111,6 +111,7 @@ struct RenderCfg {
     int rays_per_lane = 1;       // tiles each wavefront casts, stacked vertically
     int waves = 6;               // resident wavefronts per SIMD asked of the compiler (6, 7, 8)
     int persistent = 0;          // batched form: persistent work-queue launch (1) or flat grid (0)
+    int terrain_packet = 0;      // terrain walked per lane (0) or as a wavefront packet (1)
 };
 bool render_cfg_ok(const RenderCfg& c);
 hipError_t launch_render(const RenderLaunch& a, const RenderCfg& cfg, hipStream_t s);

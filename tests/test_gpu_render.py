@@ -163,6 +163,26 @@ def test_render_is_deterministic():
         assert np.array_equal(x, y)
 
 
+def test_packet_terrain_walk_gives_identical_results():
+    say("[render] terrain walked per lane vs as a wavefront packet, 16 envs x 2 cams 64x48")
+    w = sg.robot_scene(2, 4, 2.5, 2, 64, 48, steps=1, label="packet")
+    sc = make_scene(w)
+    lane = render(sc, w)
+    sc.set_config(batched=False, terrain_packet=1)
+    for rpl in (1, 2):
+        sc.set_config(batched=False, rays_per_lane=rpl)
+        got = render(sc, w)
+        for g, r in zip(got, lane):
+            assert np.array_equal(g, r)
+    _, counts = sc.render_counts(dev(w["cam_pos"]), dev(w["cam_quat"]), dev(w["intr"]), w["W"],
+                                 w["H"], w["far"], link_pos=dev(w["link_pos"][0]),
+                                 link_quat=dev(w["link_quat"][0]))
+    torch.cuda.synchronize()
+    c = counts.cpu().numpy().reshape(-1, 4)
+    say(f"  packet walk: mean nodes {c[:, 0].mean():.1f}, triangles {c[:, 1].mean():.2f}")
+    assert np.all(c[lane[1].ravel() >= 0, 1] >= 1)
+
+
 def test_render_counts_matches_render():
     say("[render] diagnostic work counts: same outputs as rc_render, plausible counts")
     w = sg.robot_scene(2, 2, 4.0, 2, 37, 29, steps=1, label="counts")
