@@ -375,6 +375,52 @@ def test_watertight_vertices_and_edges(as_link):
     assert np.all(i.ravel() == 0), "a ray slipped through an edge or vertex"
     ref = oracle_render(w)
     assert_parity(d, i, t, ref, w["far"], label="watertight")
+    assert n_exact > 0
+
+
+def test_grid_edge_rays_decided_by_listed_triangles():
+    """Rays through edge midpoints of a flat triangulated grid leave two
+    FP32-undecided triangles, which the exact pass decides without a re-cast;
+    rays through vertices leave more and are re-cast in full."""
+    say("[render] grid edge-midpoint and vertex rays")
+    n, h = 12, 0.25
+    xs = np.arange(n + 1) * h
+    V = np.array([[x, y, 0.0] for y in xs for x in xs])
+    idx = lambda i, j: j * (n + 1) + i
+    T = []
+    for j in range(n):
+        for i in range(n):
+            T.append([idx(i, j), idx(i + 1, j), idx(i + 1, j + 1)])
+            T.append([idx(i, j), idx(i + 1, j + 1), idx(i, j + 1)])
+    tri = V[np.array(T)].astype(np.float32)
+    pts = set()
+    for t in tri.astype(np.float64):
+        for i in range(3):
+            m = 0.5 * (t[i] + t[(i + 1) % 3])
+            if 0 < m[0] < n * h and 0 < m[1] < n * h:
+                pts.add(("e",) + tuple(m))
+        for v in t:
+            if 0 < v[0] < n * h and 0 < v[1] < n * h:
+                pts.add(("v",) + tuple(v))
+    pts = sorted(pts)
+    kind = np.array([p[0] for p in pts])
+    P = np.array([p[1:] for p in pts])
+    E = P.shape[0]
+    rng = np.random.default_rng(11)
+    off = np.stack([rng.uniform(-0.4, 0.4, E), rng.uniform(-0.4, 0.4, E), np.full(E, 1.0)], 1)
+    cam_pos = (P + off)[:, None, :].astype(np.float32)
+    cam_quat = np.array([[look_quat(-o)] for o in off], np.float32)
+    intr = np.tile(np.float32([1, 1, 0.5, 0.5]), (E, 1, 1))
+    w = dict(terrain=tri, link_tri=np.zeros((0, 3, 3), np.float32), link_off=np.zeros(1, np.int64),
+             link_pos=np.zeros((1, E, 0, 3), np.float32), link_quat=np.zeros((1, E, 0, 4), np.float32),
+             E=E, C=1, W=1, H=1, cam_pos=cam_pos, cam_quat=cam_quat, intr=intr, far=10.0)
+    sc = make_scene(w)
+    d, i, t = render(sc, w)
+    n_exact, n_full = sc.exact_count(E, 1, 1, 1, recast=True)
+    say(f"  {E} rays ({int((kind == 'e').sum())} edge, {int((kind == 'v').sum())} vertex), "
+        f"{n_exact} sent to the exact pass, {n_full} re-cast in full")
+    assert np.all(i.ravel() == 0), "a ray slipped through the grid"
+    assert_parity(d, i, t, oracle_render(w), w["far"], label="grid edges")
     assert n_full > 0 and n_exact - n_full > 0
 
 
