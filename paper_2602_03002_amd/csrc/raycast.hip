@@ -231,11 +231,14 @@ struct RayCount {
 
 // Test one triangle (leaf-order record v) against the ray (origin o, shear m).
 // FP32 decides when all three edge functions clearly share a sign (hit) or
-// clearly disagree (miss).  Otherwise the fast pass only records the plane
-// distance in h.tu (the ray is re-cast by the exact pass if that could beat
-// its final hit), and the exact pass repeats the test in FP64.
+// clearly disagree (miss).  Otherwise the fast pass keeps the triangle for the
+// exact pass (an LDS slot, or the ray is re-cast if they are full), which
+// repeats the test in FP64.  The hit distance is T * rcp(det) (a couple of
+// ulp; the same expression in both passes), the input triangle id is read
+// only for an accepted hit.
 template <bool EXACT>
-__device__ __forceinline__ void tri_test(const float* __restrict__ v, int32_t tri_id, uint32_t inst,
+__device__ __forceinline__ void tri_test(const float* __restrict__ v,
+                                         const int32_t* __restrict__ tri_ids, uint32_t inst,
                                          float ox, float oy, float oz, const Shear& m, float kappa,
                                          Hit& h, const PixelRef& px, int link, int leaf) {
     const float p0x = v[0] - ox, p0y = v[1] - oy, p0z = v[2] - oz;
@@ -251,19 +254,24 @@ __device__ __forceinline__ void tri_test(const float* __restrict__ v, int32_t tr
     const float V = __fmaf_rn(Ax, Cy, -(Ay * Cx));
     const float W = __fmaf_rn(Bx, Ay, -(By * Ax));
     const float thr = (fabsf(U) + fabsf(V) + fabsf(W)) * kappa;
-    const bool neg = (U < -thr) || (V < -thr) || (W < -thr);
-    const bool pos = (U > thr) || (V > thr) || (W > thr);
-    if (neg && pos) return;  // certainly outside
+    const float lo = fminf(fminf(U, V), W), hi = fmaxf(fmaxf(U, V), W);
+    if (lo < -thr && hi > thr) return;  // certainly outside
     // certain hit only when all three clear the margin with the same sign
-    const bool sure = thr > 0.0f && ((U > thr && V > thr && W > thr) || (U < -thr && V < -thr && W < -thr));
+    const bool sure = thr > 0.0f && (lo > thr || hi < -thr);
     float t;
-    if (!EXACT || sure) {
+    if (EXACT && !sure) {
+        double t64;
+        if (!refine(v, px.cam.pos, px.cam.quat, px.cam.intr, px.x, px.y, link, px.e, px.n_links,
+                    px.link_pos, px.link_quat, &t64))
+            return;
+        t = (float)t64;
+    } else {
         const float Az = __fmaf_rn(m.m3z, p0z, __fmaf_rn(m.m3y, p0y, m.m3x * p0x));
         const float Bz = __fmaf_rn(m.m3z, p1z, __fmaf_rn(m.m3y, p1y, m.m3x * p1x));
         const float Cz = __fmaf_rn(m.m3z, p2z, __fmaf_rn(m.m3y, p2y, m.m3x * p2x));
         const float det = U + V + W;
         const float T = __fmaf_rn(W, Cz, __fmaf_rn(V, Bz, U * Az));
-        t = T / det;
+        t = T * __builtin_amdgcn_rcpf(det);
         if (!EXACT && !sure) {
             // undecided in FP32: keep the triangle for the exact pass unless its
             // plane is behind the origin (well conditioned) or beyond the bound
@@ -285,32 +293,36 @@ __device__ __forceinline__ void tri_test(const float* __restrict__ v, int32_t tr
             h.tu = fminf(h.tu, tu);  // no free slot: the ray will be re-cast in full
             return;
         }
-    } else {
-        double t64;
-        if (!refine(v, px.cam.pos, px.cam.quat, px.cam.intr, px.x, px.y, link, px.e, px.n_links,
-                    px.link_pos, px.link_quat, &t64))
-            return;
-        t = (float)t64;
     }
-    if (!(t > 0.0f) || t > h.tmax) return;
-    const uint64_t key = ((uint64_t)inst << 32) | (uint32_t)tri_id;
-    if (t < h.tmax || key < h.key) {
-        h.tmax = t;
-        h.key = key;
+    if (t > 0.0f && t <= h.tmax) {
+        const uint64_t key = ((uint64_t)inst << 32) | (uint32_t)tri_ids[leaf];
+        const bool upd = t < h.tmax || key < h.key;
+        h.tmax = upd ? t : h.tmax;
+        h.key = upd ? key : h.key;
     }
 }
 
-// Per-lane stackless nearest-first traversal of the subtree at `start` of a
-// hierarchy of n_nodes records and n_prim leaves; `leaf(i)` handles leaf i.  Indices are range
+// Per-lane nearest-first traversal of the subtree at `start` of a hierarchy
+// of n_nodes records and n_prim leaves; `leaf(i)` handles leaf i.  A 64-bit
+// trail marks, per level below the start, whether the far child is still
+// pending.  With a short stack (stk: this lane's column of an LDS array,
+// kStack entries, stride kLanes), the pending far children of the shallowest
+// kStack such levels are kept there, so backtracking is a pop; a pending level
+// beyond them is reached by climbing the parent links stored in the records,
+// which is also the whole mechanism without a stack.  Indices are range
 // checked and the loop is bounded (a valid hierarchy needs fewer than
 // 2 n_nodes + 2 steps), so a corrupt hierarchy ends the ray instead of
 // faulting or spinning.
+constexpr int kStack = 12;
+constexpr int kLanes = 64 * kWavesPerBlock;
+
 template <typename Cnt, typename Leaf>
 __device__ __forceinline__ void traverse(const Node* __restrict__ nodes, int n_nodes, int n_prim,
                                          const Slab& r, Hit& h, Cnt& cnt, Leaf&& leaf,
-                                         int start = 0) {
+                                         int start = 0, uint32_t* stk = nullptr) {
     uint64_t trail = 0;
     int cur = start;
+    int sp = 0;  // far children kept on the stack (the shallowest pending levels)
     int budget = 2 * n_nodes + 2;
     for (;;) {
         if ((unsigned)cur >= (unsigned)n_nodes || --budget < 0) return;
@@ -339,8 +351,10 @@ __device__ __forceinline__ void traverse(const Node* __restrict__ nodes, int n_n
         const bool g0 = h0 && !l0 && tn0 <= h.tmax;
         const bool g1 = h1 && !l1 && tn1 <= h.tmax;
         if (g0 && g1) {
+            const bool first1 = tn1 < tn0;
             trail = (trail << 1) | 1ull;
-            cur = (tn1 < tn0) ? c1 : c0;
+            cur = first1 ? c1 : c0;
+            if (stk && sp < kStack) stk[kLanes * sp++] = (uint32_t)(first1 ? c0 : c1);
             continue;
         }
         if (g0 || g1) {
@@ -348,10 +362,15 @@ __device__ __forceinline__ void traverse(const Node* __restrict__ nodes, int n_n
             cur = g0 ? c0 : c1;
             continue;
         }
-        // backtrack to the deepest level whose other child is pending
+        if (trail == 0ull) return;
+        if (stk && __popcll(trail) == sp) {  // the deepest pending level is on the stack
+            trail = (trail >> __builtin_ctzll(trail)) ^ 1ull;
+            cur = (int)stk[kLanes * --sp];
+            continue;
+        }
+        // climb to the deepest level whose other child is pending
         int par = q3.z, sib = q3.w;
         for (;;) {
-            if (trail == 0ull) return;
             if (trail & 1ull) {
                 trail ^= 1ull;
                 cur = sib;
@@ -373,7 +392,7 @@ __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlan
 template <bool EXACT, typename Cnt>
 __device__ __forceinline__ void enter_link(const RenderLaunch& a, int e, int b, float ox, float oy,
                                            float oz, float dx, float dy, float dz, Hit& h,
-                                           const PixelRef& px, Cnt& cnt) {
+                                           const PixelRef& px, Cnt& cnt, uint32_t* stk) {
     cnt.inst();
     const InstXform X = a.xf[(int64_t)e * a.n_links + b];
     const float px_ = ox - X.t[0], py_ = oy - X.t[1], pz_ = oz - X.t[2];
@@ -390,9 +409,9 @@ __device__ __forceinline__ void enter_link(const RenderLaunch& a, int e, int b, 
     const int32_t* __restrict__ ids = a.link_tri_id + M.id_base;
     traverse(a.link_nodes + M.node_base, M.n_tri > 1 ? M.n_tri - 1 : 1, M.n_tri, ls, h, cnt, [&](int i) {
         cnt.tri();
-        tri_test<EXACT>(tris + 9 * (int64_t)i, ids[i], (uint32_t)b, lox, loy, loz, lm, kLinkKappa, h,
+        tri_test<EXACT>(tris + 9 * (int64_t)i, ids, (uint32_t)b, lox, loy, loz, lm, kLinkKappa, h,
                         px, b, i);
-    });
+    }, 0, stk);
 }
 
 // One pixel ray: robot bodies first, then the terrain under their bound
@@ -403,7 +422,8 @@ __device__ __forceinline__ void enter_link(const RenderLaunch& a, int e, int b, 
 // walks the top level alone.
 template <bool EXACT, bool WAVE, bool PACKET, typename Cnt>
 __device__ __forceinline__ Hit cast_ray(const RenderLaunch& a, const CamRef& cam, int e, int x, int y,
-                                        double& scale, float bound, uint2* cand, Cnt& cnt) {
+                                        double& scale, float bound, uint2* cand, uint32_t* stk,
+                                        Cnt& cnt) {
     double o64[3], d64[3], rx, ry;
     pixel_ray64(cam, x, y, o64, d64, rx, ry);
     const float ox = (float)o64[0], oy = (float)o64[1], oz = (float)o64[2];
@@ -421,7 +441,7 @@ __device__ __forceinline__ Hit cast_ray(const RenderLaunch& a, const CamRef& cam
         if (!WAVE) {
             const Slab ws = make_slab(ox, oy, oz, dx, dy, dz);
             traverse(tl, n_rec, a.n_links, ws, h, cnt, [&](int b) {
-                enter_link<EXACT>(a, e, b, ox, oy, oz, dx, dy, dz, h, px, cnt);
+                enter_link<EXACT>(a, e, b, ox, oy, oz, dx, dy, dz, h, px, cnt, nullptr);
             });
         } else {
             uint32_t trail = 0;
@@ -443,7 +463,7 @@ __device__ __forceinline__ Hit cast_ray(const RenderLaunch& a, const CamRef& cam
                     const int c = k == 0 ? c0 : c1;
                     const bool hk = k == 0 ? h0 : h1;
                     if (c >= 0 || __ballot(hk) == 0ull) continue;
-                    if (hk) enter_link<EXACT>(a, e, ~c, ox, oy, oz, dx, dy, dz, h, px, cnt);
+                    if (hk) enter_link<EXACT>(a, e, ~c, ox, oy, oz, dx, dy, dz, h, px, cnt, stk);
                 }
                 const bool g0 = c0 >= 0 && h0 && tn0 <= h.tmax;
                 const bool g1 = c1 >= 0 && h1 && tn1 <= h.tmax;
@@ -513,11 +533,11 @@ __device__ __forceinline__ Hit cast_ray(const RenderLaunch& a, const CamRef& cam
             const int n_nodes = a.n_terrain > 1 ? a.n_terrain - 1 : 1;
             auto leaf = [&](int i) {
                 cnt.tri();
-                tri_test<EXACT>(a.terrain_tris + 9 * (int64_t)i, a.terrain_tri_id[i],
+                tri_test<EXACT>(a.terrain_tris + 9 * (int64_t)i, a.terrain_tri_id,
                                 (uint32_t)a.n_links, ox, oy, oz, wm, kTerrainKappa, h, px, -1, i);
             };
             if (!PACKET) {
-                traverse(a.terrain_nodes, n_nodes, a.n_terrain, ws, h, cnt, leaf, entry);
+                traverse(a.terrain_nodes, n_nodes, a.n_terrain, ws, h, cnt, leaf, entry, stk);
             } else {
                 // Packet form: the wavefront walks the terrain hierarchy together
                 // (node index, trail and records wave-uniform); a child is
@@ -611,8 +631,10 @@ __device__ __forceinline__ void cast_tile(const RenderLaunch& a, const TileCfg& 
     const int lane = threadIdx.x & 63;
     const int span_h = c.th * RPL;
     const int xt = tx * c.tw + (lane % c.tw);
-    __shared__ uint2 s_cand[64 * kWavesPerBlock * kCandSlots];
+    __shared__ uint2 s_cand[kLanes * kCandSlots];
+    __shared__ uint32_t s_stack[kLanes * kStack];
     uint2* cand = s_cand + kCandSlots * threadIdx.x;
+    uint32_t* stk = s_stack + threadIdx.x;
 #pragma unroll
     for (int r = 0; r < RPL; ++r) {
         const int y0 = ty * span_h + r * c.th;
@@ -624,7 +646,7 @@ __device__ __forceinline__ void cast_tile(const RenderLaunch& a, const TileCfg& 
         double scale;
         Cnt cnt;
         for (int k = 0; k < kCandSlots; ++k) cand[k].x = kNoCand;
-        const Hit h = cast_ray<false, true, PACKET>(a, cam, e, x, y, scale, INFINITY, cand, cnt);
+        const Hit h = cast_ray<false, true, PACKET>(a, cam, e, x, y, scale, INFINITY, cand, stk, cnt);
         if (!valid) continue;
         const int64_t p = out0 + (int64_t)y * width + x;
         write_out(a, p, h, scale);
@@ -817,7 +839,7 @@ __device__ __forceinline__ void exact_one(const RenderLaunch& a, int64_t p, uint
     entry_cam(a, cam_index, cam, e);
     double scale;
     NoCount none;
-    const Hit h = cast_ray<true, false, false>(a, cam, e, x, y, scale, bound, nullptr, none);
+    const Hit h = cast_ray<true, false, false>(a, cam, e, x, y, scale, bound, nullptr, nullptr, none);
     write_out(a, p, h, scale);
 }
 
