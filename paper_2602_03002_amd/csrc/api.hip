@@ -247,12 +247,15 @@ rc_status rc_robot_meshes(rc_scene* scene, const float* link_tri, const int64_t*
 // the exact pass's counter and bounded list, and for the batched form the
 // tile table, the eight per-XCD queue counters (64 bytes apart) and a status word.
 struct RenderWs {
-    size_t xf, count, list, tiles, queues, status, end;
+    size_t xf, count, list, tiles, queues, status, cams, end;
     int64_t cap;
 };
 
+// n_cams: cameras of the launch (n_env * n_cam, or the descriptors); their ray
+// bases come last, so the offsets before them depend on n_env, n_pixels and
+// n_desc only.
 static RenderWs render_layout(int64_t n_env, int64_t n_pixels, int32_t n_links, int64_t n_desc,
-                              int64_t cap_rays = -1) {
+                              int64_t n_cams, int64_t cap_rays = -1) {
     RenderWs L;
     size_t o = 0;
     if (n_links > 0) {
@@ -277,6 +280,8 @@ static RenderWs render_layout(int64_t n_env, int64_t n_pixels, int32_t n_links, 
     o = align_up(o + 8 * 64);
     L.status = o;
     o = align_up(o + 4);
+    L.cams = o;
+    o = align_up(o + (size_t)n_cams * 16 * sizeof(double));
     L.end = o;
     return L;
 }
@@ -294,7 +299,8 @@ rc_status rc_render_size(const rc_scene* scene, int32_t n_env, int32_t n_cam, in
     if (!render_dims_ok(n_env, n_cam, width, height))
         return fail(RC_ERR_INVALID_ARG, "rc_render_size: sizes must be >= 1, width and height "
                                         "<= 65535, at most 2^32 - 1 rays");
-    *ws_bytes = render_layout(n_env, (int64_t)n_env * n_cam * width * height, scene->n_links, 0).end;
+    *ws_bytes = render_layout(n_env, (int64_t)n_env * n_cam * width * height, scene->n_links, 0,
+                              (int64_t)n_env * n_cam).end;
     return RC_OK;
 }
 
@@ -327,7 +333,7 @@ static rc_status prep_plain(const rc_scene* scene, const rc_render_args* a, void
     if (a->depth_mode != RC_DEPTH_PLANAR && a->depth_mode != RC_DEPTH_RANGE)
         return fail(RC_ERR_INVALID_ARG, w + ": unknown depth_mode");
     const int64_t n_rays = (int64_t)a->n_env * a->n_cam * a->width * a->height;
-    const RenderWs W = render_layout(a->n_env, n_rays, scene->n_links, 0);
+    const RenderWs W = render_layout(a->n_env, n_rays, scene->n_links, 0, (int64_t)a->n_env * a->n_cam);
     if (!ws || ws_bytes < W.end || !aligned(ws))
         return fail(RC_ERR_WORKSPACE, w + ": workspace needs " + std::to_string(W.end) +
                                           " bytes, 256-byte aligned");
@@ -351,6 +357,7 @@ static rc_status prep_plain(const rc_scene* scene, const rc_render_args* a, void
     L.exact_count = (uint32_t*)((char*)ws + W.count);
     L.exact_list = (uint4*)((char*)ws + W.list);
     L.exact_cap = W.cap;
+    L.cam_basis = (double*)((char*)ws + W.cams);
     L.ev_begin = a->timing ? (hipEvent_t)a->timing[0] : nullptr;
     L.ev_end = a->timing ? (hipEvent_t)a->timing[1] : nullptr;
     L.desc = nullptr;
@@ -407,7 +414,7 @@ rc_status rc_render_batched_size(const rc_scene* scene, int32_t n_env, int32_t n
     if (!batch_dims_ok(n_env, n_desc, n_pixels))
         return fail(RC_ERR_INVALID_ARG, "rc_render_batched_size: need n_env >= 1, 1 <= n_desc <= "
                                         "2^24, 1 <= n_pixels <= 2^32 - 1");
-    *ws_bytes = render_layout(n_env, n_pixels, scene->n_links, n_desc).end;
+    *ws_bytes = render_layout(n_env, n_pixels, scene->n_links, n_desc, n_desc).end;
     return RC_OK;
 }
 
@@ -444,7 +451,7 @@ static rc_status prep_batched(const rc_scene* scene, const rc_batch_args* a, voi
         return fail(RC_ERR_INVALID_ARG, w + ": far_plane must be finite and > 0");
     if (a->depth_mode != RC_DEPTH_PLANAR && a->depth_mode != RC_DEPTH_RANGE)
         return fail(RC_ERR_INVALID_ARG, w + ": unknown depth_mode");
-    W = render_layout(a->n_env, a->n_pixels, scene->n_links, a->n_desc, cap_rays);
+    W = render_layout(a->n_env, a->n_pixels, scene->n_links, a->n_desc, a->n_desc, cap_rays);
     if (!ws || ws_bytes < W.end || !aligned(ws))
         return fail(RC_ERR_WORKSPACE, w + ": workspace needs " + std::to_string(W.end) +
                                           " bytes, 256-byte aligned");
@@ -465,6 +472,7 @@ static rc_status prep_batched(const rc_scene* scene, const rc_batch_args* a, voi
     L.exact_count = (uint32_t*)((char*)ws + W.count);
     L.exact_list = (uint4*)((char*)ws + W.list);
     L.exact_cap = W.cap;
+    L.cam_basis = (double*)((char*)ws + W.cams);
     L.ev_begin = a->timing ? (hipEvent_t)a->timing[0] : nullptr;
     L.ev_end = a->timing ? (hipEvent_t)a->timing[1] : nullptr;
     L.desc = a->desc;
@@ -504,7 +512,7 @@ rc_status rc_render_batched_status(const rc_scene* scene, const rc_batch_args* a
     if (!scene || !a || !ws || !status) return fail(RC_ERR_INVALID_ARG, "rc_render_batched_status: NULL");
     if (!batch_dims_ok(a->n_env, a->n_desc, a->n_pixels))
         return fail(RC_ERR_INVALID_ARG, "rc_render_batched_status: bad sizes");
-    const RenderWs W = render_layout(a->n_env, a->n_pixels, scene->n_links, a->n_desc);
+    const RenderWs W = render_layout(a->n_env, a->n_pixels, scene->n_links, a->n_desc, a->n_desc);
     uint32_t v[3] = {0, 0, 0};
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = hipMemcpyAsync(&v[0], (const char*)ws + W.status, 4, hipMemcpyDeviceToHost, s);
@@ -656,7 +664,8 @@ rc_status rc_render_exact_count(const rc_scene* scene, int32_t n_env, int32_t n_
     if (!scene || !ws || !count) return fail(RC_ERR_INVALID_ARG, "rc_render_exact_count: NULL pointer");
     if (!render_dims_ok(n_env, n_cam, width, height))
         return fail(RC_ERR_INVALID_ARG, "rc_render_exact_count: bad sizes");
-    const RenderWs W = render_layout(n_env, (int64_t)n_env * n_cam * width * height, scene->n_links, 0);
+    const RenderWs W = render_layout(n_env, (int64_t)n_env * n_cam * width * height, scene->n_links, 0,
+                                     (int64_t)n_env * n_cam);
     uint32_t c[2] = {0, 0};
     hipError_t e = hipMemcpyAsync(c, (const char*)ws + W.count, 8, hipMemcpyDeviceToHost,
                                   (hipStream_t)stream);
@@ -869,7 +878,7 @@ rc_status rc_bvh_layout_of(const rc_scene* scene, int32_t which, rc_bvh_layout* 
 namespace rc {
 
 size_t batched_ws_bytes(const rc_scene* scene, int64_t n_env, int64_t n_desc, int64_t cap_rays) {
-    return render_layout(n_env, 1, scene->n_links, n_desc, cap_rays).end;
+    return render_layout(n_env, 1, scene->n_links, n_desc, n_desc, cap_rays).end;
 }
 
 rc_status enqueue_batched(const rc_scene* scene, const rc_batch_args* a, int64_t cap_rays, void* ws,

@@ -21,6 +21,8 @@
 // to zero to be decided in FP32 is repeated in FP64 from the FP64 ray (full
 // rate on CDNA), so hit decisions agree with exact arithmetic except for
 // rays within ~1e-12 of an edge.
+#include <algorithm>
+
 #include "rc_internal.h"
 
 #pragma clang fp contract(off)
@@ -137,39 +139,48 @@ __device__ __forceinline__ void quat_mat64(const float* __restrict__ q, double R
     R[6] = 2 * (x * z - y * w); R[7] = 2 * (y * z + x * w); R[8] = 1 - 2 * (x * x + y * y);
 }
 
-// A camera: centre p_c [3], quaternion q_c [4] (optical -> world), intrinsics
-// (fx, fy, cx, cy) [4]; either rows of the plain [env][cam] arrays or fields
-// of a batched camera descriptor.
+// A camera's FP64 ray basis (16 doubles, written once per launch by
+// k_cam_prep from the camera's centre p_c, quaternion q_c (optical -> world)
+// and intrinsics (fx, fy, cx, cy)): R(q_c) row-major [9], p_c [3], 1/fx, 1/fy,
+// cx, cy.
 struct CamRef {
-    const float* pos;
-    const float* quat;
-    const float* intr;
+    const double* b;
 };
+constexpr int kCamBasis = 16;
+
+__device__ __forceinline__ void cam_basis(const float* pos, const float* quat, const float* intr,
+                                          double* b) {
+    double R[9];
+    quat_mat64(quat, R);
+    for (int k = 0; k < 9; ++k) b[k] = R[k];
+    b[9] = pos[0]; b[10] = pos[1]; b[11] = pos[2];
+    b[12] = 1.0 / (double)intr[0];
+    b[13] = 1.0 / (double)intr[1];
+    b[14] = intr[2];
+    b[15] = intr[3];
+}
 
 // FP64 camera ray of pixel (x, y): o = p_c, d = R(q_c) K^-1 [x+.5, y+.5, 1].
 __device__ __forceinline__ void pixel_ray64(const CamRef& cam, int x, int y, double o[3],
                                             double d[3], double& rx, double& ry) {
-    const float* K = cam.intr;
-    rx = ((double)x + 0.5 - (double)K[2]) / (double)K[0];
-    ry = ((double)y + 0.5 - (double)K[3]) / (double)K[1];
-    double R[9];
-    quat_mat64(cam.quat, R);
-    d[0] = R[0] * rx + R[1] * ry + R[2];
-    d[1] = R[3] * rx + R[4] * ry + R[5];
-    d[2] = R[6] * rx + R[7] * ry + R[8];
-    o[0] = cam.pos[0]; o[1] = cam.pos[1]; o[2] = cam.pos[2];
+    const double* b = cam.b;
+    rx = ((double)x + 0.5 - b[14]) * b[12];
+    ry = ((double)y + 0.5 - b[15]) * b[13];
+    d[0] = b[0] * rx + b[1] * ry + b[2];
+    d[1] = b[3] * rx + b[4] * ry + b[5];
+    d[2] = b[6] * rx + b[7] * ry + b[8];
+    o[0] = b[9]; o[1] = b[10]; o[2] = b[11];
 }
 
 // The exact-decision path: rebuild the pixel's FP64 ray (and its FP64 link-frame
 // ray for link >= 0) and repeat the triangle test in FP64.  Rarely taken, so it
 // recomputes everything instead of keeping an FP64 ray live in registers.
-__device__ __noinline__ bool refine(const float* __restrict__ v, const float* cam_pos,
-                                    const float* cam_quat, const float* cam_intr, int x, int y,
+__device__ __noinline__ bool refine(const float* __restrict__ v, const double* cam, int x, int y,
                                     int link, int e, int n_links,
                                     const float* __restrict__ link_pos,
                                     const float* __restrict__ link_quat, double* t) {
     double o[3], d[3], rx, ry;
-    pixel_ray64(CamRef{cam_pos, cam_quat, cam_intr}, x, y, o, d, rx, ry);
+    pixel_ray64(CamRef{cam}, x, y, o, d, rx, ry);
     if (link >= 0) {
         const int64_t eb = (int64_t)e * n_links + link;
         double R[9];
@@ -261,7 +272,7 @@ __device__ __forceinline__ void tri_test(const float* __restrict__ v,
     float t;
     if (EXACT && !sure) {
         double t64;
-        if (!refine(v, px.cam.pos, px.cam.quat, px.cam.intr, px.x, px.y, link, px.e, px.n_links,
+        if (!refine(v, px.cam.b, px.x, px.y, link, px.e, px.n_links,
                     px.link_pos, px.link_quat, &t64))
             return;
         t = (float)t64;
@@ -422,15 +433,16 @@ __device__ __forceinline__ void enter_link(const RenderLaunch& a, int e, int b, 
 // walks the top level alone.
 template <bool EXACT, bool WAVE, bool PACKET, typename Cnt>
 __device__ __forceinline__ Hit cast_ray(const RenderLaunch& a, const CamRef& cam, int e, int x, int y,
-                                        double& scale, float bound, uint2* cand, uint32_t* stk,
+                                        float bound, uint2* cand, uint32_t* stk,
                                         Cnt& cnt) {
     double o64[3], d64[3], rx, ry;
     pixel_ray64(cam, x, y, o64, d64, rx, ry);
     const float ox = (float)o64[0], oy = (float)o64[1], oz = (float)o64[2];
     const float dx = (float)d64[0], dy = (float)d64[1], dz = (float)d64[2];
-    scale = a.depth_mode == RC_DEPTH_RANGE ? sqrt(rx * rx + ry * ry + 1.0) : 1.0;
+    const double scale = a.depth_mode == RC_DEPTH_RANGE ? sqrt(rx * rx + ry * ry + 1.0) : 1.0;
     Hit h;
-    h.tmax = fminf((float)((double)a.far_plane / scale), bound);
+    h.tmax = fminf(a.depth_mode == RC_DEPTH_RANGE ? (float)((double)a.far_plane / scale) : a.far_plane,
+                   bound);
     h.key = ~0ull;
     h.tu = INFINITY;
     const PixelRef px{cam, a.link_pos, a.link_quat, x, y, e, a.n_links, cand};
@@ -600,20 +612,40 @@ __device__ __forceinline__ Hit cast_ray(const RenderLaunch& a, const CamRef& cam
     return h;
 }
 
+// Output of one ray: planar depth is the ray parameter; range depth scales it
+// by |K^-1 [x + .5, y + .5, 1]| (recomputed here rather than kept live).
 __device__ __forceinline__ void write_out(const RenderLaunch& a, int64_t p, const Hit& h,
-                                          double scale) {
+                                          const CamRef& cam, int x, int y) {
     const bool hit = h.key != ~0ull;
-    a.depth[p] = hit ? (float)((double)h.tmax * scale) : a.far_plane;
+    float depth = h.tmax;
+    if (a.depth_mode == RC_DEPTH_RANGE) {
+        const double rx = ((double)x + 0.5 - cam.b[14]) * cam.b[12];
+        const double ry = ((double)y + 0.5 - cam.b[15]) * cam.b[13];
+        depth = (float)((double)h.tmax * sqrt(rx * rx + ry * ry + 1.0));
+    }
+    a.depth[p] = hit ? depth : a.far_plane;
     if (a.inst) a.inst[p] = hit ? (int32_t)(h.key >> 32) : -1;
     if (a.tri) a.tri[p] = hit ? (int32_t)(uint32_t)h.key : -1;
 }
 
-__device__ __forceinline__ CamRef plain_cam(const RenderLaunch& a, int64_t ec) {
-    return CamRef{a.cam_pos + 3 * ec, a.cam_quat + 4 * ec, a.intr + 4 * ec};
+// Camera `index` of the launch: (env * n_cam + cam) in the plain form, the
+// descriptor's index in the batched form.
+__device__ __forceinline__ CamRef launch_cam(const RenderLaunch& a, int64_t index) {
+    return CamRef{a.cam_basis + kCamBasis * index};
 }
 
-__device__ __forceinline__ CamRef desc_cam(const rc_cam_desc* d) {
-    return CamRef{d->pos, d->quat, d->intr};
+// Ray bases of every camera of the launch.
+__global__ void k_cam_prep(RenderLaunch a, int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        if (a.desc) {
+            const rc_cam_desc& D = a.desc[i];
+            cam_basis(D.pos, D.quat, D.intr, a.cam_basis + kCamBasis * i);
+        } else {
+            cam_basis(a.cam_pos + 3 * i, a.cam_quat + 4 * i, a.intr + 4 * i,
+                      a.cam_basis + kCamBasis * i);
+        }
+    }
 }
 
 // Cast the rpl stacked tw x th sub-tiles of one wavefront tile of an image
@@ -643,13 +675,12 @@ __device__ __forceinline__ void cast_tile(const RenderLaunch& a, const TileCfg& 
         const bool valid = xt < width && yt < height;
         const int x = xt < width ? xt : width - 1;
         const int y = yt < height ? yt : height - 1;
-        double scale;
         Cnt cnt;
         for (int k = 0; k < kCandSlots; ++k) cand[k].x = kNoCand;
-        const Hit h = cast_ray<false, true, PACKET>(a, cam, e, x, y, scale, INFINITY, cand, stk, cnt);
+        const Hit h = cast_ray<false, true, PACKET>(a, cam, e, x, y, INFINITY, cand, stk, cnt);
         if (!valid) continue;
         const int64_t p = out0 + (int64_t)y * width + x;
-        write_out(a, p, h, scale);
+        write_out(a, p, h, cam, x, y);
         if constexpr (Cnt::kOn)
             reinterpret_cast<uint4*>(a.counts)[p] = make_uint4(cnt.n, cnt.t, cnt.i, 0u);
         const float lim = h.tmax * kUndecidedSlack;
@@ -692,7 +723,7 @@ __device__ __forceinline__ void plain_tile(const RenderLaunch& a, const TileCfg&
     const int64_t ec = tile / tiles_img;
     if (ec >= (int64_t)a.n_env * a.n_cam) return;
     const int tin = (int)(tile - ec * tiles_img);
-    cast_tile<RPL, PACKET, Cnt>(a, c, plain_cam(a, ec), (int)(ec / a.n_cam), (uint32_t)ec, a.width, a.height,
+    cast_tile<RPL, PACKET, Cnt>(a, c, launch_cam(a, ec), (int)(ec / a.n_cam), (uint32_t)ec, a.width, a.height,
                         ec * (int64_t)a.width * a.height, tin % tiles_x, tin / tiles_x);
 }
 
@@ -788,7 +819,7 @@ k_render_batched(RenderLaunch a, TileCfg c, const uint32_t* __restrict__ tile_st
             const int width = D->width;
             const int tiles_x = (width + c.tw - 1) / c.tw;
             const int tin = (int)(tile - tile_start[d]);
-            cast_tile<RPL, PACKET>(a, c, desc_cam(D), D->env, (uint32_t)d, width, D->height,
+            cast_tile<RPL, PACKET>(a, c, launch_cam(a, d), D->env, (uint32_t)d, width, D->height,
                                    (int64_t)D->out_offset, tin % tiles_x, tin / tiles_x);
         }
     }
@@ -814,7 +845,7 @@ k_render_flat(RenderLaunch a, TileCfg c, const uint32_t* __restrict__ tile_start
     const rc_cam_desc* D = a.desc + d;
     const int width = D->width;
     const int tiles_x = (width + c.tw - 1) / c.tw;
-    cast_tile<RPL, PACKET>(a, c, desc_cam(D), D->env, (uint32_t)d, width, D->height,
+    cast_tile<RPL, PACKET>(a, c, launch_cam(a, d), D->env, (uint32_t)d, width, D->height,
                            (int64_t)D->out_offset, k % tiles_x, k / tiles_x);
 }
 
@@ -823,10 +854,10 @@ __device__ __forceinline__ void entry_cam(const RenderLaunch& a, uint32_t cam_in
                                           int& e) {
     if (a.desc) {
         const rc_cam_desc* D = a.desc + cam_index;
-        cam = desc_cam(D);
+        cam = launch_cam(a, cam_index);
         e = D->env;
     } else {
-        cam = plain_cam(a, cam_index);
+        cam = launch_cam(a, cam_index);
         e = (int)(cam_index / (uint32_t)a.n_cam);
     }
 }
@@ -837,10 +868,9 @@ __device__ __forceinline__ void exact_one(const RenderLaunch& a, int64_t p, uint
     CamRef cam;
     int e;
     entry_cam(a, cam_index, cam, e);
-    double scale;
     NoCount none;
-    const Hit h = cast_ray<true, false, false>(a, cam, e, x, y, scale, bound, nullptr, nullptr, none);
-    write_out(a, p, h, scale);
+    const Hit h = cast_ray<true, false, false>(a, cam, e, x, y, bound, nullptr, nullptr, none);
+    write_out(a, p, h, cam, x, y);
 }
 
 // Decide a listed ray's undecided triangles in FP64 and merge them with the
@@ -851,9 +881,6 @@ __device__ __forceinline__ void resolve_one(const RenderLaunch& a, const uint4 h
     int e;
     entry_cam(a, head.y, cam, e);
     const int x = (int)(head.z & 0xFFFFu), y = (int)(head.z >> 16);
-    double o[3], d[3], rx, ry;
-    pixel_ray64(cam, x, y, o, d, rx, ry);
-    const double scale = a.depth_mode == RC_DEPTH_RANGE ? sqrt(rx * rx + ry * ry + 1.0) : 1.0;
     Hit h;
     h.tmax = __uint_as_float(head.w);
     h.key = ((uint64_t)rest.y << 32) | rest.x;
@@ -880,7 +907,7 @@ __device__ __forceinline__ void resolve_one(const RenderLaunch& a, const uint4 h
             inst = (uint32_t)link;
         }
         double t64;
-        if (!refine(v, cam.pos, cam.quat, cam.intr, x, y, link, e, a.n_links, a.link_pos,
+        if (!refine(v, cam.b, x, y, link, e, a.n_links, a.link_pos,
                     a.link_quat, &t64))
             continue;
         const float t = (float)t64;
@@ -891,7 +918,7 @@ __device__ __forceinline__ void resolve_one(const RenderLaunch& a, const uint4 h
             h.key = key;
         }
     }
-    write_out(a, head.x, h, scale);
+    write_out(a, head.x, h, cam, x, y);
 }
 
 __global__ void k_zero_count(uint32_t* c) { c[0] = c[1] = 0u; }
@@ -956,6 +983,9 @@ hipError_t launch_render(const RenderLaunch& a, const RenderCfg& cfg, hipStream_
     const int64_t per_xcd = (n_logical + 7) / 8;
     const dim3 grid((unsigned)(per_xcd * 8)), block(64 * kWavesPerBlock);
     hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(1), 0, s, a.exact_count);
+    const int64_t n_cams = (int64_t)a.n_env * a.n_cam;
+    hipLaunchKernelGGL(k_cam_prep, dim3((unsigned)std::min<int64_t>((n_cams + 255) / 256, 4096)),
+                       dim3(256), 0, s, a, n_cams);
     if (a.ev_begin) hipEventRecord(a.ev_begin, s);
     if (a.counts) {
         if (cfg.terrain_packet)
@@ -983,6 +1013,8 @@ hipError_t launch_render_batched(const RenderLaunch& a, const RenderCfg& cfg, ui
                                  hipStream_t s) {
     TileCfg c{cfg.tile_w, cfg.tile_h, cfg.rays_per_lane};
     hipLaunchKernelGGL(k_batch_prep, dim3(1), dim3(1024), 0, s, a, c, tile_start, queues, status);
+    hipLaunchKernelGGL(k_cam_prep, dim3((unsigned)std::min<int64_t>((a.n_desc + 255) / 256, 4096)),
+                       dim3(256), 0, s, a, (int64_t)a.n_desc);
     if (a.ev_begin) hipEventRecord(a.ev_begin, s);
     const dim3 block(64 * kWavesPerBlock);
     if (cfg.persistent) {

@@ -96,6 +96,7 @@ struct RenderLaunch {
     uint32_t* exact_count;
     uint4* exact_list;
     int64_t exact_cap;  // entries
+    double* cam_basis;        // workspace: FP64 ray basis of every camera (16 doubles each)
     const rc_cam_desc* desc;  // batched form: camera descriptors (NULL: plain layout)
     int n_desc;
     int max_width, max_height;  // batched form: largest image a descriptor may have
