@@ -123,7 +123,7 @@ def traversal_report(sc, kw, ref):
     surface-area cost of its terrain hierarchy, beside the reference's."""
     import torch
     _, counts = sc.render_counts(**kw)
-    c = counts.view(-1, 4)[:, :3].double().mean(0).tolist()
+    c = counts.view(-1, 4).double().mean(0).tolist()
     lay = sc.bvh_layout(-1)
     m = int(lay.n_nodes)
     rec = sc.ws.view()[lay.node_offset:lay.node_offset + 64 * m].view(torch.float32).view(m, 16)
@@ -135,7 +135,8 @@ def traversal_report(sc, kw, ref):
     # one triangle per leaf and C_trav = C_tri = 1: every child box weighs 1
     sah = float((a_root + area.sum()) / a_root)
     del counts, rec, b, ext, area
-    own = {"node": round(c[0], 3), "tri": round(c[1], 3), "inst": round(c[2], 3)}
+    own = {"node": round(c[0], 3), "tri": round(c[1], 3), "inst": round(c[2], 3),
+           "link_node": round(c[3], 3)}
     own["bytes_per_ray"] = round(12 + 56 * c[0] + 36 * c[1] + 28 * c[2], 1)
     out = {"own": own, "sah_cost_terrain_own": round(sah, 3)}
     if ref is not None:

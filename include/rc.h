@@ -153,7 +153,8 @@ rc_status rc_render_exact_count(const rc_scene* scene, int32_t n_env, int32_t n_
 /* Diagnostic render: rc_render (same workspace, same outputs) whose fast
  * pass also writes, per ray, the work it did as uint32 [n_env][n_cam]
  * [height][width][4] = (node records whose child boxes the ray's lane
- * tested, triangles tested, link instances entered, 0) into `counts`
+ * tested, triangles tested, link instances entered, the part of the node
+ * records that belong to link hierarchies) into `counts`
  * (device, 16-byte aligned, caller owned).  Node records read by a
  * wavefront's shared top-level walk and terrain entry descent count once per
  * lane.  The exact pass's re-casts are not counted.  The fast pass runs

@@ -53,9 +53,12 @@ struct Shear {  // rows of the watertight shear: x' = m1.(v-o), y' = m2.(v-o), z
     float m1x, m1y, m1z, m2x, m2y, m2z, m3x, m3y, m3z;
 };
 
+// Reciprocals of ray quantities use the hardware reciprocal (about 1 ulp): box
+// tests are covered by the boxes' outward padding, and every triangle test of
+// a ray uses the same shear, so decisions stay consistent across edges.
 __device__ __forceinline__ float safe_inv(float d) {
     float a = fabsf(d) < 1e-20f ? copysignf(1e-20f, d) : d;
-    return 1.0f / a;
+    return __builtin_amdgcn_rcpf(a);
 }
 
 __device__ __forceinline__ Slab make_slab(float ox, float oy, float oz, float dx, float dy, float dz) {
@@ -76,7 +79,7 @@ __device__ __forceinline__ Shear make_shear(float dx, float dy, float dz) {
     if (dk < 0.0f) { int t = kx; kx = ky; ky = t; }
     float dkx = kx == 0 ? dx : (kx == 1 ? dy : dz);
     float dky = ky == 0 ? dx : (ky == 1 ? dy : dz);
-    float sz = 1.0f / dk;
+    float sz = __builtin_amdgcn_rcpf(dk);
     float sx = dkx * sz, sy = dky * sz;
     Shear m;
     m.m1x = (kx == 0) ? 1.0f : (kz == 0 ? -sx : 0.0f);
@@ -231,13 +234,17 @@ struct NoCount {
     __device__ __forceinline__ void node() {}
     __device__ __forceinline__ void tri() {}
     __device__ __forceinline__ void inst() {}
+    __device__ __forceinline__ uint32_t nodes() const { return 0; }
+    __device__ __forceinline__ void link_nodes(uint32_t) {}
 };
 struct RayCount {
     static constexpr bool kOn = true;
-    uint32_t n = 0, t = 0, i = 0;
+    uint32_t n = 0, t = 0, i = 0, l = 0;  // l: node records of link hierarchies (part of n)
     __device__ __forceinline__ void node() { ++n; }
     __device__ __forceinline__ void tri() { ++t; }
     __device__ __forceinline__ void inst() { ++i; }
+    __device__ __forceinline__ uint32_t nodes() const { return n; }
+    __device__ __forceinline__ void link_nodes(uint32_t k) { l += k; }
 };
 
 // Test one triangle (leaf-order record v) against the ray (origin o, shear m).
@@ -418,11 +425,13 @@ __device__ __forceinline__ void enter_link(const RenderLaunch& a, int e, int b, 
     const LinkMeta M = a.link_meta[b];
     const float* __restrict__ tris = a.link_tris + M.tri_base;
     const int32_t* __restrict__ ids = a.link_tri_id + M.id_base;
+    const uint32_t n0 = cnt.nodes();
     traverse(a.link_nodes + M.node_base, M.n_tri > 1 ? M.n_tri - 1 : 1, M.n_tri, ls, h, cnt, [&](int i) {
         cnt.tri();
         tri_test<EXACT>(tris + 9 * (int64_t)i, ids, (uint32_t)b, lox, loy, loz, lm, kLinkKappa, h,
                         px, b, i);
     }, 0, stk);
+    cnt.link_nodes(cnt.nodes() - n0);
 }
 
 // One pixel ray: robot bodies first, then the terrain under their bound
@@ -682,7 +691,7 @@ __device__ __forceinline__ void cast_tile(const RenderLaunch& a, const TileCfg& 
         const int64_t p = out0 + (int64_t)y * width + x;
         write_out(a, p, h, cam, x, y);
         if constexpr (Cnt::kOn)
-            reinterpret_cast<uint4*>(a.counts)[p] = make_uint4(cnt.n, cnt.t, cnt.i, 0u);
+            reinterpret_cast<uint4*>(a.counts)[p] = make_uint4(cnt.n, cnt.t, cnt.i, cnt.l);
         const float lim = h.tmax * kUndecidedSlack;
         const uint4 head = make_uint4((uint32_t)p, cam_index, (uint32_t)x | ((uint32_t)y << 16),
                                       __float_as_uint(h.tmax));

@@ -328,7 +328,7 @@ class Scene:
     def render_counts(self, cam_pos, cam_quat, intr, width, height, far_plane, link_pos=None,
                       link_quat=None, depth_mode=RC_DEPTH_PLANAR, out=None, stream=None):
         """rc_render plus per-ray work counts.  Returns ((depth, inst, tri),
-        counts int32 [E,C,H,W,4] = (node records, triangles, instances, 0))."""
+        counts int32 [E,C,H,W,4] = (node records, triangles, instances, link node records))."""
         a, outs, ws = self._plain_args(cam_pos, cam_quat, intr, width, height, far_plane, link_pos,
                                        link_quat, depth_mode, out, True)
         counts = torch.empty((cam_pos.shape[0], cam_pos.shape[1], height, width, 4),

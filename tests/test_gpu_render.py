@@ -196,7 +196,8 @@ def test_render_counts_matches_render():
         assert np.array_equal(g.cpu().numpy(), r)
     c = counts.cpu().numpy().reshape(-1, 4)
     inst = ref[1].ravel()
-    assert np.all(c[:, 3] == 0)
+    assert np.all(c[:, 3] <= c[:, 0]), "link node records are part of all node records"
+    assert np.all(c[c[:, 2] == 0, 3] == 0), "no link nodes without an entered link"
     assert np.all(c[:, 0] >= 1), "every ray reads at least one node record"
     assert np.all(c[:, 2] <= sc.n_links), "a link is entered at most once per ray"
     assert np.all(c[inst >= 0, 1] >= 1), "a hit needs a triangle test"
