@@ -375,7 +375,7 @@ typedef struct {
 
 /* Workspace bytes of a sensor-model state for frames [n_env][n_cam][height]
  * [width] with latencies up to max_latency frames (a device ring of
- * max_latency + 1 frames). */
+ * max_latency + 1 captures and their dropout masks). */
 rc_status rc_post_size(int32_t n_env, int32_t n_cam, int32_t height, int32_t width,
                        int32_t max_latency, size_t* ws_bytes);
 

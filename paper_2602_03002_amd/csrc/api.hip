@@ -31,7 +31,8 @@ struct rc_post {
     int32_t n_env, n_cam, height, width, max_latency;
     bool packed;
     int64_t n_pix;
-    float* ring;
+    float* ring;         // [L][n_pix] captures
+    uint8_t* ring_drop;  // [L][n_pix] dropout mask of each capture
     bool started;
     uint64_t s0, last;
 };
@@ -685,7 +686,15 @@ static rc_status post_dims(int32_t n_env, int32_t n_cam, int32_t height, int32_t
     const int64_t hw = (int64_t)height * width;
     if (hw > (int64_t)0xFFFFFFFF)
         return fail(RC_ERR_INVALID_ARG, std::string(who) + ": image too large");
+    if ((int64_t)n_env * n_cam > (int64_t)0x7FFFFFFF)
+        return fail(RC_ERR_INVALID_ARG, std::string(who) + ": more than 2^31 - 1 images");
     return RC_OK;
+}
+
+// The ring of max_latency + 1 captures (float) and their dropout masks (byte).
+static size_t post_ring_bytes(int64_t n_pix, int32_t max_latency) {
+    const size_t L = (size_t)(max_latency + 1);
+    return align_up((size_t)n_pix * 4 * L) + align_up((size_t)n_pix * L);
 }
 
 rc_status rc_post_size(int32_t n_env, int32_t n_cam, int32_t height, int32_t width,
@@ -694,7 +703,7 @@ rc_status rc_post_size(int32_t n_env, int32_t n_cam, int32_t height, int32_t wid
     rc_status st = post_dims(n_env, n_cam, height, width, max_latency, "rc_post_size");
     if (st != RC_OK) return st;
     const int64_t n_pix = (int64_t)n_env * n_cam * height * width;
-    *ws_bytes = align_up((size_t)n_pix * 4 * (size_t)(max_latency + 1));
+    *ws_bytes = post_ring_bytes(n_pix, max_latency);
     return RC_OK;
 }
 
@@ -714,6 +723,7 @@ rc_status rc_post_create(int32_t n_env, int32_t n_cam, int32_t height, int32_t w
     p->max_latency = max_latency;
     p->n_pix = (int64_t)n_env * n_cam * height * width;
     p->ring = (float*)ws;
+    p->ring_drop = (uint8_t*)ws + align_up((size_t)p->n_pix * 4 * (size_t)(max_latency + 1));
     p->started = false;
     p->s0 = p->last = 0;
     *out = p;
@@ -751,12 +761,14 @@ static rc_status post_common(rc_post* post, const float* depth_in, const rc_post
         return fail(RC_ERR_STATE, w + ": steps must be consecutive (call rc_post_reset)");
     L.depth_in = depth_in;
     L.ring = post->ring;
+    L.ring_drop = post->ring_drop;
     L.depth_out = depth_out;
     L.n_pix = post->n_pix;
     L.n_env = post->n_env; L.n_cam = post->n_cam; L.height = post->height; L.width = post->width;
     L.ring_len = post->max_latency + 1;
     L.step = step;
     L.s0 = post->started ? post->s0 : step;
+    L.slot = (int)(step % (uint64_t)L.ring_len);
     L.seed = pp->seed;
     double t = std::floor((double)pp->p_drop * 4294967296.0);
     L.drop_thr = t > 0.0 ? (uint64_t)t : 0ull;
@@ -795,7 +807,7 @@ rc_status rc_post_size_packed(int64_t n_pixels, int32_t max_latency, size_t* ws_
     if (n_pixels < 1 || n_pixels > (int64_t)0xFFFFFFFF || max_latency < 0 || max_latency > 255)
         return fail(RC_ERR_INVALID_ARG, "rc_post_size_packed: need 1 <= n_pixels <= 2^32 - 1, "
                                         "0 <= max_latency <= 255");
-    *ws_bytes = align_up((size_t)n_pixels * 4 * (size_t)(max_latency + 1));
+    *ws_bytes = post_ring_bytes(n_pixels, max_latency);
     return RC_OK;
 }
 
@@ -815,6 +827,7 @@ rc_status rc_post_create_packed(int64_t n_pixels, int32_t max_latency, void* ws,
     p->max_latency = max_latency;
     p->n_pix = n_pixels;
     p->ring = (float*)ws;
+    p->ring_drop = (uint8_t*)ws + align_up((size_t)n_pixels * 4 * (size_t)(max_latency + 1));
     p->started = false;
     p->s0 = p->last = 0;
     *out = p;

@@ -7,6 +7,8 @@
 // camera uid, capture step): no generator state is stored, and a request's
 // draws do not depend on how it is batched with others.  The ring buffer
 // keeps the last max_latency + 1 captures per pixel on the device.
+#include <algorithm>
+
 #include "rc_internal.h"
 
 #pragma clang fp contract(off)
@@ -17,8 +19,10 @@ namespace {
 
 __device__ __forceinline__ uint4 philox10(uint4 c, uint32_t k0, uint32_t k1) {
     for (int r = 0; r < 10; ++r) {
-        const uint32_t hi0 = __umulhi(0xD2511F53u, c.x), lo0 = 0xD2511F53u * c.x;
-        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z), lo1 = 0xCD9E8D57u * c.z;
+        // one 32 x 32 -> 64-bit multiply gives both halves of each product
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c.x, p1 = (uint64_t)0xCD9E8D57u * c.z;
+        const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
         c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
@@ -30,9 +34,20 @@ __device__ __forceinline__ uint32_t step_hi(uint64_t s) {
     return (uint32_t)(((s >> 32) & 0xFFFFull) << 16);
 }
 
-// Sensor model of packed pixel p: pixel `pix` of its image, camera `uid`.
+// Latency (frames) of camera `uid` at this step: one draw per (camera, step).
+__device__ __forceinline__ int latency_draw(const PostLaunch& a, uint32_t uid) {
+    if (!(a.flags & RC_POST_LATENCY)) return 0;
+    const uint64_t s = a.step;
+    const uint4 wl = philox10(make_uint4(0xFFFFFFFFu, uid, (uint32_t)s, step_hi(s) | 1u),
+                              (uint32_t)a.seed, (uint32_t)(a.seed >> 32));
+    const uint64_t span = (uint64_t)(a.lat_max - a.lat_min + 1);
+    return a.lat_min + (int)(((uint64_t)wl.x * span) >> 32);
+}
+
+// Sensor model of packed pixel p: pixel `pix` of its image, camera `uid`,
+// whose latency at this step is k frames.
 __device__ __forceinline__ void post_pixel(const PostLaunch& a, int64_t p, uint32_t pix, uint32_t uid,
-                                           uint8_t* lat_slot) {
+                                           int k) {
     const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
     const uint64_t s = a.step;
 
@@ -55,57 +70,57 @@ __device__ __forceinline__ void post_pixel(const PostLaunch& a, int64_t p, uint3
     }
     zz = fminf(fmaxf(zz, a.near_plane), a.far_plane);
     const float cap = drop ? a.fill : zz;
-    a.ring[(int64_t)(s % (uint64_t)a.ring_len) * a.n_pix + p] = cap;
+    const int64_t here = (int64_t)a.slot * a.n_pix + p;
+    a.ring[here] = cap;
+    a.ring_drop[here] = drop ? 1 : 0;
 
-    // frame shown at this step
-    int k = 0;
-    if (a.flags & RC_POST_LATENCY) {
-        const uint4 wl = philox10(make_uint4(0xFFFFFFFFu, uid, (uint32_t)s, step_hi(s) | 1u), k0, k1);
-        const uint64_t span = (uint64_t)(a.lat_max - a.lat_min + 1);
-        k = a.lat_min + (int)(((uint64_t)wl.x * span) >> 32);
-    }
-    const uint64_t src = (s - a.s0 >= (uint64_t)k) ? s - (uint64_t)k : a.s0;
+    // frame shown at this step: the capture of step max(s - k, s0), k < ring_len
+    const int d = (s - a.s0 >= (uint64_t)k) ? k : (int)(s - a.s0);
     float out = cap;
     bool out_drop = drop;
-    if (src != s) {
-        out = a.ring[(int64_t)(src % (uint64_t)a.ring_len) * a.n_pix + p];
-        if (a.drop_out) {
-            const uint4 wo = philox10(make_uint4(pix, uid, (uint32_t)src, step_hi(src)), k0, k1);
-            out_drop = (a.flags & RC_POST_DROPOUT) && ((uint64_t)wo.x < a.drop_thr);
-        }
+    if (d > 0) {
+        const int slot = a.slot >= d ? a.slot - d : a.slot - d + a.ring_len;
+        const int64_t there = (int64_t)slot * a.n_pix + p;
+        out = a.ring[there];
+        out_drop = a.ring_drop[there] != 0;
     }
     a.depth_out[p] = out;
     if (a.drop_out) a.drop_out[p] = out_drop ? 1 : 0;
-    if (lat_slot && pix == 0) *lat_slot = (uint8_t)k;
 }
 
-// Plain layout [env][cam][height][width]: one thread per pixel.
+// Plain layout [env][cam][height][width]: block row x = image (env, cam), the
+// blocks of a row stride over its pixels.
 __global__ void __launch_bounds__(256) k_post(PostLaunch a) {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= a.n_pix) return;
+    const int64_t ec = blockIdx.x;
     const int64_t hw = (int64_t)a.height * a.width;
-    const int64_t ec = p / hw;
-    const uint32_t pix = (uint32_t)(p - ec * hw);
     const uint32_t uid = a.cam_uid ? a.cam_uid[ec] : (uint32_t)ec;
-    post_pixel(a, p, pix, uid, a.lat_out ? a.lat_out + ec : nullptr);
+    const int k = latency_draw(a, uid);
+    if (a.lat_out && blockIdx.y == 0 && threadIdx.x == 0) a.lat_out[ec] = (uint8_t)k;
+    for (int64_t q = (int64_t)blockIdx.y * blockDim.x + threadIdx.x; q < hw;
+         q += (int64_t)gridDim.y * blockDim.x)
+        post_pixel(a, ec * hw + q, (uint32_t)q, uid, k);
 }
 
-// Packed batch: block row x = camera, the blocks of a row stride over its pixels.
+// Packed batch: block row x = camera descriptor, the blocks of a row stride
+// over its pixels.
 __global__ void __launch_bounds__(256) k_post_batched(PostLaunch a, const rc_cam_desc* desc) {
     const rc_cam_desc D = desc[blockIdx.x];
     const int64_t np = (int64_t)D.width * D.height;
     if (D.width < 1 || D.height < 1 || (int64_t)D.out_offset + np > a.n_pix) return;
+    const int k = latency_draw(a, D.cam_uid);
+    if (a.lat_out && blockIdx.y == 0 && threadIdx.x == 0) a.lat_out[blockIdx.x] = (uint8_t)k;
     for (int64_t q = (int64_t)blockIdx.y * blockDim.x + threadIdx.x; q < np;
          q += (int64_t)gridDim.y * blockDim.x)
-        post_pixel(a, (int64_t)D.out_offset + q, (uint32_t)q, D.cam_uid,
-                   a.lat_out ? a.lat_out + blockIdx.x : nullptr);
+        post_pixel(a, (int64_t)D.out_offset + q, (uint32_t)q, D.cam_uid, k);
 }
 
 }  // namespace
 
 hipError_t launch_post(const PostLaunch& a, hipStream_t s) {
-    const unsigned blocks = (unsigned)((a.n_pix + 255) / 256);
-    hipLaunchKernelGGL(k_post, dim3(blocks), dim3(256), 0, s, a);
+    const int64_t hw = (int64_t)a.height * a.width;
+    const unsigned per_image = (unsigned)std::min<int64_t>((hw + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_post, dim3((unsigned)((int64_t)a.n_env * a.n_cam), per_image), dim3(256), 0,
+                       s, a);
     return hipGetLastError();
 }
 

@@ -124,12 +124,14 @@ struct PostLaunch {
     const float* depth_in;
     const int32_t* inst_in;
     const uint32_t* cam_uid;
-    float* ring;  // [L][n_pix]
+    float* ring;         // [L][n_pix] captures
+    uint8_t* ring_drop;  // [L][n_pix] their dropout masks
     float* depth_out;
     uint8_t* drop_out;
     uint8_t* lat_out;
     int64_t n_pix;
     int n_env, n_cam, height, width, ring_len;
+    int slot;  // ring slot of this step: step mod ring_len
     uint64_t step, s0;
     uint64_t seed;
     uint64_t drop_thr;  // floor(p_drop * 2^32) in [0, 2^32]
