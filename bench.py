@@ -35,6 +35,8 @@ def bytes_per_ray():
 
 
 COUNTERS = os.path.join(ROOT, "profiles", "k_render_4096x2_64x48_hbm_counters.txt")
+SQ_COUNTERS = os.path.join(ROOT, "profiles", "k_render_4096x2_64x48_sq_counters.txt")
+L2_COUNTERS = os.path.join(ROOT, "profiles", "k_render_4096x2_64x48_l2_counters.txt")
 KERNEL_SRC = [os.path.join(ROOT, "paper_2602_03002_amd", "csrc", f)
               for f in ("raycast.hip", "rc_internal.h")]
 
@@ -47,19 +49,38 @@ def kernel_sha():
     return h.hexdigest()
 
 
+def _profile(path):
+    kv = {}
+    if os.path.exists(path):
+        for line in open(path):
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    return kv
+
+
 def measured_traffic():
     """HBM bytes per fast-pass launch from the committed rocprofv3 counter
     summary, or None if the kernel source changed since it was taken."""
-    if not os.path.exists(COUNTERS):
-        return None
-    kv = {}
-    for line in open(COUNTERS):
-        if ":" in line and not line.startswith("#"):
-            k, v = line.split(":", 1)
-            kv[k.strip()] = v.strip()
+    kv = _profile(COUNTERS)
     if kv.get("kernel_source_sha256") != kernel_sha():
         return None
     return int(float(kv["traffic_bytes_per_launch"]))
+
+
+def measured_issue():
+    """VALU issue rate (fraction of one wave64 VALU instruction per CU per
+    cycle) and L2 hit rate of the fast pass from the committed counter
+    summaries, or None when they predate the kernel source."""
+    sq = _profile(SQ_COUNTERS)
+    l2 = _profile(L2_COUNTERS)
+    out = {}
+    if sq.get("kernel_source_sha256") == kernel_sha():
+        out["valu_issue_frac"] = float(sq["valu_issue_per_cu_cycle"])
+        out["salu_issue_frac"] = float(sq["salu_issue_per_cu_cycle"])
+    if l2.get("kernel_source_sha256") == kernel_sha():
+        out["l2_hit_rate"] = float(l2["l2_hit_rate"])
+    return out
 
 
 def _oracle_rate(w, budget_s, seed):
@@ -455,6 +476,7 @@ def main():
                 "kernel": "k_render (fast pass)", "bytes_per_ray": round(bpr, 1),
                 "kernel_ms": round(r_ms, 4), "copy_gbs": round(copy_gbs, 1),
                 "frac_of_copy": round(achieved / copy_gbs, 4)}
+        roof.update(measured_issue())
     # bytes a step cannot avoid: the scene read once, top levels written and
     # read, poses, render outputs, sensor-model traffic
     lay = sc.bvh_layout(-1)
