@@ -367,7 +367,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--schedule", default=None,
                     help="fix the plain fast-pass schedule tile_w,tile_h,rays_per_lane,waves,"
-                         "terrain_packet (no autotuning), e.g. to profile the schedule a full run chose")
+                         "terrain_packet,bodies_flat (no autotuning), e.g. to profile the schedule a "
+                         "full run chose")
     ap.add_argument("--no-batched", action="store_true", help="skip the uneven batched section")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving section")
     ap.add_argument("--serve-seconds", type=float, default=6.0)
@@ -426,9 +427,9 @@ def main():
 
     tuned = None
     if args.schedule:
-        tw, th, rpl, wv, tp = (int(v) for v in args.schedule.split(","))
+        tw, th, rpl, wv, tp, bf = (int(v) for v in args.schedule.split(","))
         sc.set_config(batched=False, tile_w=tw, tile_h=th, rays_per_lane=rpl, waves=wv,
-                      terrain_packet=tp)
+                      terrain_packet=tp, bodies_flat=bf)
         tuned = sc.config(batched=False)
     elif not args.no_autotune:
         tuned, tuned_ms = sc.autotune(reps=2, cam_pos=cp, cam_quat=cq, intr=K, width=W, height=H,

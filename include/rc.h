@@ -235,6 +235,10 @@ typedef struct {
     int32_t terrain_packet;  /* 0: each lane walks the terrain hierarchy alone; 1: the
                                 wavefront walks it as a packet (a node is entered if any
                                 of its rays reaches it) */
+    int32_t bodies_flat;     /* 0: links are found by walking the environment's top-level
+                                hierarchy; 1: by testing every link's bounding sphere against
+                                the cone of the wavefront's rays, then each ray against the
+                                surviving spheres */
 } rc_render_config;
 
 /* Schedule used by rc_render (batched = 0) or rc_render_batched (batched = 1). */
@@ -243,7 +247,8 @@ rc_status rc_set_render_config(rc_scene* scene, int32_t batched, const rc_render
 
 /* Time every candidate schedule (tile 8x8, 16x4, 4x16, 32x2; 1 or 2 tiles
  * per wavefront; 6, 7 or 8 wavefronts per SIMD; per-lane or packet terrain
- * walk; for the batched form also persistent or flat) on this exact launch -
+ * walk; top-level or cone-culled links; for the batched form also
+ * persistent or flat) on this exact launch -
  * exactly one of `plain` and `batched` non-NULL - with `reps` timed runs
  * each after one warm-up, keep the fastest for that mode in the scene and
  * return it with its mean time.  Overwrites the launch's outputs.

@@ -532,6 +532,7 @@ static RenderCfg to_cfg(const rc_render_config& c) {
     r.tile_w = c.tile_w; r.tile_h = c.tile_h; r.rays_per_lane = c.rays_per_lane; r.waves = c.waves;
     r.persistent = c.persistent ? 1 : 0;
     r.terrain_packet = c.terrain_packet;
+    r.bodies_flat = c.bodies_flat;
     return r;
 }
 
@@ -540,6 +541,7 @@ static rc_render_config from_cfg(const RenderCfg& c) {
     r.tile_w = c.tile_w; r.tile_h = c.tile_h; r.rays_per_lane = c.rays_per_lane; r.waves = c.waves;
     r.persistent = c.persistent;
     r.terrain_packet = c.terrain_packet;
+    r.bodies_flat = c.bodies_flat;
     return r;
 }
 
@@ -555,7 +557,7 @@ rc_status rc_set_render_config(rc_scene* scene, int32_t batched, const rc_render
     if (!render_cfg_ok(c))
         return fail(RC_ERR_INVALID_ARG, "rc_set_render_config: need tile_w * tile_h = 64, "
                                         "rays_per_lane in {1, 2}, waves in {6, 7, 8}, "
-                                        "terrain_packet in {0, 1}");
+                                        "terrain_packet and bodies_flat in {0, 1}");
     (batched ? scene->cfg_batched : scene->cfg) = c;
     return RC_OK;
 }
@@ -583,6 +585,7 @@ rc_status rc_autotune(rc_scene* scene, const rc_render_args* plain, const rc_bat
     const int n_modes = plain ? 1 : 2;
     for (int pm = 0; pm < n_modes && e == hipSuccess; ++pm)
     for (int tp = 0; tp < 2 && e == hipSuccess; ++tp)
+    for (int bf = 0; bf < 2 && e == hipSuccess; ++bf)
     for (int t = 0; t < 4 && e == hipSuccess; ++t)
         for (int rpl = 1; rpl <= 2 && e == hipSuccess; ++rpl)
             for (int wv = 6; wv <= 8 && e == hipSuccess; ++wv) {
@@ -590,6 +593,7 @@ rc_status rc_autotune(rc_scene* scene, const rc_render_args* plain, const rc_bat
                 c.tile_w = tiles[t][0]; c.tile_h = tiles[t][1]; c.rays_per_lane = rpl; c.waves = wv;
                 c.persistent = pm;
                 c.terrain_packet = tp;
+                c.bodies_flat = bf;
                 for (int r = 0; r <= reps && e == hipSuccess; ++r) {
                     if (r == 1) e = hipEventRecord(e0, s);
                     if (e == hipSuccess)

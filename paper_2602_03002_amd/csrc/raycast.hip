@@ -273,9 +273,9 @@ __device__ __forceinline__ void tri_test(const float* __restrict__ v,
     const float W = __fmaf_rn(Bx, Ay, -(By * Ax));
     const float thr = (fabsf(U) + fabsf(V) + fabsf(W)) * kappa;
     const float lo = fminf(fminf(U, V), W), hi = fmaxf(fmaxf(U, V), W);
-    if (lo < -thr && hi > thr) return;  // certainly outside
+    if ((lo < -thr) & (hi > thr)) return;  // certainly outside
     // certain hit only when all three clear the margin with the same sign
-    const bool sure = thr > 0.0f && (lo > thr || hi < -thr);
+    const bool sure = (thr > 0.0f) & ((lo > thr) | (hi < -thr));
     float t;
     if (EXACT && !sure) {
         double t64;
@@ -352,9 +352,10 @@ __device__ __forceinline__ void traverse(const Node* __restrict__ nodes, int n_n
         bool h0 = slab(q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, r, h.tmax, tn0);
         bool h1 = slab(q1.z, q1.w, q2.x, q2.y, q2.z, q2.w, r, h.tmax, tn1);
         const int c0 = q3.x, c1 = q3.y;
-        h0 = h0 && (c0 >= 0 || (unsigned)~c0 < (unsigned)n_prim);
-        h1 = h1 && (c1 >= 0 || (unsigned)~c1 < (unsigned)n_prim);
-        const bool l0 = h0 && c0 < 0, l1 = h1 && c1 < 0;
+        // non-short-circuit forms: mask arithmetic instead of branches
+        h0 = h0 & ((c0 >= 0) | ((unsigned)~c0 < (unsigned)n_prim));
+        h1 = h1 & ((c1 >= 0) | ((unsigned)~c1 < (unsigned)n_prim));
+        const bool l0 = h0 & (c0 < 0), l1 = h1 & (c1 < 0);
         if (l0 || l1) {  // leaf children first, nearest first
             const bool swap = l0 && l1 && tn1 < tn0;
             const int la = (l0 && !swap) ? ~c0 : ~c1;
@@ -366,8 +367,8 @@ __device__ __forceinline__ void traverse(const Node* __restrict__ nodes, int n_n
                 leaf(lf);
             }
         }
-        const bool g0 = h0 && !l0 && tn0 <= h.tmax;
-        const bool g1 = h1 && !l1 && tn1 <= h.tmax;
+        const bool g0 = h0 & !l0 & (tn0 <= h.tmax);
+        const bool g1 = h1 & !l1 & (tn1 <= h.tmax);
         if (g0 && g1) {
             const bool first1 = tn1 < tn0;
             trail = (trail << 1) | 1ull;
@@ -434,13 +435,45 @@ __device__ __forceinline__ void enter_link(const RenderLaunch& a, int e, int b, 
     cnt.link_nodes(cnt.nodes() - n0);
 }
 
+// Schedule variants of the fast pass (bits of MODE).
+constexpr int kPacketTerrain = 1;  // walk the terrain as a wavefront packet
+constexpr int kFlatBodies = 2;     // cull links against the wavefront's cone instead of the top level
+
+__device__ __forceinline__ float wave_sum(float v) {
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+__device__ __forceinline__ float wave_min(float v) {
+    for (int off = 32; off >= 1; off >>= 1) v = fminf(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// World bounding sphere of link b of env e: the centre of its local (padded)
+// box under the pose, the box's half-diagonal as radius, widened by 1% + 1 mm
+// so FP32 rounding cannot cull a reachable link.
+__device__ __forceinline__ void link_sphere(const RenderLaunch& a, int e, int b, float& cx, float& cy,
+                                            float& cz, float& rad) {
+    const InstXform X = a.xf[(int64_t)e * a.n_links + b];
+    const float* rb = a.link_meta[b].root;
+    const float lx = 0.5f * (rb[0] + rb[1]), ly = 0.5f * (rb[2] + rb[3]), lz = 0.5f * (rb[4] + rb[5]);
+    const float hx = 0.5f * (rb[1] - rb[0]), hy = 0.5f * (rb[3] - rb[2]), hz = 0.5f * (rb[5] - rb[4]);
+    rad = sqrtf(__fmaf_rn(hz, hz, __fmaf_rn(hy, hy, hx * hx))) * 1.01f + 1e-3f;
+    // centre = R c + t with X.m = R^T
+    cx = __fmaf_rn(X.m[6], lz, __fmaf_rn(X.m[3], ly, X.m[0] * lx)) + X.t[0];
+    cy = __fmaf_rn(X.m[7], lz, __fmaf_rn(X.m[4], ly, X.m[1] * lx)) + X.t[1];
+    cz = __fmaf_rn(X.m[8], lz, __fmaf_rn(X.m[5], ly, X.m[2] * lx)) + X.t[2];
+}
+
 // One pixel ray: robot bodies first, then the terrain under their bound
 // (Algorithm 1's query order).  WAVE: the wavefront shares the environment
 // and walks its top-level hierarchy together (trail and node records are
 // wave-uniform, in scalar registers; a node is entered if any lane's ray hits
-// it, a link only by the lanes whose rays hit its box).  Otherwise each lane
+// it, a link only by the lanes whose rays hit its box) - or, with
+// kFlatBodies, tests every link's bounding sphere against the cone of its
+// rays (one link per lane) and visits the survivors one by one, entering a
+// link where the lane's ray segment passes its sphere.  Otherwise each lane
 // walks the top level alone.
-template <bool EXACT, bool WAVE, bool PACKET, typename Cnt>
+template <bool EXACT, bool WAVE, int MODE, typename Cnt>
 __device__ __forceinline__ Hit cast_ray(const RenderLaunch& a, const CamRef& cam, int e, int x, int y,
                                         float bound, uint2* cand, uint32_t* stk,
                                         Cnt& cnt) {
@@ -464,6 +497,50 @@ __device__ __forceinline__ Hit cast_ray(const RenderLaunch& a, const CamRef& cam
             traverse(tl, n_rec, a.n_links, ws, h, cnt, [&](int b) {
                 enter_link<EXACT>(a, e, b, ox, oy, oz, dx, dy, dz, h, px, cnt, nullptr);
             });
+        } else if (MODE & kFlatBodies) {
+            // cone of the wavefront's rays (common apex o): unit axis and the
+            // cosine of its half-angle, widened for rounding
+            const float il = rsqrtf(__fmaf_rn(dz, dz, __fmaf_rn(dy, dy, dx * dx)));
+            const float nx = dx * il, ny = dy * il, nz = dz * il;
+            float ax = wave_sum(nx), ay = wave_sum(ny), az = wave_sum(nz);
+            const float al = sqrtf(__fmaf_rn(az, az, __fmaf_rn(ay, ay, ax * ax)));
+            float cmin = -1.0f;
+            if (al > 1e-3f) {
+                ax /= al; ay /= al; az /= al;
+                cmin = wave_min(__fmaf_rn(nz, az, __fmaf_rn(ny, ay, nx * ax))) - 1e-4f;
+            }
+            const float smin = sqrtf(fmaxf(0.0f, 1.0f - cmin * cmin));
+            // lane b: world bounding sphere of link b (local box centre under
+            // the pose, half-diagonal radius with a margin) against the cone;
+            // the survivors' spheres are rebuilt from wave-uniform loads below
+            const int lane = threadIdx.x & 63;
+            bool keep = false;
+            if (lane < a.n_links) {
+                float cx, cy, cz, rad;
+                link_sphere(a, e, lane, cx, cy, cz, rad);
+                const float vx = cx - ox, vy = cy - oy, vz = cz - oz;
+                const float along = __fmaf_rn(vz, az, __fmaf_rn(vy, ay, vx * ax));
+                const float v2 = __fmaf_rn(vz, vz, __fmaf_rn(vy, vy, vx * vx));
+                const float perp = sqrtf(fmaxf(0.0f, v2 - along * along));
+                keep = cmin <= -1.0f || __fmaf_rn(perp, cmin, -along * smin) <= rad;
+            }
+            uint64_t todo = __ballot(keep);
+            while (todo) {  // wave-uniform loop over the surviving links
+                const int b = uni(__builtin_ctzll(todo));
+                todo &= todo - 1ull;
+                float sx, sy, sz, sr;
+                link_sphere(a, e, b, sx, sy, sz, sr);
+                // closest point of the lane's segment [o, o + tmax d] to the centre
+                const float wx = sx - ox, wy = sy - oy, wz = sz - oz;
+                const float dd = __fmaf_rn(dz, dz, __fmaf_rn(dy, dy, dx * dx));
+                const float tc = fminf(fmaxf(__fmaf_rn(wz, dz, __fmaf_rn(wy, dy, wx * dx)) *
+                                                 __builtin_amdgcn_rcpf(dd), 0.0f),
+                                       h.tmax);
+                const float qx = __fmaf_rn(-tc, dx, wx), qy = __fmaf_rn(-tc, dy, wy),
+                            qz = __fmaf_rn(-tc, dz, wz);
+                if (__fmaf_rn(qz, qz, __fmaf_rn(qy, qy, qx * qx)) <= sr * sr)
+                    enter_link<EXACT>(a, e, b, ox, oy, oz, dx, dy, dz, h, px, cnt, stk);
+            }
         } else {
             uint32_t trail = 0;
             int cur = 0;
@@ -557,7 +634,7 @@ __device__ __forceinline__ Hit cast_ray(const RenderLaunch& a, const CamRef& cam
                 tri_test<EXACT>(a.terrain_tris + 9 * (int64_t)i, a.terrain_tri_id,
                                 (uint32_t)a.n_links, ox, oy, oz, wm, kTerrainKappa, h, px, -1, i);
             };
-            if (!PACKET) {
+            if (!(MODE & kPacketTerrain)) {
                 traverse(a.terrain_nodes, n_nodes, a.n_terrain, ws, h, cnt, leaf, entry, stk);
             } else {
                 // Packet form: the wavefront walks the terrain hierarchy together
@@ -665,7 +742,7 @@ __global__ void k_cam_prep(RenderLaunch a, int64_t n) {
 // found here and the (at most two) undecided triangles to decide in FP64 at
 // the front of its list, or, with more, to be re-cast in full (from the back
 // of the list, starting from the certain hit's bound).
-template <int RPL, bool PACKET, typename Cnt = NoCount>
+template <int RPL, int MODE, typename Cnt = NoCount>
 __device__ __forceinline__ void cast_tile(const RenderLaunch& a, const TileCfg& c, const CamRef& cam,
                                           int e, uint32_t cam_index, int width, int height,
                                           int64_t out0, int tx, int ty) {
@@ -686,7 +763,7 @@ __device__ __forceinline__ void cast_tile(const RenderLaunch& a, const TileCfg& 
         const int y = yt < height ? yt : height - 1;
         Cnt cnt;
         for (int k = 0; k < kCandSlots; ++k) cand[k].x = kNoCand;
-        const Hit h = cast_ray<false, true, PACKET>(a, cam, e, x, y, INFINITY, cand, stk, cnt);
+        const Hit h = cast_ray<false, true, MODE>(a, cam, e, x, y, INFINITY, cand, stk, cnt);
         if (!valid) continue;
         const int64_t p = out0 + (int64_t)y * width + x;
         write_out(a, p, h, cam, x, y);
@@ -715,7 +792,7 @@ __device__ __forceinline__ void cast_tile(const RenderLaunch& a, const TileCfg& 
 }
 
 // Fast pass over the plain [env][cam][H][W] layout, one wavefront tile.
-template <int RPL, bool PACKET, typename Cnt>
+template <int RPL, int MODE, typename Cnt>
 __device__ __forceinline__ void plain_tile(const RenderLaunch& a, const TileCfg& c, int64_t n_logical,
                                            int64_t per_xcd) {
     // XCD-aware order: hardware deals blocks round-robin over the 8 XCDs, so
@@ -732,25 +809,25 @@ __device__ __forceinline__ void plain_tile(const RenderLaunch& a, const TileCfg&
     const int64_t ec = tile / tiles_img;
     if (ec >= (int64_t)a.n_env * a.n_cam) return;
     const int tin = (int)(tile - ec * tiles_img);
-    cast_tile<RPL, PACKET, Cnt>(a, c, launch_cam(a, ec), (int)(ec / a.n_cam), (uint32_t)ec, a.width, a.height,
+    cast_tile<RPL, MODE, Cnt>(a, c, launch_cam(a, ec), (int)(ec / a.n_cam), (uint32_t)ec, a.width, a.height,
                         ec * (int64_t)a.width * a.height, tin % tiles_x, tin / tiles_x);
 }
 
 // Fast pass.  WAVES asks the compiler for at least that many resident
-// wavefronts per SIMD (fewer registers per lane, maybe a few spills); PACKET
-// walks the terrain as a wavefront packet instead of per lane.  The autotuner
-// picks them and the tile schedule.
-template <int WAVES, int RPL, bool PACKET>
+// wavefronts per SIMD (fewer registers per lane, maybe a few spills); MODE
+// selects the body culling and terrain walk variants.  The autotuner picks
+// them and the tile schedule.
+template <int WAVES, int RPL, int MODE>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES, 8)))
 k_render(RenderLaunch a, TileCfg c, int64_t n_logical, int64_t per_xcd) {
-    plain_tile<RPL, PACKET, NoCount>(a, c, n_logical, per_xcd);
+    plain_tile<RPL, MODE, NoCount>(a, c, n_logical, per_xcd);
 }
 
 // The fast pass with per-ray work counters (diagnostic render).
-template <bool PACKET>
+template <int MODE>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8)))
 k_render_counts(RenderLaunch a, TileCfg c, int64_t n_logical, int64_t per_xcd) {
-    plain_tile<1, PACKET, RayCount>(a, c, n_logical, per_xcd);
+    plain_tile<1, MODE, RayCount>(a, c, n_logical, per_xcd);
 }
 
 // Batched uneven form, setup: validate each camera descriptor, count its
@@ -804,7 +881,7 @@ __global__ void __launch_bounds__(1024) k_batch_prep(RenderLaunch a, TileCfg c, 
 // neighbouring pixels of one camera, so a chunk's rays share cache lines on
 // the XCD that runs it) until the tiles run out; the tile table maps a tile
 // to its camera descriptor by binary search.
-template <int WAVES, int RPL, bool PACKET>
+template <int WAVES, int RPL, int MODE>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES, 8)))
 k_render_batched(RenderLaunch a, TileCfg c, const uint32_t* __restrict__ tile_start,
                  uint32_t* queue) {
@@ -828,7 +905,7 @@ k_render_batched(RenderLaunch a, TileCfg c, const uint32_t* __restrict__ tile_st
             const int width = D->width;
             const int tiles_x = (width + c.tw - 1) / c.tw;
             const int tin = (int)(tile - tile_start[d]);
-            cast_tile<RPL, PACKET>(a, c, launch_cam(a, d), D->env, (uint32_t)d, width, D->height,
+            cast_tile<RPL, MODE>(a, c, launch_cam(a, d), D->env, (uint32_t)d, width, D->height,
                                    (int64_t)D->out_offset, tin % tiles_x, tin / tiles_x);
         }
     }
@@ -838,7 +915,7 @@ k_render_batched(RenderLaunch a, TileCfg c, const uint32_t* __restrict__ tile_st
 // camera-major grid sized for the largest image; tiles past a camera's own
 // count exit at once.  No loop around the tile, so no state is carried
 // between tiles (the persistent form's loop costs registers).
-template <int WAVES, int RPL, bool PACKET>
+template <int WAVES, int RPL, int MODE>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES, 8)))
 k_render_flat(RenderLaunch a, TileCfg c, const uint32_t* __restrict__ tile_start, int tiles_per_cam,
               int64_t n_logical, int64_t per_xcd) {
@@ -854,8 +931,8 @@ k_render_flat(RenderLaunch a, TileCfg c, const uint32_t* __restrict__ tile_start
     const rc_cam_desc* D = a.desc + d;
     const int width = D->width;
     const int tiles_x = (width + c.tw - 1) / c.tw;
-    cast_tile<RPL, PACKET>(a, c, launch_cam(a, d), D->env, (uint32_t)d, width, D->height,
-                           (int64_t)D->out_offset, k % tiles_x, k / tiles_x);
+    cast_tile<RPL, MODE>(a, c, launch_cam(a, d), D->env, (uint32_t)d, width, D->height,
+                         (int64_t)D->out_offset, k % tiles_x, k / tiles_x);
 }
 
 // Exact pass.  If the list overflowed, every pixel is re-cast.
@@ -878,7 +955,7 @@ __device__ __forceinline__ void exact_one(const RenderLaunch& a, int64_t p, uint
     int e;
     entry_cam(a, cam_index, cam, e);
     NoCount none;
-    const Hit h = cast_ray<true, false, false>(a, cam, e, x, y, bound, nullptr, nullptr, none);
+    const Hit h = cast_ray<true, false, 0>(a, cam, e, x, y, bound, nullptr, nullptr, none);
     write_out(a, p, h, cam, x, y);
 }
 
@@ -972,13 +1049,16 @@ __global__ void __launch_bounds__(64) k_render_exact(RenderLaunch a, const uint3
 
 }  // namespace
 
-// Kernel variant index: 100 * packet + 10 * waves + tiles per wavefront.
+// Kernel variant index: 100 * mode + 10 * waves + tiles per wavefront.
+#define RC_MODE_VARIANTS(X, M) X(6, 1, M) X(6, 2, M) X(7, 1, M) X(7, 2, M) X(8, 1, M) X(8, 2, M)
 #define RC_VARIANTS(X) \
-    X(6, 1, false) X(6, 2, false) X(7, 1, false) X(7, 2, false) X(8, 1, false) X(8, 2, false) \
-    X(6, 1, true) X(6, 2, true) X(7, 1, true) X(7, 2, true) X(8, 1, true) X(8, 2, true)
+    RC_MODE_VARIANTS(X, 0) RC_MODE_VARIANTS(X, 1) RC_MODE_VARIANTS(X, 2) RC_MODE_VARIANTS(X, 3)
 
+static int cfg_mode(const RenderCfg& cfg) {
+    return (cfg.terrain_packet ? kPacketTerrain : 0) | (cfg.bodies_flat ? kFlatBodies : 0);
+}
 static int variant(const RenderCfg& cfg, int rpl) {
-    return 100 * (cfg.terrain_packet ? 1 : 0) + 10 * cfg.waves + rpl;
+    return 100 * cfg_mode(cfg) + 10 * cfg.waves + rpl;
 }
 
 hipError_t launch_render(const RenderLaunch& a, const RenderCfg& cfg, hipStream_t s) {
@@ -997,14 +1077,19 @@ hipError_t launch_render(const RenderLaunch& a, const RenderCfg& cfg, hipStream_
                        dim3(256), 0, s, a, n_cams);
     if (a.ev_begin) hipEventRecord(a.ev_begin, s);
     if (a.counts) {
-        if (cfg.terrain_packet)
-            hipLaunchKernelGGL((k_render_counts<true>), grid, block, 0, s, a, c, n_logical, per_xcd);
-        else
-            hipLaunchKernelGGL((k_render_counts<false>), grid, block, 0, s, a, c, n_logical, per_xcd);
+        switch (cfg_mode(cfg)) {
+#define RC_COUNT(M)                                                                             \
+    case M:                                                                                    \
+        hipLaunchKernelGGL((k_render_counts<M>), grid, block, 0, s, a, c, n_logical, per_xcd); \
+        break;
+            RC_COUNT(0) RC_COUNT(1) RC_COUNT(2) RC_COUNT(3)
+#undef RC_COUNT
+            default: return hipErrorInvalidValue;
+        }
     } else {
         switch (variant(cfg, c.rpl)) {
 #define RC_PLAIN(W, R, P)                                                                      \
-    case 100 * (P ? 1 : 0) + 10 * W + R:                                                      \
+    case 100 * P + 10 * W + R:                                                      \
         hipLaunchKernelGGL((k_render<W, R, P>), grid, block, 0, s, a, c, n_logical, per_xcd); \
         break;
             RC_VARIANTS(RC_PLAIN)
@@ -1030,7 +1115,7 @@ hipError_t launch_render_batched(const RenderLaunch& a, const RenderCfg& cfg, ui
         const dim3 grid((unsigned)persistent_blocks);
         switch (variant(cfg, c.rpl)) {
 #define RC_BATCH(W, R, P)                                                                          \
-    case 100 * (P ? 1 : 0) + 10 * W + R:                                                          \
+    case 100 * P + 10 * W + R:                                                          \
         hipLaunchKernelGGL((k_render_batched<W, R, P>), grid, block, 0, s, a, c, tile_start, queues); \
         break;
             RC_VARIANTS(RC_BATCH)
@@ -1046,7 +1131,7 @@ hipError_t launch_render_batched(const RenderLaunch& a, const RenderCfg& cfg, ui
         const dim3 grid((unsigned)(per_xcd * 8));
         switch (variant(cfg, c.rpl)) {
 #define RC_FLAT(W, R, P)                                                                         \
-    case 100 * (P ? 1 : 0) + 10 * W + R:                                                         \
+    case 100 * P + 10 * W + R:                                                         \
         hipLaunchKernelGGL((k_render_flat<W, R, P>), grid, block, 0, s, a, c,                    \
                            (const uint32_t*)tile_start, tiles_per_cam, n_logical, per_xcd);      \
         break;
@@ -1064,7 +1149,8 @@ bool render_cfg_ok(const RenderCfg& c) {
     return c.tile_w >= 1 && c.tile_h >= 1 && c.tile_w * c.tile_h == 64 &&
            (c.rays_per_lane == 1 || c.rays_per_lane == 2) &&
            (c.waves == 6 || c.waves == 7 || c.waves == 8) &&
-           (c.terrain_packet == 0 || c.terrain_packet == 1) && (c.persistent == 0 || c.persistent == 1);
+           (c.terrain_packet == 0 || c.terrain_packet == 1) && (c.bodies_flat == 0 || c.bodies_flat == 1) &&
+           (c.persistent == 0 || c.persistent == 1);
 }
 
 }  // namespace rc

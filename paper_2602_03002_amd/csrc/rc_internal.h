@@ -113,6 +113,7 @@ struct RenderCfg {
     int waves = 6;               // resident wavefronts per SIMD asked of the compiler (6, 7, 8)
     int persistent = 0;          // batched form: persistent work-queue launch (1) or flat grid (0)
     int terrain_packet = 0;      // terrain walked per lane (0) or as a wavefront packet (1)
+    int bodies_flat = 0;         // links found by the top-level walk (0) or by cone culling (1)
 };
 bool render_cfg_ok(const RenderCfg& c);
 hipError_t launch_render(const RenderLaunch& a, const RenderCfg& cfg, hipStream_t s);

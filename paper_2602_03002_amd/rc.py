@@ -78,7 +78,8 @@ class BatchArgs(ctypes.Structure):
 class RenderConfig(ctypes.Structure):
     _fields_ = [("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32),
                 ("rays_per_lane", ctypes.c_int32), ("waves", ctypes.c_int32),
-                ("persistent", ctypes.c_int32), ("terrain_packet", ctypes.c_int32)]
+                ("persistent", ctypes.c_int32), ("terrain_packet", ctypes.c_int32),
+                ("bodies_flat", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

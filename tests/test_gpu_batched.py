@@ -93,11 +93,12 @@ def test_batched_equals_plain_per_camera_and_oracle():
 
 
 @pytest.mark.parametrize("cfg", [
-    dict(tile_w=8, tile_h=8, rays_per_lane=1, waves=6, persistent=1, terrain_packet=0),
-    dict(tile_w=16, tile_h=4, rays_per_lane=2, waves=7, persistent=1, terrain_packet=1),
-    dict(tile_w=4, tile_h=16, rays_per_lane=1, waves=8, persistent=0, terrain_packet=0),
-    dict(tile_w=32, tile_h=2, rays_per_lane=2, waves=6, persistent=0, terrain_packet=1),
-    dict(tile_w=8, tile_h=8, rays_per_lane=1, waves=6, persistent=0, terrain_packet=1),
+    dict(tile_w=8, tile_h=8, rays_per_lane=1, waves=6, persistent=1, terrain_packet=0, bodies_flat=0),
+    dict(tile_w=16, tile_h=4, rays_per_lane=2, waves=7, persistent=1, terrain_packet=1, bodies_flat=1),
+    dict(tile_w=4, tile_h=16, rays_per_lane=1, waves=8, persistent=0, terrain_packet=0, bodies_flat=1),
+    dict(tile_w=32, tile_h=2, rays_per_lane=2, waves=6, persistent=0, terrain_packet=1, bodies_flat=0),
+    dict(tile_w=8, tile_h=8, rays_per_lane=1, waves=6, persistent=0, terrain_packet=1, bodies_flat=1),
+    dict(tile_w=8, tile_h=8, rays_per_lane=1, waves=7, persistent=0, terrain_packet=0, bodies_flat=1),
 ])
 def test_every_schedule_gives_identical_results(cfg):
     say(f"[batched] schedule {cfg}")
@@ -114,7 +115,8 @@ def test_every_schedule_gives_identical_results(cfg):
     sc.set_config(batched=False, **plain)
     r = sc.render(dev(w["cam_pos"]), dev(w["cam_quat"]), dev(w["intr"]), w["W"], w["H"], w["far"],
                   link_pos=dev(w["link_pos"][0]), link_quat=dev(w["link_quat"][0]))
-    sc.set_config(batched=False, tile_w=8, tile_h=8, rays_per_lane=1, waves=6, terrain_packet=0)
+    sc.set_config(batched=False, tile_w=8, tile_h=8, rays_per_lane=1, waves=6, terrain_packet=0,
+                  bodies_flat=0)
     r0 = sc.render(dev(w["cam_pos"]), dev(w["cam_quat"]), dev(w["intr"]), w["W"], w["H"], w["far"],
                    link_pos=dev(w["link_pos"][0]), link_quat=dev(w["link_quat"][0]))
     for g, h in zip(host(r), host(r0)):
