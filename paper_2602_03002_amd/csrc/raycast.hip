@@ -95,15 +95,34 @@ __device__ __forceinline__ Shear make_shear(float dx, float dy, float dz) {
 }
 
 // Slab test of one box (lo.x, hi.x, lo.y, hi.y, lo.z, hi.z) over [0, tmax].
+// OCT >= 0: the signs of (1/dx, 1/dy, 1/dz) are known (bit k set: axis k
+// negative), so the near and far planes are known and no min/max pairs are
+// needed; fma is monotonic, so the result equals the general form bit for bit.
+template <int OCT = -1>
 __device__ __forceinline__ bool slab(float lx, float hx, float ly, float hy, float lz, float hz,
                                      const Slab& r, float tmax, float& tn) {
-    float tx0 = __fmaf_rn(lx, r.ix, -r.oix), tx1 = __fmaf_rn(hx, r.ix, -r.oix);
-    float ty0 = __fmaf_rn(ly, r.iy, -r.oiy), ty1 = __fmaf_rn(hy, r.iy, -r.oiy);
-    float tz0 = __fmaf_rn(lz, r.iz, -r.oiz), tz1 = __fmaf_rn(hz, r.iz, -r.oiz);
-    float a = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fmaxf(fminf(tz0, tz1), 0.0f));
-    float b = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fminf(fmaxf(tz0, tz1), tmax));
+    float a, b;
+    if (OCT < 0) {
+        float tx0 = __fmaf_rn(lx, r.ix, -r.oix), tx1 = __fmaf_rn(hx, r.ix, -r.oix);
+        float ty0 = __fmaf_rn(ly, r.iy, -r.oiy), ty1 = __fmaf_rn(hy, r.iy, -r.oiy);
+        float tz0 = __fmaf_rn(lz, r.iz, -r.oiz), tz1 = __fmaf_rn(hz, r.iz, -r.oiz);
+        a = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fmaxf(fminf(tz0, tz1), 0.0f));
+        b = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fminf(fmaxf(tz0, tz1), tmax));
+    } else {
+        const float nx = (OCT & 1) ? hx : lx, fx = (OCT & 1) ? lx : hx;
+        const float ny = (OCT & 2) ? hy : ly, fy = (OCT & 2) ? ly : hy;
+        const float nz = (OCT & 4) ? hz : lz, fz = (OCT & 4) ? lz : hz;
+        a = fmaxf(fmaxf(__fmaf_rn(nx, r.ix, -r.oix), __fmaf_rn(ny, r.iy, -r.oiy)),
+                  fmaxf(__fmaf_rn(nz, r.iz, -r.oiz), 0.0f));
+        b = fminf(fminf(__fmaf_rn(fx, r.ix, -r.oix), __fmaf_rn(fy, r.iy, -r.oiy)),
+                  fminf(__fmaf_rn(fz, r.iz, -r.oiz), tmax));
+    }
     tn = a;
     return a <= b;
+}
+
+__device__ __forceinline__ int slab_octant(const Slab& r) {
+    return (r.ix < 0.0f ? 1 : 0) | (r.iy < 0.0f ? 2 : 0) | (r.iz < 0.0f ? 4 : 0);
 }
 
 // FP64 watertight test of one triangle; closed triangle, both sides; hit at t > 0.
@@ -334,7 +353,7 @@ __device__ __forceinline__ void tri_test(const float* __restrict__ v,
 constexpr int kStack = 12;
 constexpr int kLanes = 64 * kWavesPerBlock;
 
-template <typename Cnt, typename Leaf>
+template <int OCT = -1, typename Cnt, typename Leaf>
 __device__ __forceinline__ void traverse(const Node* __restrict__ nodes, int n_nodes, int n_prim,
                                          const Slab& r, Hit& h, Cnt& cnt, Leaf&& leaf,
                                          int start = 0, uint32_t* stk = nullptr) {
@@ -349,8 +368,8 @@ __device__ __forceinline__ void traverse(const Node* __restrict__ nodes, int n_n
         const int4 q3 = reinterpret_cast<const int4*>(np)[3];
         cnt.node();
         float tn0, tn1;
-        bool h0 = slab(q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, r, h.tmax, tn0);
-        bool h1 = slab(q1.z, q1.w, q2.x, q2.y, q2.z, q2.w, r, h.tmax, tn1);
+        bool h0 = slab<OCT>(q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, r, h.tmax, tn0);
+        bool h1 = slab<OCT>(q1.z, q1.w, q2.x, q2.y, q2.z, q2.w, r, h.tmax, tn1);
         const int c0 = q3.x, c1 = q3.y;
         // non-short-circuit forms: mask arithmetic instead of branches
         h0 = h0 & ((c0 >= 0) | ((unsigned)~c0 < (unsigned)n_prim));
@@ -635,7 +654,20 @@ __device__ __forceinline__ Hit cast_ray(const RenderLaunch& a, const CamRef& cam
                                 (uint32_t)a.n_links, ox, oy, oz, wm, kTerrainKappa, h, px, -1, i);
             };
             if (!(MODE & kPacketTerrain)) {
-                traverse(a.terrain_nodes, n_nodes, a.n_terrain, ws, h, cnt, leaf, entry, stk);
+                // a wavefront whose rays share one direction octant (the common
+                // case for a tile) runs the octant's specialised box tests
+                const int oct = slab_octant(ws);
+                const int oct0 = uni(oct);
+                if (WAVE && !EXACT && __ballot(oct != oct0) == 0ull) {
+                    switch (oct0) {
+#define RC_OCT(K) \
+    case K: traverse<K>(a.terrain_nodes, n_nodes, a.n_terrain, ws, h, cnt, leaf, entry, stk); break;
+                        RC_OCT(0) RC_OCT(1) RC_OCT(2) RC_OCT(3) RC_OCT(4) RC_OCT(5) RC_OCT(6) RC_OCT(7)
+#undef RC_OCT
+                    }
+                } else {
+                    traverse(a.terrain_nodes, n_nodes, a.n_terrain, ws, h, cnt, leaf, entry, stk);
+                }
             } else {
                 // Packet form: the wavefront walks the terrain hierarchy together
                 // (node index, trail and records wave-uniform); a child is
