@@ -544,9 +544,6 @@ __device__ __forceinline__ Hit cast_ray(const RenderLaunch& a, const CamRef& cam
                 keep = cmin <= -1.0f || __fmaf_rn(perp, cmin, -along * smin) <= rad;
             }
             uint64_t todo = __ballot(keep);
-            uint64_t mine = 0ull;  // this lane's links
-            const float dd = __fmaf_rn(dz, dz, __fmaf_rn(dy, dy, dx * dx));
-            const float idd = __builtin_amdgcn_rcpf(dd);
             while (todo) {  // wave-uniform loop over the surviving links
                 const int b = uni(__builtin_ctzll(todo));
                 todo &= todo - 1ull;
@@ -554,19 +551,14 @@ __device__ __forceinline__ Hit cast_ray(const RenderLaunch& a, const CamRef& cam
                 link_sphere(a, e, b, sx, sy, sz, sr);
                 // closest point of the lane's segment [o, o + tmax d] to the centre
                 const float wx = sx - ox, wy = sy - oy, wz = sz - oz;
-                const float tc = fminf(fmaxf(__fmaf_rn(wz, dz, __fmaf_rn(wy, dy, wx * dx)) * idd, 0.0f),
+                const float dd = __fmaf_rn(dz, dz, __fmaf_rn(dy, dy, dx * dx));
+                const float tc = fminf(fmaxf(__fmaf_rn(wz, dz, __fmaf_rn(wy, dy, wx * dx)) *
+                                                 __builtin_amdgcn_rcpf(dd), 0.0f),
                                        h.tmax);
                 const float qx = __fmaf_rn(-tc, dx, wx), qy = __fmaf_rn(-tc, dy, wy),
                             qz = __fmaf_rn(-tc, dz, wz);
-                if (__fmaf_rn(qz, qz, __fmaf_rn(qy, qy, qx * qx)) <= sr * sr) mine |= 1ull << b;
-            }
-            // each lane enters its own links: lanes in different links proceed
-            // together, so the wavefront pays the largest per-lane sum instead
-            // of the sum over links of the slowest lane
-            while (mine) {
-                const int b = __builtin_ctzll(mine);
-                mine &= mine - 1ull;
-                enter_link<EXACT>(a, e, b, ox, oy, oz, dx, dy, dz, h, px, cnt, stk);
+                if (__fmaf_rn(qz, qz, __fmaf_rn(qy, qy, qx * qx)) <= sr * sr)
+                    enter_link<EXACT>(a, e, b, ox, oy, oz, dx, dy, dz, h, px, cnt, stk);
             }
         } else {
             uint32_t trail = 0;
