@@ -344,20 +344,19 @@ __device__ __forceinline__ void tri_test(const float* __restrict__ v,
 // trail marks, per level below the start, whether the far child is still
 // pending.  With a short stack (stk: this lane's column of an LDS array,
 // kStack entries, stride kLanes), the pending far children of the shallowest
-// kStack such levels are kept there with their box entry distance, so
-// backtracking is a pop, and a far child whose box now starts beyond the
-// shrunken bound is dropped without being loaded; a pending level beyond them
-// is reached by climbing the parent links stored in the records, which is also
-// the whole mechanism without a stack.  Indices are range checked and the
-// loop is bounded (a valid hierarchy needs fewer than 2 n_nodes + 2 steps), so
-// a corrupt hierarchy ends the ray instead of faulting or spinning.
-constexpr int kStack = 8;
+// kStack such levels are kept there, so backtracking is a pop; a pending level
+// beyond them is reached by climbing the parent links stored in the records,
+// which is also the whole mechanism without a stack.  Indices are range
+// checked and the loop is bounded (a valid hierarchy needs fewer than
+// 2 n_nodes + 2 steps), so a corrupt hierarchy ends the ray instead of
+// faulting or spinning.
+constexpr int kStack = 12;
 constexpr int kLanes = 64 * kWavesPerBlock;
 
 template <int OCT = -1, typename Cnt, typename Leaf>
 __device__ __forceinline__ void traverse(const Node* __restrict__ nodes, int n_nodes, int n_prim,
                                          const Slab& r, Hit& h, Cnt& cnt, Leaf&& leaf,
-                                         int start = 0, uint2* stk = nullptr) {
+                                         int start = 0, uint32_t* stk = nullptr) {
     uint64_t trail = 0;
     int cur = start;
     int sp = 0;  // far children kept on the stack (the shallowest pending levels)
@@ -393,9 +392,7 @@ __device__ __forceinline__ void traverse(const Node* __restrict__ nodes, int n_n
             const bool first1 = tn1 < tn0;
             trail = (trail << 1) | 1ull;
             cur = first1 ? c1 : c0;
-            if (stk && sp < kStack)
-                stk[kLanes * sp++] = make_uint2((uint32_t)(first1 ? c0 : c1),
-                                                __float_as_uint(first1 ? tn0 : tn1));
+            if (stk && sp < kStack) stk[kLanes * sp++] = (uint32_t)(first1 ? c0 : c1);
             continue;
         }
         if (g0 || g1) {
@@ -403,20 +400,12 @@ __device__ __forceinline__ void traverse(const Node* __restrict__ nodes, int n_n
             cur = g0 ? c0 : c1;
             continue;
         }
-        // backtrack: pop while the deepest pending level is on the stack (its
-        // invariant: sp pending levels stored = the shallowest ones)
-        bool popped = false;
-        while (stk && trail != 0ull && __popcll(trail) == sp) {
-            trail = (trail >> __builtin_ctzll(trail)) ^ 1ull;
-            const uint2 e = stk[kLanes * --sp];
-            if (__uint_as_float(e.y) <= h.tmax) {
-                cur = (int)e.x;
-                popped = true;
-                break;
-            }
-        }
-        if (popped) continue;
         if (trail == 0ull) return;
+        if (stk && __popcll(trail) == sp) {  // the deepest pending level is on the stack
+            trail = (trail >> __builtin_ctzll(trail)) ^ 1ull;
+            cur = (int)stk[kLanes * --sp];
+            continue;
+        }
         // climb to the deepest level whose other child is pending
         int par = q3.z, sib = q3.w;
         for (;;) {
@@ -441,7 +430,7 @@ __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlan
 template <bool EXACT, typename Cnt>
 __device__ __forceinline__ void enter_link(const RenderLaunch& a, int e, int b, float ox, float oy,
                                            float oz, float dx, float dy, float dz, Hit& h,
-                                           const PixelRef& px, Cnt& cnt, uint2* stk) {
+                                           const PixelRef& px, Cnt& cnt, uint32_t* stk) {
     cnt.inst();
     const InstXform X = a.xf[(int64_t)e * a.n_links + b];
     const float px_ = ox - X.t[0], py_ = oy - X.t[1], pz_ = oz - X.t[2];
@@ -505,7 +494,7 @@ __device__ __forceinline__ void link_sphere(const RenderLaunch& a, int e, int b,
 // walks the top level alone.
 template <bool EXACT, bool WAVE, int MODE, typename Cnt>
 __device__ __forceinline__ Hit cast_ray(const RenderLaunch& a, const CamRef& cam, int e, int x, int y,
-                                        float bound, uint2* cand, uint2* stk,
+                                        float bound, uint2* cand, uint32_t* stk,
                                         Cnt& cnt) {
     double o64[3], d64[3], rx, ry;
     pixel_ray64(cam, x, y, o64, d64, rx, ry);
@@ -793,9 +782,9 @@ __device__ __forceinline__ void cast_tile(const RenderLaunch& a, const TileCfg& 
     const int span_h = c.th * RPL;
     const int xt = tx * c.tw + (lane % c.tw);
     __shared__ uint2 s_cand[kLanes * kCandSlots];
-    __shared__ uint2 s_stack[kLanes * kStack];
+    __shared__ uint32_t s_stack[kLanes * kStack];
     uint2* cand = s_cand + kCandSlots * threadIdx.x;
-    uint2* stk = s_stack + threadIdx.x;
+    uint32_t* stk = s_stack + threadIdx.x;
 #pragma unroll
     for (int r = 0; r < RPL; ++r) {
         const int y0 = ty * span_h + r * c.th;
