@@ -431,6 +431,21 @@ rc_status rc_postprocess_batched(rc_post* post, const float* depth_in, const int
 /* Release the handle (not the workspace). NULL is a no-op. */
 rc_status rc_post_destroy(rc_post* post);
 
+/* Downsample rendered frames by block pooling (the paper feeds its policy
+ * 240x135 depth downsampled to 48x27, Sec. 4.1; the pooling rule is not
+ * stated): output pixel (y, x) of image i is the mean depth of the hit pixels
+ * (inst >= 0, or depth < far_plane when inst is NULL) in rows [y f, y f + f)
+ * and columns [x f, x f + f), summed in row-major order in FP32, or
+ * far_plane when none of them hit.  depth_in, inst_in [n_img][height][width]
+ * and depth_out [n_img][height / f][width / f] (floor division; rows and
+ * columns beyond the last full block are ignored) are device memory owned by
+ * the caller.  Asynchronous on `stream`.  Errors: INVALID_ARG (NULL depth
+ * pointers, sizes < 1, factor < 1 or > min(height, width), an image of more
+ * than 2^31 - 1 pixels, non-finite far_plane), DEVICE. */
+rc_status rc_downsample(const float* depth_in, const int32_t* inst_in, int64_t n_img, int32_t height,
+                        int32_t width, int32_t factor, float far_plane, float* depth_out,
+                        rc_stream stream);
+
 /* ---------------------------------------------------------------------
  * Inspection of built hierarchies (for tests; no compute).
  * ------------------------------------------------------------------- */

@@ -139,3 +139,21 @@ def post(depth, inst, params, s0=0, cam_uid=None):
     if rc != 0:
         raise ValueError("oracle_post: bad arguments")
     return out, drop, lat
+
+
+def downsample(depth, inst, factor, far):
+    """Block pooling of frames [..., H, W] into [..., H // f, W // f]: the mean
+    depth (FP64) of the block's hit pixels (inst >= 0), or far when none hit.
+    The paper downsamples its 240x135 depth to 48x27 (Sec. 4.1) without naming
+    the pooling rule; this is the reading used."""
+    depth = np.asarray(depth, dtype=np.float64)
+    inst = np.asarray(inst)
+    f = int(factor)
+    H, W = depth.shape[-2], depth.shape[-1]
+    Ho, Wo = H // f, W // f
+    lead = depth.shape[:-2]
+    d = depth[..., :Ho * f, :Wo * f].reshape(lead + (Ho, f, Wo, f))
+    hit = (inst[..., :Ho * f, :Wo * f] >= 0).reshape(lead + (Ho, f, Wo, f))
+    s = np.where(hit, d, 0.0).sum(axis=(-3, -1))
+    n = hit.sum(axis=(-3, -1))
+    return np.where(n > 0, s / np.maximum(n, 1), float(far))

@@ -859,6 +859,22 @@ rc_status rc_postprocess_batched(rc_post* post, const float* depth_in, const int
     return RC_OK;
 }
 
+rc_status rc_downsample(const float* depth_in, const int32_t* inst_in, int64_t n_img, int32_t height,
+                        int32_t width, int32_t factor, float far_plane, float* depth_out,
+                        rc_stream stream) {
+    if (!depth_in || !depth_out) return fail(RC_ERR_INVALID_ARG, "rc_downsample: NULL depth pointer");
+    if (n_img < 1 || height < 1 || width < 1 || factor < 1 || factor > height || factor > width)
+        return fail(RC_ERR_INVALID_ARG, "rc_downsample: need n_img, height, width >= 1 and "
+                                        "1 <= factor <= min(height, width)");
+    if ((int64_t)height * width > (int64_t)0x7FFFFFFF)
+        return fail(RC_ERR_INVALID_ARG, "rc_downsample: image too large");
+    if (!std::isfinite(far_plane)) return fail(RC_ERR_INVALID_ARG, "rc_downsample: far_plane not finite");
+    hipError_t e = launch_downsample(depth_in, inst_in, n_img, height, width, factor, far_plane,
+                                     depth_out, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "rc_downsample: launch");
+    return RC_OK;
+}
+
 rc_status rc_post_destroy(rc_post* post) {
     delete post;
     return RC_OK;

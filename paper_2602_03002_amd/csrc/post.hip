@@ -114,7 +114,47 @@ __global__ void __launch_bounds__(256) k_post_batched(PostLaunch a, const rc_cam
         post_pixel(a, (int64_t)D.out_offset + q, (uint32_t)q, D.cam_uid, k);
 }
 
+// Block pooling of rendered frames (the paper feeds its policy 240x135 depth
+// downsampled to 48x27, Sec. 4.1): output pixel (oy, ox) is the mean depth of
+// the hit pixels of its f x f block, summed in row-major order, or far when
+// none of them hit.  Grid: x over the output pixels of an image, y over images.
+__global__ void __launch_bounds__(256) k_downsample(const float* __restrict__ depth,
+                                                    const int32_t* __restrict__ inst, int64_t n_img,
+                                                    int H, int W, int f, float far_plane,
+                                                    float* __restrict__ out) {
+    const int Ho = H / f, Wo = W / f;
+    const int per = Ho * Wo;
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= per) return;
+    const int oy = q / Wo, ox = q - oy * Wo;
+    for (int64_t img = blockIdx.y; img < n_img; img += gridDim.y) {
+        const int64_t base = img * H * W + (int64_t)(oy * f) * W + (int64_t)ox * f;
+        float sum = 0.0f;
+        int cnt = 0;
+        for (int dy = 0; dy < f; ++dy)
+            for (int dx = 0; dx < f; ++dx) {
+                const int64_t p = base + (int64_t)dy * W + dx;
+                const float z = depth[p];
+                const bool hit = inst ? inst[p] >= 0 : z < far_plane;
+                if (hit) {
+                    sum += z;
+                    ++cnt;
+                }
+            }
+        out[img * per + q] = cnt ? sum / (float)cnt : far_plane;
+    }
+}
+
 }  // namespace
+
+hipError_t launch_downsample(const float* depth, const int32_t* inst, int64_t n_img, int H, int W,
+                             int f, float far_plane, float* out, hipStream_t s) {
+    const int per = (H / f) * (W / f);
+    const unsigned gy = (unsigned)std::min<int64_t>(n_img, 65535);
+    hipLaunchKernelGGL(k_downsample, dim3((unsigned)((per + 255) / 256), gy), dim3(256), 0, s, depth,
+                       inst, n_img, H, W, f, far_plane, out);
+    return hipGetLastError();
+}
 
 hipError_t launch_post(const PostLaunch& a, hipStream_t s) {
     const int64_t hw = (int64_t)a.height * a.width;

@@ -22,6 +22,7 @@ EXPORTED = [
     "rc_robot_size", "rc_robot_meshes",
     "rc_render_size", "rc_render", "rc_render_exact_count", "rc_render_counts",
     "rc_post_size", "rc_post_create", "rc_post_reset", "rc_postprocess", "rc_post_destroy",
+    "rc_downsample",
     "rc_bvh_layout_of",
     "rc_render_batched_size", "rc_render_batched", "rc_render_batched_status",
     "rc_get_render_config", "rc_set_render_config", "rc_autotune",
@@ -147,6 +148,7 @@ def lib():
         L.rc_post_size.argtypes = [i32, i32, i32, i32, i32, ctypes.POINTER(sz)]
         L.rc_post_create.argtypes = [i32, i32, i32, i32, i32, vp, sz, ctypes.POINTER(vp)]
         L.rc_post_reset.argtypes = [vp]
+        L.rc_downsample.argtypes = [vp, vp, i64, i32, i32, i32, ctypes.c_float, vp, vp]
         L.rc_postprocess.argtypes = [vp, vp, vp, ctypes.POINTER(PostParams), ctypes.c_uint64, vp,
                                      vp, vp, vp, vp]
         L.rc_post_destroy.argtypes = [vp]
@@ -463,6 +465,23 @@ class Graph:
             self.close()
         except Exception:
             pass
+
+
+def downsample(depth, inst, factor, far_plane, out=None, stream=None):
+    """Block pooling of frames [..., H, W] (mean of hit pixels, else far_plane)
+    into [..., H // factor, W // factor]."""
+    H, W = depth.shape[-2], depth.shape[-1]
+    lead = depth.shape[:-2]
+    n_img = 1
+    for d in lead:
+        n_img *= d
+    _dev_f32(depth, depth.shape, "depth")
+    if out is None:
+        out = torch.empty(tuple(lead) + (H // factor, W // factor), dtype=torch.float32,
+                          device=depth.device)
+    check(lib().rc_downsample(_ptr(depth), _ptr(inst), n_img, H, W, factor, float(far_plane),
+                              _ptr(out), _stream(stream)))
+    return out
 
 
 def post_params(seed=0, sigma_abs=0.0, sigma_rel=0.0, p_drop=0.0, near=0.05, far=3.0, fill=0.0,

@@ -7,5 +7,6 @@ from .terrain import ProfileTerrain, TileTerrain, SlopeTile, StairsTile, StonesT
 from .robot import Robot, octasphere, quat_from_matrix, N_LINKS
 from .cameras import intrinsics_from_fov, optical_axes, mounted_cameras
 from .workloads import (small_plain_case, robot_scene, robots_64, robots_4096, uneven_cameras,
-                        uneven_4096, CAM_DESC, RES_SET,
+                        uneven_4096, CAM_DESC, RES_SET, table1, TABLE1_W, TABLE1_H,
+                        TABLE1_HFOV, TABLE1_VFOV, TABLE1_POOL,
                         synthetic_frames, SENSOR, NEAR, FAR)

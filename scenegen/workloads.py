@@ -46,7 +46,7 @@ def env_grid(side, spacing):
 
 
 def robot_scene(n_tiles, env_side, spacing, n_cam, W, H, steps, seed=MASTER_SEED,
-                label="scene", terrain=None, robot=None):
+                label="scene", terrain=None, robot=None, hfov=HFOV, vfov=VFOV):
     """Envs on a tile terrain, each with the 30-link robot and mounted cameras."""
     terr = terrain if terrain is not None else TileTerrain(n_tiles, seed=seed)
     rob = robot if robot is not None else Robot(seed=seed)
@@ -64,7 +64,7 @@ def robot_scene(n_tiles, env_side, spacing, n_cam, W, H, steps, seed=MASTER_SEED
         link_pos[s] = p
         link_quat[s] = quat_from_matrix(R)
     cam_pos, cam_quat = mounted_cameras(root_pos, yaw_matrix(yaw), n_cam)
-    intr = np.broadcast_to(intrinsics_from_fov(W, H, HFOV, VFOV), (E, n_cam, 4))
+    intr = np.broadcast_to(intrinsics_from_fov(W, H, hfov, vfov), (E, n_cam, 4))
     link_tri, link_off = rob.link_triangles()
     return dict(
         name=f"{E} envs x {n_cam} cams {W}x{H}, {n_tiles}x{n_tiles} tiles, 30 links",
@@ -86,6 +86,19 @@ def robots_64():
 def robots_4096(steps=100):
     """4096 envs x 2 cams 64x48 on a 20x20 tile terrain (about 2M triangles)."""
     return robot_scene(20, 64, 2.5, 2, 64, 48, steps=steps, label="robots4096")
+
+
+# The paper's perception setting (Sec. 4.1, Perception Settings; Table 1):
+# 1024 envs, up to 4 cameras (front, rear, left, right), 240x135 raw depth at
+# 101 x 69 degrees, downsampled to 48x27.
+TABLE1_W, TABLE1_H, TABLE1_HFOV, TABLE1_VFOV, TABLE1_POOL = 240, 135, 101.0, 69.0, 5
+
+
+def table1(n_cam, steps=3, terrain=None, robot=None):
+    """1024 envs x n_cam x 240x135 at 101x69 degrees on the 20x20 tile terrain
+    (a 32 x 32 env grid at 5 m spacing)."""
+    return robot_scene(20, 32, 5.0, n_cam, TABLE1_W, TABLE1_H, steps=steps, label="table1",
+                       terrain=terrain, robot=robot, hfov=TABLE1_HFOV, vfov=TABLE1_VFOV)
 
 
 def synthetic_frames(E, C, H, W, steps, seed=MASTER_SEED, label="frames", far=FAR):

@@ -370,3 +370,42 @@ def test_post_latency_semantics_and_histogram():
     expect = ks.size / 3
     chi2 = np.sum((counts - expect) ** 2 / expect)
     assert chi2 < 13.8  # chi-square, 2 dof, p = 0.001
+
+
+# ---------------------------------------------------------------------------
+# block pooling of frames (240x135 -> 48x27, Sec. 4.1)
+# ---------------------------------------------------------------------------
+
+def test_downsample_worked_example():
+    far = 3.0
+    depth = np.array([[1.0, 2.0, 5.0, 5.0],
+                      [3.0, 9.0, 5.0, 5.0]])
+    inst = np.array([[0, 4, -1, -1],
+                     [30, -1, -1, -1]])
+    out = oracle.downsample(depth[None], inst[None], 2, far)[0]
+    # block 0: hits 1, 2, 3 (the 9 is a miss), block 1: no hit -> far
+    assert out.shape == (1, 2)
+    assert out[0, 0] == pytest.approx(2.0, abs=0) and out[0, 1] == far
+
+
+def test_downsample_constant_all_hit_and_all_miss():
+    d = np.full((2, 3, 10, 15), 1.25)
+    hit = np.zeros(d.shape, np.int32)
+    assert np.all(oracle.downsample(d, hit, 5, 3.0) == 1.25)
+    assert np.all(oracle.downsample(d, hit - 1, 5, 3.0) == 3.0)
+
+
+def test_downsample_brute_force_and_trailing_pixels():
+    rng = np.random.default_rng(4)
+    H, W, f = 7, 11, 3
+    d = rng.uniform(0.1, 3.0, (2, H, W))
+    inst = rng.integers(-1, 3, (2, H, W))
+    got = oracle.downsample(d, inst, f, 3.0)
+    assert got.shape == (2, H // f, W // f)
+    for i in range(2):
+        for y in range(H // f):
+            for x in range(W // f):
+                vals = [d[i, yy, xx] for yy in range(y * f, y * f + f) for xx in range(x * f, x * f + f)
+                        if inst[i, yy, xx] >= 0]
+                want = sum(vals) / len(vals) if vals else 3.0
+                assert got[i, y, x] == pytest.approx(want, rel=1e-15, abs=1e-15)
