@@ -476,7 +476,7 @@ def downsample(depth, inst, factor, far_plane, out=None, stream=None):
     for d in lead:
         n_img *= d
     _dev_f32(depth, depth.shape, "depth")
-    if out is None:
+    if out is None and 1 <= factor <= min(H, W):  # other factors: the library reports the error
         out = torch.empty(tuple(lead) + (H // factor, W // factor), dtype=torch.float32,
                           device=depth.device)
     check(lib().rc_downsample(_ptr(depth), _ptr(inst), n_img, H, W, factor, float(far_plane),
