@@ -404,7 +404,7 @@ def bench_serving(sc, w_main, capacity_mrays, duration_s=6.0, stream_s=60.0):
     lit["load"] = "2000 req/s (the stated stream)"
     runs.append(lit)
     print(f"[bench] serving {lit}", file=sys.stderr, flush=True)
-    base = run(2000.0, duration_s / 2, n_streams=1, max_batch_rays=1)
+    base = run(2000.0, stream_s, n_streams=1, max_batch_rays=1)
     base["load"] = "2000 req/s, one request per launch on one stream (plain per-request)"
     print(f"[bench] serving {base}", file=sys.stderr, flush=True)
     return {"mean_rays_per_request": round(mean_rays), "runs": runs, "plain_per_request": base,
