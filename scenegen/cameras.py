@@ -32,7 +32,7 @@ def optical_axes(forward_yaw, pitch_down):
     return np.stack([x, y, z], 1)
 
 
-# front and back depth cameras (the paper deploys a front-back pair, Sec. 4.1)
+# front, rear, left and right depth cameras (Sec. 4.1; the paper deploys the front-rear pair)
 MOUNTS = [
     (np.array([0.20, 0.0, 0.25]), optical_axes(0.0, math.radians(45.0))),
     (np.array([-0.20, 0.0, 0.25]), optical_axes(math.pi, math.radians(45.0))),
