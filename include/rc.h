@@ -107,6 +107,28 @@ rc_status rc_robot_meshes(rc_scene* scene, const float* link_tri, const int64_t*
 #define RC_DEPTH_PLANAR 0 /* optical-z depth (what depth cameras report) */
 #define RC_DEPTH_RANGE 1  /* distance along the ray */
 
+/* Perception randomisation of the cameras (the paper's Table 6: depth camera
+ * translation, rotation as Euler angles and field of view, each uniform in a
+ * symmetric range), drawn on the device per camera and launch.  For camera
+ * uid u (plain form: env * n_cam + cam; batched form: the descriptor's
+ * cam_uid) the words of Philox4x32-10 with key = seed and counter
+ * (u, 0xFFFFFFFE, epoch_lo32, (epoch_hi16 << 16) | s) give, for s = 2,
+ * (tx, ty, tz, phi) and, for s = 3, (theta, psi, dfov, unused), each as
+ * a (2u - 1) with u = (w >> 8) 2^-24 and a the half-range.  The translation is
+ * in the camera's own frame, the rotation is R Rx(phi) Ry(theta) Rz(psi)
+ * (about the camera's x, y, z), and the field of view of both axes changes
+ * by dfov: f' = c / tan(atan(c / f) + dfov / 2) (skipped when dfov_deg = 0).
+ * Computed in FP64 once per camera; epoch lets the caller redraw (e.g. per
+ * episode).  Half-ranges must be finite and >= 0, dfov_deg < 90. */
+typedef struct {
+    uint64_t seed;
+    uint64_t epoch;
+    float trans_m[3];    /* half-ranges of the offsets along the camera's x, y, z (m) */
+    float euler_deg[3];  /* half-ranges of the rotations about x, y, z (degrees) */
+    float dfov_deg;      /* half-range of the field-of-view change (degrees) */
+    float reserved;
+} rc_cam_rand;
+
 typedef struct {
     int32_t n_env, n_cam, width, height;
     const float* link_pos;  /* device [n_env][n_links][3]: t_b per env (world, m) */
@@ -121,6 +143,7 @@ typedef struct {
     int32_t* tri;           /* device out, same shape, or NULL */
     void* const* timing;    /* NULL, or host array of two hipEvent_t recorded on the
                                stream just before and after the fast-pass kernel */
+    const rc_cam_rand* cam_rand; /* NULL, or host struct: randomise the cameras */
 } rc_render_args;
 
 /* Workspace bytes of rc_render for n_env x n_cam images of width x height:
@@ -198,6 +221,7 @@ typedef struct {
     int32_t* inst;             /* device out [n_pixels] or NULL */
     int32_t* tri;              /* device out [n_pixels] or NULL */
     void* const* timing;       /* NULL, or two hipEvent_t around the fast-pass kernel */
+    const rc_cam_rand* cam_rand; /* NULL, or host struct: randomise the cameras */
 } rc_batch_args;
 
 /* Workspace bytes of rc_render_batched. */

@@ -7,6 +7,7 @@ paper (Sec. 3.2.2, Algorithm 1; sensor model in Sec. 1, Sec. 4.1 and Table
 ``oracle/build.py`` (gcc, OpenMP) into ``oracle/liboracle.so``.
 """
 import ctypes
+import math
 import os
 import numpy as np
 
@@ -58,11 +59,13 @@ def _f32(a):
 
 
 def render(terrain, link_tri, link_off, link_pos, link_quat, cam_pos, cam_quat, intr,
-           W, H, far, depth_mode=0, rays=None, K=8):
+           W, H, far, depth_mode=0, rays=None, K=8, cam64=None):
     """Brute-force FP64 render.
 
     terrain [T,3,3]; link_tri [LT,3,3] with link_off [B+1]; link_pos [E,B,3];
     link_quat [E,B,4]; cam_pos [E,C,3]; cam_quat [E,C,4]; intr [E,C,4].
+    cam64: optional FP64 cameras [E,C,16] (R row-major, p, fx, fy, cx, cy)
+    replacing cam_pos / cam_quat / intr (see cam_randomize).
     rays: optional int64 linear pixel ids into [E,C,H,W].
     Returns dict(depth f64, inst i32, tri i32, flags i32, cand i32 [n,K,2],
     cand_depth f64 [n,K]); flat over ``rays`` (or all pixels).
@@ -88,13 +91,14 @@ def render(terrain, link_tri, link_off, link_pos, link_quat, cam_pos, cam_quat, 
     flags = np.empty(n, np.int32)
     cand = np.empty((n, K, 2), np.int32)
     cand_d = np.empty((n, K), np.float64)
+    c64 = None if cam64 is None else np.ascontiguousarray(cam64, dtype=np.float64).reshape(E, C, 16)
     rc = lib().oracle_render(
         _p(terrain), ctypes.c_int64(terrain.shape[0]), _p(link_tri), _p(link_off), ctypes.c_int(B),
         _p(link_pos), _p(link_quat), _p(cam_pos), _p(cam_quat), _p(intr),
         ctypes.c_int(E), ctypes.c_int(C), ctypes.c_int(W), ctypes.c_int(H),
         ctypes.c_double(far), ctypes.c_int(depth_mode),
         _p(rays), ctypes.c_int64(n),
-        _p(depth), _p(inst), _p(tri), _p(flags), _p(cand), _p(cand_d), ctypes.c_int(K))
+        _p(depth), _p(inst), _p(tri), _p(flags), _p(cand), _p(cand_d), ctypes.c_int(K), _p(c64))
     if rc != 0:
         raise ValueError("oracle_render: bad arguments")
     return dict(depth=depth, inst=inst, tri=tri, flags=flags, cand=cand, cand_depth=cand_d)
@@ -157,3 +161,53 @@ def downsample(depth, inst, factor, far):
     s = np.where(hit, d, 0.0).sum(axis=(-3, -1))
     n = hit.sum(axis=(-3, -1))
     return np.where(n > 0, s / np.maximum(n, 1), float(far))
+
+
+def cam_randomize(cam_pos, cam_quat, intr, cam_uid, seed, epoch, trans_m, euler_deg, dfov_deg):
+    """Per-camera perception randomisation (the paper's Table 6: depth camera
+    translation, rotation as Euler angles and field of view, each uniform in a
+    symmetric range) as FP64 cameras [N,16] (R row-major, p, fx, fy, cx, cy).
+
+    Draws: Philox4x32-10 with key = seed and counter (uid, 0xFFFFFFFE,
+    epoch_lo32, (epoch_hi16 << 16) | stream), stream 2 -> (tx, ty, tz, phi),
+    stream 3 -> (theta, psi, dfov, -); u = (w >> 8) 2^-24, offset = a (2u - 1).
+    The translation is taken in the camera's own (unperturbed) frame, the
+    rotation is R0 Rx(phi) Ry(theta) Rz(psi) (about the camera's x, y, z),
+    and the field of view widens both axes: f' = c / tan(atan(c / f) + dfov / 2)
+    (no change when the FOV range is 0)."""
+    pos = np.asarray(cam_pos, np.float64).reshape(-1, 3)
+    quat = np.asarray(cam_quat, np.float64).reshape(-1, 4)
+    K = np.asarray(intr, np.float64).reshape(-1, 4)
+    uid = np.asarray(cam_uid, np.uint64).reshape(-1)
+    out = np.zeros((pos.shape[0], 16))
+    e_lo = int(epoch) & 0xFFFFFFFF
+    e_hi = (int(epoch) >> 32) & 0xFFFF
+    key = np.array([int(seed) & 0xFFFFFFFF, (int(seed) >> 32) & 0xFFFFFFFF], np.uint32)
+
+    def offsets(w, a):
+        u = (np.asarray(w, np.uint64) >> np.uint64(8)).astype(np.float64) * 2.0 ** -24
+        return np.asarray(a, np.float64) * (2.0 * u - 1.0)
+
+    for i in range(pos.shape[0]):
+        w2 = philox(np.array([uid[i], 0xFFFFFFFE, e_lo, (e_hi << 16) | 2], np.uint32), key)
+        w3 = philox(np.array([uid[i], 0xFFFFFFFE, e_lo, (e_hi << 16) | 3], np.uint32), key)
+        t = offsets(w2[:3], trans_m)
+        ang = np.radians(offsets([w2[3], w3[0], w3[1]], euler_deg))
+        dfov = math.radians(float(offsets([w3[2]], [dfov_deg])[0]))
+        x, y, z, w = quat[i] / np.linalg.norm(quat[i])
+        R0 = np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - z * w), 2 * (x * z + y * w)],
+                       [2 * (x * y + z * w), 1 - 2 * (x * x + z * z), 2 * (y * z - x * w)],
+                       [2 * (x * z - y * w), 2 * (y * z + x * w), 1 - 2 * (x * x + y * y)]])
+        c, s_ = np.cos(ang), np.sin(ang)
+        Rx = np.array([[1, 0, 0], [0, c[0], -s_[0]], [0, s_[0], c[0]]])
+        Ry = np.array([[c[1], 0, s_[1]], [0, 1, 0], [-s_[1], 0, c[1]]])
+        Rz = np.array([[c[2], -s_[2], 0], [s_[2], c[2], 0], [0, 0, 1]])
+        R = R0 @ Rx @ Ry @ Rz
+        fx, fy, cx, cy = K[i]
+        if float(dfov_deg) != 0.0:
+            fx = cx / math.tan(math.atan(cx / fx) + dfov / 2)
+            fy = cy / math.tan(math.atan(cy / fy) + dfov / 2)
+        out[i, :9] = R.ravel()
+        out[i, 9:12] = pos[i] + R0 @ t
+        out[i, 12:] = (fx, fy, cx, cy)
+    return out

@@ -114,6 +114,7 @@ typedef struct {
     const float* link_tri; const int64_t* link_off; int n_links;
     const float* link_pos; const float* link_quat;  /* [E][B][3], [E][B][4] */
     const float* cam_pos; const float* cam_quat; const float* intr; /* [E][C][*] */
+    const double* cam64;  /* optional [E][C][16]: R row-major [9], p [3], fx, fy, cx, cy */
     int E, C, W, H;
     double far; int depth_mode; /* 0 planar, 1 range */
 } scene_t;
@@ -122,13 +123,25 @@ typedef struct {
 static double make_ray(const scene_t* s, int64_t p, v3* o, v3* d, int* env) {
     int64_t x = p % s->W, y = (p / s->W) % s->H;
     int64_t ec = p / ((int64_t)s->W * s->H);
-    const float* K = s->intr + 4 * ec;
-    v3 r = {((double)x + 0.5 - (double)K[2]) / (double)K[0],
-            ((double)y + 0.5 - (double)K[3]) / (double)K[1], 1.0};
-    double R[9];
-    quat_to_mat(s->cam_quat + 4 * ec, R);
+    double R[9], fx, fy, cx, cy;
+    if (s->cam64) {  /* a camera given in FP64 (e.g. after randomisation) */
+        const double* c = s->cam64 + 16 * ec;
+        for (int k = 0; k < 9; ++k) R[k] = c[k];
+        fx = c[12]; fy = c[13]; cx = c[14]; cy = c[15];
+    } else {
+        const float* K = s->intr + 4 * ec;
+        fx = K[0]; fy = K[1]; cx = K[2]; cy = K[3];
+        quat_to_mat(s->cam_quat + 4 * ec, R);
+    }
+    v3 r = {((double)x + 0.5 - cx) / fx, ((double)y + 0.5 - cy) / fy, 1.0};
     *d = mat_mul(R, r);
-    *o = v3f(s->cam_pos + 3 * ec);
+    if (s->cam64) {
+        const double* c = s->cam64 + 16 * ec;
+        v3 po = {c[9], c[10], c[11]};
+        *o = po;
+    } else {
+        *o = v3f(s->cam_pos + 3 * ec);
+    }
     *env = (int)(ec / s->C);
     return s->depth_mode == 1 ? sqrt(dot(r, r)) : 1.0;
 }
@@ -223,6 +236,8 @@ static void render_ray(const scene_t* s, int64_t p, double* depth, int32_t* inst
  * oracle_render: depth, inst, tri and flags for the listed pixels.
  * rays: linear indices into [E][C][H][W] (n of them), or NULL for all pixels.
  * cand [n][K][2] / cand_depth [n][K]: nearest candidates (any ray), -1/NaN pad.
+ * cam64: NULL, or FP64 cameras [E][C][16] (R row-major, p, fx, fy, cx, cy)
+ * that replace cam_pos / cam_quat / intr.
  * Returns 0, or -1 on bad arguments.
  */
 /* Host threads of the parallel loops (timing of the oracle only). */
@@ -236,10 +251,10 @@ int oracle_render(const float* terrain, int64_t n_terrain,
                   int E, int C, int W, int H, double far, int depth_mode,
                   const int64_t* rays, int64_t n,
                   double* depth, int32_t* inst, int32_t* tri, int32_t* flags,
-                  int32_t* cand, double* cand_depth, int K) {
+                  int32_t* cand, double* cand_depth, int K, const double* cam64) {
     if (E < 0 || C < 0 || W < 0 || H < 0 || n_links < 0 || n_terrain < 0 || K < 1) return -1;
     scene_t s = {terrain, n_terrain, link_tri, link_off, n_links, link_pos, link_quat,
-                 cam_pos, cam_quat, intr, E, C, W, H, far, depth_mode};
+                 cam_pos, cam_quat, intr, cam64, E, C, W, H, far, depth_mode};
     int64_t total = (int64_t)E * C * H * W;
     if (rays == NULL) n = total;
     #pragma omp parallel for schedule(dynamic, 16)

@@ -317,6 +317,21 @@ static void fill_scene(const rc_scene* scene, RenderLaunch& L) {
     L.n_terrain = (int)scene->terrain.n_prim;
 }
 
+static bool cam_rand_ok(const rc_cam_rand* r) {
+    if (!r) return true;
+    for (int k = 0; k < 3; ++k)
+        if (!(r->trans_m[k] >= 0.0f) || !std::isfinite(r->trans_m[k]) || !(r->euler_deg[k] >= 0.0f) ||
+            !std::isfinite(r->euler_deg[k]))
+            return false;
+    return r->dfov_deg >= 0.0f && r->dfov_deg < 90.0f;
+}
+
+static void set_cam_rand(RenderLaunch& L, const rc_cam_rand* r) {
+    L.cam_rand_on = r ? 1 : 0;
+    if (r) L.cam_rand = *r;
+    else std::memset(&L.cam_rand, 0, sizeof(L.cam_rand));
+}
+
 static rc_status prep_plain(const rc_scene* scene, const rc_render_args* a, void* ws,
                             size_t ws_bytes, RenderLaunch& L, const char* who) {
     const std::string w(who);
@@ -333,6 +348,9 @@ static rc_status prep_plain(const rc_scene* scene, const rc_render_args* a, void
         return fail(RC_ERR_INVALID_ARG, w + ": far_plane must be finite and > 0");
     if (a->depth_mode != RC_DEPTH_PLANAR && a->depth_mode != RC_DEPTH_RANGE)
         return fail(RC_ERR_INVALID_ARG, w + ": unknown depth_mode");
+    if (!cam_rand_ok(a->cam_rand))
+        return fail(RC_ERR_INVALID_ARG, w + ": camera randomisation ranges must be finite and "
+                                            ">= 0, dfov_deg < 90");
     const int64_t n_rays = (int64_t)a->n_env * a->n_cam * a->width * a->height;
     const RenderWs W = render_layout(a->n_env, n_rays, scene->n_links, 0, (int64_t)a->n_env * a->n_cam);
     if (!ws || ws_bytes < W.end || !aligned(ws))
@@ -359,6 +377,7 @@ static rc_status prep_plain(const rc_scene* scene, const rc_render_args* a, void
     L.exact_list = (uint4*)((char*)ws + W.list);
     L.exact_cap = W.cap;
     L.cam_basis = (double*)((char*)ws + W.cams);
+    set_cam_rand(L, a->cam_rand);
     L.ev_begin = a->timing ? (hipEvent_t)a->timing[0] : nullptr;
     L.ev_end = a->timing ? (hipEvent_t)a->timing[1] : nullptr;
     L.desc = nullptr;
@@ -452,6 +471,9 @@ static rc_status prep_batched(const rc_scene* scene, const rc_batch_args* a, voi
         return fail(RC_ERR_INVALID_ARG, w + ": far_plane must be finite and > 0");
     if (a->depth_mode != RC_DEPTH_PLANAR && a->depth_mode != RC_DEPTH_RANGE)
         return fail(RC_ERR_INVALID_ARG, w + ": unknown depth_mode");
+    if (!cam_rand_ok(a->cam_rand))
+        return fail(RC_ERR_INVALID_ARG, w + ": camera randomisation ranges must be finite and "
+                                            ">= 0, dfov_deg < 90");
     W = render_layout(a->n_env, a->n_pixels, scene->n_links, a->n_desc, a->n_desc, cap_rays);
     if (!ws || ws_bytes < W.end || !aligned(ws))
         return fail(RC_ERR_WORKSPACE, w + ": workspace needs " + std::to_string(W.end) +
@@ -474,6 +496,7 @@ static rc_status prep_batched(const rc_scene* scene, const rc_batch_args* a, voi
     L.exact_list = (uint4*)((char*)ws + W.list);
     L.exact_cap = W.cap;
     L.cam_basis = (double*)((char*)ws + W.cams);
+    set_cam_rand(L, a->cam_rand);
     L.ev_begin = a->timing ? (hipEvent_t)a->timing[0] : nullptr;
     L.ev_end = a->timing ? (hipEvent_t)a->timing[1] : nullptr;
     L.desc = a->desc;

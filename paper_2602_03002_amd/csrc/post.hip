@@ -17,19 +17,6 @@ namespace rc {
 
 namespace {
 
-__device__ __forceinline__ uint4 philox10(uint4 c, uint32_t k0, uint32_t k1) {
-    for (int r = 0; r < 10; ++r) {
-        // one 32 x 32 -> 64-bit multiply gives both halves of each product
-        const uint64_t p0 = (uint64_t)0xD2511F53u * c.x, p1 = (uint64_t)0xCD9E8D57u * c.z;
-        const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
-        const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
-        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
-        k0 += 0x9E3779B9u;
-        k1 += 0xBB67AE85u;
-    }
-    return c;
-}
-
 __device__ __forceinline__ uint32_t step_hi(uint64_t s) {
     return (uint32_t)(((s >> 32) & 0xFFFFull) << 16);
 }
@@ -38,7 +25,7 @@ __device__ __forceinline__ uint32_t step_hi(uint64_t s) {
 __device__ __forceinline__ int latency_draw(const PostLaunch& a, uint32_t uid) {
     if (!(a.flags & RC_POST_LATENCY)) return 0;
     const uint64_t s = a.step;
-    const uint4 wl = philox10(make_uint4(0xFFFFFFFFu, uid, (uint32_t)s, step_hi(s) | 1u),
+    const uint4 wl = philox4x32_10(make_uint4(0xFFFFFFFFu, uid, (uint32_t)s, step_hi(s) | 1u),
                               (uint32_t)a.seed, (uint32_t)(a.seed >> 32));
     const uint64_t span = (uint64_t)(a.lat_max - a.lat_min + 1);
     return a.lat_min + (int)(((uint64_t)wl.x * span) >> 32);
@@ -54,7 +41,7 @@ __device__ __forceinline__ void post_pixel(const PostLaunch& a, int64_t p, uint3
     // capture of this step
     const float z = a.depth_in[p];
     const bool hit = a.inst_in ? (a.inst_in[p] >= 0) : (z < a.far_plane);
-    const uint4 wd = philox10(make_uint4(pix, uid, (uint32_t)s, step_hi(s)), k0, k1);
+    const uint4 wd = philox4x32_10(make_uint4(pix, uid, (uint32_t)s, step_hi(s)), k0, k1);
     const bool drop = (a.flags & RC_POST_DROPOUT) && ((uint64_t)wd.x < a.drop_thr);
     float zz;
     if (hit) {

@@ -752,17 +752,58 @@ __device__ __forceinline__ CamRef launch_cam(const RenderLaunch& a, int64_t inde
     return CamRef{a.cam_basis + kCamBasis * index};
 }
 
-// Ray bases of every camera of the launch.
+// Perception randomisation of one camera basis b (the draws and the rules are
+// stated with rc_cam_rand): offset = a (2u - 1), u = (w >> 8) 2^-24.
+__device__ __forceinline__ double rand_offset(uint32_t w, float half) {
+    return (double)half * (2.0 * ((double)(w >> 8) * 5.9604644775390625e-08) - 1.0);
+}
+
+__device__ void cam_randomize(const rc_cam_rand& p, uint32_t uid, double* b) {
+    const uint32_t k0 = (uint32_t)p.seed, k1 = (uint32_t)(p.seed >> 32);
+    const uint32_t e_lo = (uint32_t)p.epoch, e_hi = (uint32_t)((p.epoch >> 32) & 0xFFFFull) << 16;
+    const uint4 w2 = philox4x32_10(make_uint4(uid, 0xFFFFFFFEu, e_lo, e_hi | 2u), k0, k1);
+    const uint4 w3 = philox4x32_10(make_uint4(uid, 0xFFFFFFFEu, e_lo, e_hi | 3u), k0, k1);
+    const double t[3] = {rand_offset(w2.x, p.trans_m[0]), rand_offset(w2.y, p.trans_m[1]),
+                         rand_offset(w2.z, p.trans_m[2])};
+    const double deg = 3.14159265358979323846 / 180.0;
+    const double ph = rand_offset(w2.w, p.euler_deg[0]) * deg;
+    const double th = rand_offset(w3.x, p.euler_deg[1]) * deg;
+    const double ps = rand_offset(w3.y, p.euler_deg[2]) * deg;
+    // translation in the camera's own frame
+    for (int r = 0; r < 3; ++r) b[9 + r] += b[3 * r] * t[0] + b[3 * r + 1] * t[1] + b[3 * r + 2] * t[2];
+    // R Rx(ph) Ry(th) Rz(ps)
+    const double cx = cos(ph), sx = sin(ph), cy = cos(th), sy = sin(th), cz = cos(ps), sz = sin(ps);
+    const double M[9] = {cy * cz, -cy * sz, sy,
+                         sx * sy * cz + cx * sz, -sx * sy * sz + cx * cz, -sx * cy,
+                         -cx * sy * cz + sx * sz, cx * sy * sz + sx * cz, cx * cy};
+    double R[9];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c)
+            R[3 * r + c] = b[3 * r] * M[c] + b[3 * r + 1] * M[3 + c] + b[3 * r + 2] * M[6 + c];
+    for (int k = 0; k < 9; ++k) b[k] = R[k];
+    if (p.dfov_deg != 0.0f) {  // both axes: f' = c / tan(atan(c / f) + dfov / 2)
+        const double half = 0.5 * rand_offset(w3.z, p.dfov_deg) * deg;
+        const double fx = 1.0 / b[12], fy = 1.0 / b[13];
+        b[12] = tan(atan(b[14] / fx) + half) / b[14];
+        b[13] = tan(atan(b[15] / fy) + half) / b[15];
+    }
+}
+
+// Ray bases of every camera of the launch (randomised when asked).
 __global__ void k_cam_prep(RenderLaunch a, int64_t n) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        double* b = a.cam_basis + kCamBasis * i;
+        uint32_t uid;
         if (a.desc) {
             const rc_cam_desc& D = a.desc[i];
-            cam_basis(D.pos, D.quat, D.intr, a.cam_basis + kCamBasis * i);
+            cam_basis(D.pos, D.quat, D.intr, b);
+            uid = D.cam_uid;
         } else {
-            cam_basis(a.cam_pos + 3 * i, a.cam_quat + 4 * i, a.intr + 4 * i,
-                      a.cam_basis + kCamBasis * i);
+            cam_basis(a.cam_pos + 3 * i, a.cam_quat + 4 * i, a.intr + 4 * i, b);
+            uid = (uint32_t)i;
         }
+        if (a.cam_rand_on) cam_randomize(a.cam_rand, uid, b);
     }
 }
 

@@ -97,6 +97,8 @@ struct RenderLaunch {
     uint4* exact_list;
     int64_t exact_cap;  // entries
     double* cam_basis;        // workspace: FP64 ray basis of every camera (16 doubles each)
+    rc_cam_rand cam_rand;     // perception randomisation of the cameras (if cam_rand_on)
+    int cam_rand_on;
     const rc_cam_desc* desc;  // batched form: camera descriptors (NULL: plain layout)
     int n_desc;
     int max_width, max_height;  // batched form: largest image a descriptor may have
@@ -148,6 +150,21 @@ hipError_t launch_post_batched(const PostLaunch& a, const rc_cam_desc* desc, int
                                hipStream_t s);
 
 void set_error(const std::string& msg);
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two 32x32
+// multiplications, with key increments 0x9E3779B9 and 0xBB67AE85.
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
+    for (int r = 0; r < 10; ++r) {
+        // one 32 x 32 -> 64-bit multiply gives both halves of each product
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c.x, p1 = (uint64_t)0xCD9E8D57u * c.z;
+        const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c;
+}
 
 // Serving-loop helpers (api.hip): workspace bytes of a batched render whose
 // exact-pass list is sized for cap_rays rays, and its enqueue.

@@ -47,6 +47,19 @@ class RcError(RuntimeError):
         self.status = status
 
 
+class CamRand(ctypes.Structure):
+    _fields_ = [("seed", ctypes.c_uint64), ("epoch", ctypes.c_uint64),
+                ("trans_m", ctypes.c_float * 3), ("euler_deg", ctypes.c_float * 3),
+                ("dfov_deg", ctypes.c_float), ("reserved", ctypes.c_float)]
+
+
+def cam_rand(seed=0, epoch=0, trans_m=(0.025, 0.025, 0.025), euler_deg=(2.5, 3.0, 2.5),
+             dfov_deg=2.0):
+    """Perception randomisation of the cameras (defaults: the paper's Table 6 ranges)."""
+    return CamRand(int(seed), int(epoch), (ctypes.c_float * 3)(*trans_m),
+                   (ctypes.c_float * 3)(*euler_deg), float(dfov_deg), 0.0)
+
+
 class RenderArgs(ctypes.Structure):
     _fields_ = [("n_env", ctypes.c_int32), ("n_cam", ctypes.c_int32),
                 ("width", ctypes.c_int32), ("height", ctypes.c_int32),
@@ -55,7 +68,7 @@ class RenderArgs(ctypes.Structure):
                 ("intr", ctypes.c_void_p), ("far_plane", ctypes.c_float),
                 ("depth_mode", ctypes.c_int32), ("depth", ctypes.c_void_p),
                 ("inst", ctypes.c_void_p), ("tri", ctypes.c_void_p),
-                ("timing", ctypes.c_void_p)]
+                ("timing", ctypes.c_void_p), ("cam_rand", ctypes.POINTER(CamRand))]
 
 
 class PostParams(ctypes.Structure):
@@ -73,7 +86,7 @@ class BatchArgs(ctypes.Structure):
                 ("max_width", ctypes.c_int32), ("max_height", ctypes.c_int32),
                 ("far_plane", ctypes.c_float), ("depth_mode", ctypes.c_int32),
                 ("depth", ctypes.c_void_p), ("inst", ctypes.c_void_p), ("tri", ctypes.c_void_p),
-                ("timing", ctypes.c_void_p)]
+                ("timing", ctypes.c_void_p), ("cam_rand", ctypes.POINTER(CamRand))]
 
 
 class RenderConfig(ctypes.Structure):
@@ -294,7 +307,7 @@ class Scene:
         return (c.value, r.value) if recast else c.value
 
     def _plain_args(self, cam_pos, cam_quat, intr, width, height, far_plane, link_pos, link_quat,
-                    depth_mode, out, ids, timing=None):
+                    depth_mode, out, ids, timing=None, rand=None):
         E, C = cam_pos.shape[0], cam_pos.shape[1]
         _dev_f32(cam_pos, (E, C, 3), "cam_pos")
         _dev_f32(cam_quat, (E, C, 4), "cam_quat")
@@ -312,18 +325,20 @@ class Scene:
         a = RenderArgs(E, C, width, height, _ptr(link_pos) if self.n_links else None,
                        _ptr(link_quat) if self.n_links else None, _ptr(cam_pos), _ptr(cam_quat),
                        _ptr(intr), float(far_plane), depth_mode, _ptr(depth), _ptr(inst), _ptr(tri),
-                       ctypes.cast(ev, ctypes.c_void_p) if ev is not None else None)
-        a._ev = ev  # keep the event array alive with the argument block
+                       ctypes.cast(ev, ctypes.c_void_p) if ev is not None else None,
+                       ctypes.pointer(rand) if rand is not None else None)
+        a._ev = ev  # keep the event array and randomisation alive with the argument block
+        a._rand = rand
         return a, (depth, inst, tri), self.render_workspace(E, C, width, height)
 
     def render(self, cam_pos, cam_quat, intr, width, height, far_plane, link_pos=None,
                link_quat=None, depth_mode=RC_DEPTH_PLANAR, out=None, ids=True, stream=None,
-               timing=None):
+               timing=None, rand=None):
         """Returns (depth [E,C,H,W] f32, inst i32 or None, tri i32 or None).
         timing: optional pair of recorded torch.cuda.Event(enable_timing=True) placed
-        around the fast-pass kernel."""
+        around the fast-pass kernel.  rand: optional cam_rand(...) randomisation."""
         a, outs, ws = self._plain_args(cam_pos, cam_quat, intr, width, height, far_plane, link_pos,
-                                       link_quat, depth_mode, out, ids, timing)
+                                       link_quat, depth_mode, out, ids, timing, rand)
         check(lib().rc_render(self.handle, ctypes.byref(a), ctypes.c_void_p(ws.ptr), ws.nbytes,
                               _stream(stream)))
         return outs
@@ -343,7 +358,7 @@ class Scene:
     # -- batched uneven form -------------------------------------------------
 
     def batch(self, desc, n_pixels, max_width, max_height, far_plane, link_pos=None,
-              link_quat=None, depth_mode=RC_DEPTH_PLANAR, out=None, ids=True):
+              link_quat=None, depth_mode=RC_DEPTH_PLANAR, out=None, ids=True, rand=None):
         """Argument block of a batched render.  desc: uint8 CUDA tensor holding
         n_desc rc_cam_desc records (see CAM_DESC)."""
         if desc.device.type != "cuda" or desc.dtype != torch.uint8 or desc.numel() % 64:
@@ -362,7 +377,8 @@ class Scene:
         a = BatchArgs(E, n_desc, _ptr(link_pos) if self.n_links else None,
                       _ptr(link_quat) if self.n_links else None, _ptr(desc), int(n_pixels),
                       int(max_width), int(max_height), float(far_plane), depth_mode, _ptr(depth),
-                      _ptr(inst), _ptr(tri), None)
+                      _ptr(inst), _ptr(tri), None, ctypes.pointer(rand) if rand is not None else None)
+        a._rand = rand
         key = ("batch", E, n_desc, int(n_pixels))
         ws = self._render_ws.get(key)
         if ws is None:

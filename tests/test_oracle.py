@@ -409,3 +409,49 @@ def test_downsample_brute_force_and_trailing_pixels():
                         if inst[i, yy, xx] >= 0]
                 want = sum(vals) / len(vals) if vals else 3.0
                 assert got[i, y, x] == pytest.approx(want, rel=1e-15, abs=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# perception randomisation of the cameras (the paper's Table 6)
+# ---------------------------------------------------------------------------
+
+def _cams(n, seed=3):
+    rng = np.random.default_rng(seed)
+    pos = rng.uniform(-5, 5, (n, 3))
+    quat = Rotation.random(n, random_state=seed).as_quat()
+    intr = np.tile([33.72, 43.30, 32.0, 24.0], (n, 1))
+    return pos, quat, intr
+
+
+def test_cam_randomize_zero_ranges_is_identity():
+    pos, quat, intr = _cams(50)
+    c = oracle.cam_randomize(pos, quat, intr, np.arange(50), 7, 0, [0, 0, 0], [0, 0, 0], 0.0)
+    R0 = Rotation.from_quat(quat).as_matrix()
+    assert np.allclose(c[:, :9].reshape(-1, 3, 3), R0, atol=1e-14)
+    assert np.array_equal(c[:, 9:12], pos)
+    assert np.array_equal(c[:, 12:], intr)
+
+
+def test_cam_randomize_offsets_within_ranges_and_uniform():
+    from scipy import stats
+    n = 4000
+    pos, quat, intr = _cams(n)
+    tr, eu, fov = [0.025, 0.025, 0.025], [2.5, 3.0, 2.5], 2.0
+    c = oracle.cam_randomize(pos, quat, intr, np.arange(n), 11, 5, tr, eu, fov)
+    R0 = Rotation.from_quat(quat).as_matrix()
+    # translation in the camera's own frame
+    t_local = np.einsum("nji,nj->ni", R0, c[:, 9:12] - pos)
+    assert np.all(np.abs(t_local) <= 0.025 + 1e-12)
+    # rotation: R0^T R = Rx(phi) Ry(theta) Rz(psi), an intrinsic x-y-z sequence
+    rel = np.einsum("nji,njk->nik", R0, c[:, :9].reshape(-1, 3, 3))
+    ang = Rotation.from_matrix(rel).as_euler("XYZ", degrees=True)
+    assert np.all(np.abs(ang) <= np.array(eu) + 1e-9)
+    # field of view: both axes widened or narrowed by the same offset
+    dh = np.degrees(2 * np.arctan(intr[:, 2] / c[:, 12]) - 2 * np.arctan(intr[:, 2] / intr[:, 0]))
+    dv = np.degrees(2 * np.arctan(intr[:, 3] / c[:, 13]) - 2 * np.arctan(intr[:, 3] / intr[:, 1]))
+    assert np.allclose(dh, dv, atol=1e-9) and np.all(np.abs(dh) <= fov + 1e-9)
+    for x, a in ((t_local[:, 0], 0.025), (ang[:, 1], 3.0), (dh, 2.0)):
+        assert stats.kstest(x, "uniform", args=(-a, 2 * a)).pvalue > 1e-3
+    # independent per camera uid and per epoch
+    c2 = oracle.cam_randomize(pos, quat, intr, np.arange(n), 11, 6, tr, eu, fov)
+    assert not np.allclose(c2[:, 9:12], c[:, 9:12])
