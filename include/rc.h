@@ -388,6 +388,16 @@ rc_status rc_server_destroy(rc_server* srv);
 #define RC_POST_NOISE 1u
 #define RC_POST_DROPOUT 2u
 #define RC_POST_LATENCY 4u
+/* Random side masking (Sec. 3.2, "Random Side Masking"): per environment and
+ * mask epoch a mode in {none, small, large} is drawn from the probabilities
+ * mask_p[type] of the environment's terrain type (word 0 of Philox with
+ * counter (env, 0xFFFFFFFD, epoch_lo32, (epoch_hi16 << 16) | 4), u =
+ * (w >> 8) 2^-24: none if u < p0, small if u < p0 + p1, else large).  A mode
+ * masks the columns x < m and x >= width - m of every camera image of the
+ * environment, m = round(mask_frac[mode - 1] * width); a masked pixel of
+ * the frame shown at step s becomes near + (far - near) u, u from word 3 of
+ * the pixel's own draw for step s, and its dropout mask is 0. */
+#define RC_POST_SIDEMASK 8u
 
 typedef struct {
     uint64_t seed;       /* Philox4x32-10 key (low word, high word) */
@@ -399,7 +409,11 @@ typedef struct {
     float fill;          /* value written for a dropped pixel */
     int32_t lat_min;     /* latency in frames, uniform in [lat_min, lat_max] */
     int32_t lat_max;
-    uint32_t flags;      /* RC_POST_NOISE | RC_POST_DROPOUT | RC_POST_LATENCY */
+    uint32_t flags;      /* RC_POST_NOISE | RC_POST_DROPOUT | RC_POST_LATENCY | RC_POST_SIDEMASK */
+    float mask_frac[2];  /* side band per image side, fraction of the width: small, large */
+    float mask_p[4][3];  /* per terrain type 0..3: P(none), P(small), P(large) */
+    uint64_t mask_epoch; /* draw index of the modes (e.g. the episode) */
+    const uint8_t* mask_type; /* device [n_env] terrain type per environment, or NULL (type 0) */
 } rc_post_params;
 
 /* Workspace bytes of a sensor-model state for frames [n_env][n_cam][height]

@@ -211,3 +211,45 @@ def cam_randomize(cam_pos, cam_quat, intr, cam_uid, seed, epoch, trans_m, euler_
         out[i, 9:12] = pos[i] + R0 @ t
         out[i, 12:] = (fx, fy, cx, cy)
     return out
+
+
+def side_mask(out, drop, seed, near, far, s0, mask_frac, mask_p, mask_epoch=0, mask_type=None,
+              cam_uid=None):
+    """Random side masking (the paper's RSM, Sec. 3.2) applied to the sensor
+    model's outputs out / drop [S,E,C,H,W] of steps s0.. (modified in place).
+
+    Per env e and mask epoch: u = (w0 >> 8) 2^-24 of Philox with counter
+    (e, 0xFFFFFFFD, epoch_lo32, (epoch_hi16 << 16) | 4); mode none if
+    u < p0, small if u < p0 + p1, else large (decided in FP32, with the FP32
+    sum p0 + p1); m = floor(frac * W + 0.5) in FP32.  Columns x < m and
+    x >= W - m of every camera of the env show near + (far - near) u3, u3 from
+    word 3 of the pixel's draw (pix, uid, s_lo32, s_hi16 << 16) at step s, and
+    their dropout mask is 0."""
+    S, E, C, H, W = out.shape
+    key = np.array([int(seed) & 0xFFFFFFFF, (int(seed) >> 32) & 0xFFFFFFFF], np.uint32)
+    e_lo, e_hi = int(mask_epoch) & 0xFFFFFFFF, (int(mask_epoch) >> 32) & 0xFFFF
+    f24 = np.float32(2.0 ** -24)
+    modes = np.zeros(E, np.int32)
+    for e in range(E):
+        typ = min(int(mask_type[e]), 3) if mask_type is not None else 0
+        w0 = philox(np.array([e, 0xFFFFFFFD, e_lo, (e_hi << 16) | 4], np.uint32), key)[0]
+        u = np.float32(int(w0) >> 8) * f24
+        p0, p1 = np.float32(mask_p[typ][0]), np.float32(mask_p[typ][1])
+        if u < p0:
+            continue
+        mode = 1 if u < np.float32(p0 + p1) else 2
+        modes[e] = mode
+        m = int(np.floor(np.float32(np.float32(mask_frac[mode - 1]) * np.float32(W)) + np.float32(0.5)))
+        cols = [x for x in range(W) if x < m or x >= W - m]
+        for i in range(S):
+            s = int(s0) + i
+            for c in range(C):
+                uid = int(cam_uid[e * C + c]) if cam_uid is not None else e * C + c
+                for y in range(H):
+                    for x in cols:
+                        w = philox(np.array([y * W + x, uid, s & 0xFFFFFFFF,
+                                             ((s >> 32) & 0xFFFF) << 16], np.uint32), key)
+                        u3 = float(int(w[3]) >> 8) * 2.0 ** -24
+                        out[i, e, c, y, x] = near + (far - near) * u3
+                        drop[i, e, c, y, x] = 0
+    return modes

@@ -776,8 +776,17 @@ static rc_status post_common(rc_post* post, const float* depth_in, const rc_post
         return fail(RC_ERR_INVALID_ARG, w + ": need finite near_plane <= far_plane");
     if (!std::isfinite(pp->sigma_abs) || !std::isfinite(pp->sigma_rel) || !std::isfinite(pp->fill))
         return fail(RC_ERR_INVALID_ARG, w + ": non-finite noise or fill parameter");
-    if (pp->flags & ~(RC_POST_NOISE | RC_POST_DROPOUT | RC_POST_LATENCY))
+    if (pp->flags & ~(RC_POST_NOISE | RC_POST_DROPOUT | RC_POST_LATENCY | RC_POST_SIDEMASK))
         return fail(RC_ERR_INVALID_ARG, w + ": unknown flag");
+    if (pp->flags & RC_POST_SIDEMASK) {
+        for (int m = 0; m < 2; ++m)
+            if (!(pp->mask_frac[m] >= 0.0f && pp->mask_frac[m] <= 0.5f))
+                return fail(RC_ERR_INVALID_ARG, w + ": mask_frac must be in [0, 0.5]");
+        for (int k = 0; k < 4; ++k)
+            for (int m = 0; m < 3; ++m)
+                if (!(pp->mask_p[k][m] >= 0.0f && pp->mask_p[k][m] <= 1.0f))
+                    return fail(RC_ERR_INVALID_ARG, w + ": mask_p entries must be in [0, 1]");
+    }
     if (pp->flags & RC_POST_LATENCY) {
         if (pp->lat_min < 0 || pp->lat_max < pp->lat_min)
             return fail(RC_ERR_INVALID_ARG, w + ": need 0 <= lat_min <= lat_max");
@@ -803,6 +812,11 @@ static rc_status post_common(rc_post* post, const float* depth_in, const rc_post
     L.near_plane = pp->near_plane; L.far_plane = pp->far_plane; L.fill = pp->fill;
     L.lat_min = pp->lat_min; L.lat_max = pp->lat_max;
     L.flags = pp->flags;
+    for (int m = 0; m < 2; ++m) L.mask_frac[m] = pp->mask_frac[m];
+    for (int k = 0; k < 4; ++k)
+        for (int m = 0; m < 3; ++m) L.mask_p[k][m] = pp->mask_p[k][m];
+    L.mask_epoch = pp->mask_epoch;
+    L.mask_type = pp->mask_type;
     return RC_OK;
 }
 

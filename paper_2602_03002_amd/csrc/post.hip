@@ -31,10 +31,26 @@ __device__ __forceinline__ int latency_draw(const PostLaunch& a, uint32_t uid) {
     return a.lat_min + (int)(((uint64_t)wl.x * span) >> 32);
 }
 
-// Sensor model of packed pixel p: pixel `pix` of its image, camera `uid`,
-// whose latency at this step is k frames.
+// Random side masking: columns masked on each side of the images of env
+// `env` (0 for mode none), drawn once per env and mask epoch.
+__device__ __forceinline__ int side_mask_cols(const PostLaunch& a, int env, int width) {
+    if (!(a.flags & RC_POST_SIDEMASK)) return 0;
+    const int type = a.mask_type ? min((int)a.mask_type[env], 3) : 0;
+    const uint32_t e_hi = (uint32_t)((a.mask_epoch >> 32) & 0xFFFFull) << 16;
+    const uint4 w = philox4x32_10(make_uint4((uint32_t)env, 0xFFFFFFFDu, (uint32_t)a.mask_epoch, e_hi | 4u),
+                                  (uint32_t)a.seed, (uint32_t)(a.seed >> 32));
+    const float u = (float)(w.x >> 8) * 5.9604644775390625e-08f;  // 2^-24
+    const float* pk = a.mask_p[type];
+    if (u < pk[0]) return 0;
+    const int mode = u < pk[0] + pk[1] ? 0 : 1;
+    return (int)floorf(__fmul_rn(a.mask_frac[mode], (float)width) + 0.5f);
+}
+
+// Sensor model of packed pixel p: pixel `pix` of its image (width `width`),
+// camera `uid`, whose latency at this step is k frames; mask_m side columns
+// of the image are masked.
 __device__ __forceinline__ void post_pixel(const PostLaunch& a, int64_t p, uint32_t pix, uint32_t uid,
-                                           int k) {
+                                           int k, int mask_m, int width) {
     const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
     const uint64_t s = a.step;
 
@@ -71,6 +87,14 @@ __device__ __forceinline__ void post_pixel(const PostLaunch& a, int64_t p, uint3
         out = a.ring[there];
         out_drop = a.ring_drop[there] != 0;
     }
+    if (mask_m > 0) {  // random side masking of the frame shown
+        const int x = (int)(pix % (uint32_t)width);
+        if (x < mask_m || x >= width - mask_m) {
+            const float u = (float)(wd.w >> 8) * 5.9604644775390625e-08f;
+            out = __fmaf_rn(a.far_plane - a.near_plane, u, a.near_plane);
+            out_drop = false;
+        }
+    }
     a.depth_out[p] = out;
     if (a.drop_out) a.drop_out[p] = out_drop ? 1 : 0;
 }
@@ -82,10 +106,11 @@ __global__ void __launch_bounds__(256) k_post(PostLaunch a) {
     const int64_t hw = (int64_t)a.height * a.width;
     const uint32_t uid = a.cam_uid ? a.cam_uid[ec] : (uint32_t)ec;
     const int k = latency_draw(a, uid);
+    const int mask_m = side_mask_cols(a, (int)(ec / a.n_cam), a.width);
     if (a.lat_out && blockIdx.y == 0 && threadIdx.x == 0) a.lat_out[ec] = (uint8_t)k;
     for (int64_t q = (int64_t)blockIdx.y * blockDim.x + threadIdx.x; q < hw;
          q += (int64_t)gridDim.y * blockDim.x)
-        post_pixel(a, ec * hw + q, (uint32_t)q, uid, k);
+        post_pixel(a, ec * hw + q, (uint32_t)q, uid, k, mask_m, a.width);
 }
 
 // Packed batch: block row x = camera descriptor, the blocks of a row stride
@@ -95,10 +120,11 @@ __global__ void __launch_bounds__(256) k_post_batched(PostLaunch a, const rc_cam
     const int64_t np = (int64_t)D.width * D.height;
     if (D.width < 1 || D.height < 1 || (int64_t)D.out_offset + np > a.n_pix) return;
     const int k = latency_draw(a, D.cam_uid);
+    const int mask_m = D.env >= 0 ? side_mask_cols(a, D.env, D.width) : 0;
     if (a.lat_out && blockIdx.y == 0 && threadIdx.x == 0) a.lat_out[blockIdx.x] = (uint8_t)k;
     for (int64_t q = (int64_t)blockIdx.y * blockDim.x + threadIdx.x; q < np;
          q += (int64_t)gridDim.y * blockDim.x)
-        post_pixel(a, (int64_t)D.out_offset + q, (uint32_t)q, D.cam_uid, k);
+        post_pixel(a, (int64_t)D.out_offset + q, (uint32_t)q, D.cam_uid, k, mask_m, D.width);
 }
 
 // Block pooling of rendered frames (the paper feeds its policy 240x135 depth

@@ -142,6 +142,10 @@ struct PostLaunch {
     float sigma_abs, sigma_rel, near_plane, far_plane, fill;
     int lat_min, lat_max;
     uint32_t flags;
+    float mask_frac[2];
+    float mask_p[4][3];
+    uint64_t mask_epoch;
+    const uint8_t* mask_type;
 };
 hipError_t launch_post(const PostLaunch& a, hipStream_t s);
 hipError_t launch_downsample(const float* depth, const int32_t* inst, int64_t n_img, int H, int W,

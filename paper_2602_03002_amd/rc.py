@@ -14,7 +14,13 @@ LIB_PATH = os.path.join(_HERE, "librc.so")
 
 RC_OK = 0
 RC_DEPTH_PLANAR, RC_DEPTH_RANGE = 0, 1
-RC_POST_NOISE, RC_POST_DROPOUT, RC_POST_LATENCY = 1, 2, 4
+RC_POST_NOISE, RC_POST_DROPOUT, RC_POST_LATENCY, RC_POST_SIDEMASK = 1, 2, 4, 8
+
+# Random side masking defaults (the paper gives neither the band widths nor the
+# probabilities): bands of 1/8 and 1/4 of the width per side; terrain type 0
+# (slopes, stairs) favours large masks, type 1 (stepping stones) small ones.
+SIDEMASK_FRAC = (0.125, 0.25)
+SIDEMASK_P = ((0.4, 0.2, 0.4), (0.4, 0.4, 0.2), (1.0, 0.0, 0.0), (1.0, 0.0, 0.0))
 
 EXPORTED = [
     "rc_version", "rc_status_string", "rc_last_error",
@@ -76,7 +82,9 @@ class PostParams(ctypes.Structure):
                 ("sigma_rel", ctypes.c_float), ("p_drop", ctypes.c_float),
                 ("near_plane", ctypes.c_float), ("far_plane", ctypes.c_float),
                 ("fill", ctypes.c_float), ("lat_min", ctypes.c_int32),
-                ("lat_max", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+                ("lat_max", ctypes.c_int32), ("flags", ctypes.c_uint32),
+                ("mask_frac", ctypes.c_float * 2), ("mask_p", (ctypes.c_float * 3) * 4),
+                ("mask_epoch", ctypes.c_uint64), ("mask_type", ctypes.c_void_p)]
 
 
 class BatchArgs(ctypes.Structure):
@@ -501,11 +509,19 @@ def downsample(depth, inst, factor, far_plane, out=None, stream=None):
 
 
 def post_params(seed=0, sigma_abs=0.0, sigma_rel=0.0, p_drop=0.0, near=0.05, far=3.0, fill=0.0,
-                lat_min=0, lat_max=0, flags=None):
+                lat_min=0, lat_max=0, flags=None, side_mask=False, mask_frac=SIDEMASK_FRAC,
+                mask_p=SIDEMASK_P, mask_epoch=0, mask_type=None):
+    """mask_type: optional uint8 CUDA tensor [n_env] of terrain types (0..3)."""
     if flags is None:
         flags = (RC_POST_NOISE if (sigma_abs or sigma_rel) else 0) | \
-                (RC_POST_DROPOUT if p_drop else 0) | (RC_POST_LATENCY if lat_max else 0)
-    return PostParams(seed, sigma_abs, sigma_rel, p_drop, near, far, fill, lat_min, lat_max, flags)
+                (RC_POST_DROPOUT if p_drop else 0) | (RC_POST_LATENCY if lat_max else 0) | \
+                (RC_POST_SIDEMASK if side_mask else 0)
+    p = PostParams(seed, sigma_abs, sigma_rel, p_drop, near, far, fill, lat_min, lat_max, flags,
+                   (ctypes.c_float * 2)(*mask_frac),
+                   ((ctypes.c_float * 3) * 4)(*[(ctypes.c_float * 3)(*row) for row in mask_p]),
+                   int(mask_epoch), _ptr(mask_type))
+    p._mask_type = mask_type  # keep the device table alive with the parameters
+    return p
 
 
 class Post:

@@ -455,3 +455,41 @@ def test_cam_randomize_offsets_within_ranges_and_uniform():
     # independent per camera uid and per epoch
     c2 = oracle.cam_randomize(pos, quat, intr, np.arange(n), 11, 6, tr, eu, fov)
     assert not np.allclose(c2[:, 9:12], c[:, 9:12])
+
+
+# ---------------------------------------------------------------------------
+# random side masking (Sec. 3.2)
+# ---------------------------------------------------------------------------
+
+def _masked(frac, p, E=200, W=16, types=None, epoch=0):
+    out = np.full((1, E, 1, 2, W), 1.5)
+    drop = np.ones(out.shape, np.uint8)
+    modes = oracle.side_mask(out, drop, 9, 0.05, 3.0, 0, frac, p, epoch, types)
+    return out, drop, modes
+
+
+def test_side_mask_certain_modes_and_bands():
+    for p, mode, m in (((1, 0, 0), 0, 0), ((0, 1, 0), 1, 2), ((0, 0, 1), 2, 4)):
+        out, drop, modes = _masked((0.125, 0.25), [p] * 4, E=5)
+        assert np.all(modes == mode)
+        band = np.zeros(16, bool)
+        band[:m] = True
+        band[16 - m:] = True
+        assert np.all(out[..., band] != 1.5) and np.all(out[..., ~band] == 1.5)
+        assert np.all(drop[..., band] == 0) and np.all(drop[..., ~band] == 1)
+
+
+def test_side_mask_mode_rates_fill_range_and_types():
+    from scipy import stats
+    out, drop, modes = _masked((0.125, 0.25), [(0.5, 0.2, 0.3)] * 4, E=3000)
+    for k, pk in enumerate((0.5, 0.2, 0.3)):
+        n = int(np.sum(modes == k))
+        assert stats.binomtest(n, 3000, pk).pvalue > 1e-4
+    vals = out[out != 1.5]
+    assert np.all((vals >= 0.05) & (vals < 3.0))
+    assert stats.kstest(vals, "uniform", args=(0.05, 2.95)).pvalue > 1e-3
+    # terrain type selects the probabilities
+    types = np.array([0, 1] * 50)
+    _, _, modes = _masked((0.125, 0.25), [(0, 1, 0), (0, 0, 1), (1, 0, 0), (1, 0, 0)], E=100,
+                          types=types)
+    assert np.all(modes[types == 0] == 1) and np.all(modes[types == 1] == 2)
