@@ -253,3 +253,19 @@ def side_mask(out, drop, seed, near, far, s0, mask_frac, mask_p, mask_epoch=0, m
                         out[i, e, c, y, x] = near + (far - near) * u3
                         drop[i, e, c, y, x] = 0
     return modes
+
+
+def heightmap(terrain, base_pos, base_yaw, nx=17, ny=11, dx=0.1, dy=0.1, top=1.0, depth=3.0,
+              miss=float("nan")):
+    """Brute-force FP64 privileged height map [E, ny, nx] (terrain z minus base
+    z under each grid point; see oracle_heightmap in oracle.c)."""
+    terrain = _f32(terrain).reshape(-1, 9)
+    base_pos = _f32(base_pos).reshape(-1, 3)
+    base_yaw = _f32(base_yaw).reshape(-1)
+    E = base_pos.shape[0]
+    out = np.empty((E, ny, nx), np.float64)
+    lib().oracle_heightmap(_p(terrain), ctypes.c_int64(terrain.shape[0]), _p(base_pos), _p(base_yaw),
+                           ctypes.c_int(E), ctypes.c_int(nx), ctypes.c_int(ny), ctypes.c_double(dx),
+                           ctypes.c_double(dy), ctypes.c_double(top), ctypes.c_double(depth),
+                           ctypes.c_double(miss), _p(out))
+    return out

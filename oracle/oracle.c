@@ -267,6 +267,38 @@ int oracle_render(const float* terrain, int64_t n_terrain,
     return 0;
 }
 
+/*
+ * oracle_heightmap: the privileged height map of the paper's terrain experts
+ * (Sec. 3.1: a local grid of 1.6 m x 1.0 m at 0.1 m around the robot).  For
+ * env e and grid point (i, j), i < nx along the heading, j < ny to the left:
+ * local (gx, gy) = ((i - (nx - 1) / 2) dx, (j - (ny - 1) / 2) dy), world
+ * (x, y) = base_xy + Rz(yaw) (gx, gy); a vertical ray from z = base_z + top
+ * down to depth; the closest terrain hit (closed triangles) gives
+ * heights[e][j][i] = (base_z + top - t) - base_z; no hit gives `miss`.  FP64.
+ */
+void oracle_heightmap(const float* terrain, int64_t n_terrain, const float* base_pos,
+                      const float* base_yaw, int E, int nx, int ny, double dx, double dy,
+                      double top, double depth, double miss, double* heights) {
+    #pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t q = 0; q < (int64_t)E * nx * ny; ++q) {
+        int e = (int)(q / ((int64_t)nx * ny));
+        int j = (int)((q / nx) % ny), i = (int)(q % nx);
+        double gx = (i - 0.5 * (nx - 1)) * dx, gy = (j - 0.5 * (ny - 1)) * dy;
+        double c = cos((double)base_yaw[e]), sn = sin((double)base_yaw[e]);
+        v3 o = {base_pos[3 * e] + c * gx - sn * gy, base_pos[3 * e + 1] + sn * gx + c * gy,
+                base_pos[3 * e + 2] + top};
+        v3 d = {0.0, 0.0, -1.0};
+        double best = INFINITY;
+        for (int64_t t = 0; t < n_terrain; ++t) {
+            double lam, mb;
+            if (tri_plane(o, d, terrain + 9 * t, &lam, &mb) && mb >= -CLOSED_EPS && lam > 0.0 &&
+                lam <= depth && lam < best)
+                best = lam;
+        }
+        heights[q] = best < INFINITY ? top - best : miss;
+    }
+}
+
 /* ------------------------------------------------------------------------
  * Counter-based generator: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).
  * Multipliers 0xD2511F53 and 0xCD9E8D57, key increments 0x9E3779B9 and

@@ -493,3 +493,49 @@ def test_side_mask_mode_rates_fill_range_and_types():
     _, _, modes = _masked((0.125, 0.25), [(0, 1, 0), (0, 0, 1), (1, 0, 0), (1, 0, 0)], E=100,
                           types=types)
     assert np.all(modes[types == 0] == 1) and np.all(modes[types == 1] == 2)
+
+
+# ---------------------------------------------------------------------------
+# privileged height map (Sec. 3.1)
+# ---------------------------------------------------------------------------
+
+def test_heightmap_against_analytic_terrain():
+    """Vertical rays against the meshed tile terrain equal the tiles' analytic
+    surface heights except next to a vertical step (riser or stone edge)."""
+    terr = sg.TileTerrain(2, seed=sg.MASTER_SEED)
+    tri = terr.triangles()
+    rng = np.random.default_rng(12)
+    E = 6
+    xy = np.stack([rng.uniform(-6, 6, E), rng.uniform(-6, 6, E)], 1)
+    base = np.concatenate([xy, [[terr.height(x, y) + 0.75] for x, y in xy]], 1)
+    yaw = rng.uniform(0, 2 * np.pi, E)
+    hm = oracle.heightmap(tri, base, yaw, 17, 11, 0.1, 0.1, 2.0, 5.0)
+    base32, yaw32 = base.astype(np.float32).astype(np.float64), yaw.astype(np.float32).astype(np.float64)
+    checked = 0
+    for e in range(E):
+        c, s = np.cos(yaw32[e]), np.sin(yaw32[e])
+        for j in range(11):
+            for i in range(17):
+                gx, gy = (i - 8) * 0.1, (j - 5) * 0.1
+                x, y = base32[e, 0] + c * gx - s * gy, base32[e, 1] + s * gx + c * gy
+                near = [terr.height(x + a, y + b) for a in (-1e-6, 0, 1e-6) for b in (-1e-6, 0, 1e-6)]
+                if max(near) - min(near) > 1e-6:
+                    continue  # a vertical step: either side is a valid answer
+                assert hm[e, j, i] == pytest.approx(near[4] - base32[e, 2], abs=2e-6)
+                checked += 1
+    assert checked > 0.8 * E * 17 * 11
+
+
+def test_heightmap_grid_geometry_and_miss():
+    """A single flat triangle: heights are z - base_z inside, `miss` outside,
+    and the grid is centred on the base and turned by the yaw."""
+    tri = np.array([[[-1.0, -1.0, 0.2], [3.0, -1.0, 0.2], [-1.0, 3.0, 0.2]]], np.float32)
+    hm = oracle.heightmap(tri, [[0.0, 0.0, 1.0]], [np.pi / 2], 17, 11, 0.1, 0.1, 1.0, 3.0, miss=-9.0)
+    assert hm.shape == (1, 11, 17)
+    assert hm[0, 5, 8] == pytest.approx(-0.8, abs=1e-7)
+    # yaw 90 degrees: the heading is +y, so grid x maps to world y
+    # world point of (i, j) = (-(j - 5) 0.1, (i - 8) 0.1); inside the triangle iff x + y <= 2
+    inside = np.array([[(-(j - 5) * 0.1) + ((i - 8) * 0.1) <= 2 and (-(j - 5) * 0.1) >= -1
+                        and ((i - 8) * 0.1) >= -1 for i in range(17)] for j in range(11)])
+    assert np.all(hm[0][inside] == pytest.approx(-0.8, abs=1e-7))
+    assert np.all(hm[0][~inside] == -9.0)
