@@ -318,6 +318,47 @@ def bench_table1(sc, w_main, frames=20, warmup=3):
             "runs": out}
 
 
+def bench_heightmap(sc, w_main, reps=50, warmup=5):
+    """The privileged height map (Sec. 3.1): 17 x 11 vertical rays at 0.1 m
+    around each base on the same terrain, at the 4096 bases of the scene and
+    at 65,536 bases spread over the terrain (one launch each)."""
+    import numpy as np
+    import torch
+    import scenegen as sg
+    print("[bench] height map", file=sys.stderr, flush=True)
+    lp = w_main["link_pos"][0, :, 0]
+    q = w_main["link_quat"][0, :, 0]
+    yaw = 2.0 * np.arctan2(q[:, 2], q[:, 3])  # the base link turns about +z only
+    terr = w_main["terrain_obj"]
+    rng = sg.substream("bench/heightmap")
+    half = terr.n * 4.0 - 1.0
+    xy = rng.uniform(-half, half, (65536, 2))
+    big = np.concatenate([xy, [[terr.height(x, y) + 0.75] for x, y in xy]], 1)
+    out = []
+    for base, yw in ((lp, yaw), (big, rng.uniform(0, 2 * np.pi, 65536))):
+        b = torch.from_numpy(np.ascontiguousarray(base, np.float32)).cuda()
+        y = torch.from_numpy(np.ascontiguousarray(yw, np.float32)).cuda()
+        hm = torch.empty((b.shape[0], 11, 17), dtype=torch.float32, device="cuda")
+        for _ in range(warmup):
+            sc.heightmap(b, y, out=hm)
+        a, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record()
+        for _ in range(reps):
+            sc.heightmap(b, y, out=hm)
+        e.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(e) / reps
+        pts = b.shape[0] * 187
+        r = {"bases": b.shape[0], "points": pts, "us_per_launch": round(ms * 1e3, 2),
+             "mpoints_s": round(pts / (ms / 1e3) / 1e6, 1),
+             "nan_points": int(torch.isnan(hm).sum().item())}
+        out.append(r)
+        print(f"[bench] height map {r}", file=sys.stderr, flush=True)
+    return {"workload": "17x11 grid at 0.1 m per base, rays from base z + 1 m down 3 m, "
+                        "20x20-tile terrain", "runs": out}
+
+
 def bench_serving(sc, w_main, capacity_mrays, duration_s=6.0, stream_s=60.0):
     """Poisson request stream over the resident scene: requests of 16-1024 envs
     (log-uniform), 1-4 cameras and sizes from 32x24..106x60; p50/p99 latency
@@ -430,6 +471,7 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the serving section")
     ap.add_argument("--no-table1", action="store_true",
                     help="skip the section on the paper's 240x135 perception setting")
+    ap.add_argument("--no-heightmap", action="store_true", help="skip the height-map section")
     ap.add_argument("--serve-seconds", type=float, default=6.0,
                     help="length of the 50%% and 80%%-of-capacity serving runs")
     ap.add_argument("--serve-stream-seconds", type=float, default=60.0,
@@ -556,6 +598,7 @@ def main():
     serving = None if args.no_serving else bench_serving(sc, w, value, args.serve_seconds,
                                                          args.serve_stream_seconds)
     table1 = None if args.no_table1 else bench_table1(sc, w)
+    heightmap = None if args.no_heightmap else bench_heightmap(sc, w)
     cpu = None if args.no_cpu_baseline else cpu_baseline(w)
     out = {
         "metric": "depth Mrays/s at 4096 envs x 2 cams 64x48 vs plain; p50/p99 request latency",
@@ -573,7 +616,7 @@ def main():
                    "compulsory_frac": round(compulsory_frac, 4),
                    "exact_pass_rays_last_step": exact_rays, "schedule": tuned},
         "roofline": roof, "cpu_baseline": cpu, "traversal": trav, "batched": batched,
-        "serving": serving, "table1": table1,
+        "serving": serving, "table1": table1, "heightmap": heightmap,
     }
     print(json.dumps(out), flush=True)
 

@@ -469,6 +469,32 @@ rc_status rc_postprocess_batched(rc_post* post, const float* depth_in, const int
 /* Release the handle (not the workspace). NULL is a no-op. */
 rc_status rc_post_destroy(rc_post* post);
 
+/* ---------------------------------------------------------------------
+ * Privileged height map (the terrain experts' local grid, Sec. 3.1).
+ * ------------------------------------------------------------------- */
+
+typedef struct {
+    int32_t n_env;
+    const float* base_pos; /* device [n_env][3]: robot base (world, m) */
+    const float* base_yaw; /* device [n_env]: heading about +z (rad) */
+    int32_t nx, ny;        /* grid points along the heading and to the left (17 x 11 in the paper) */
+    float dx, dy;          /* spacing (m; 0.1 in the paper) */
+    float top;             /* rays start at base z + top (m) */
+    float depth;           /* and reach down `depth` (m) */
+    float miss;            /* value of a point with no terrain below */
+    float* heights;        /* device out [n_env][ny][nx]: terrain z - base z (m) */
+} rc_heightmap_args;
+
+/* Height map of the terrain around each robot base: grid point (i, j) sits at
+ * local ((i - (nx - 1) / 2) dx, (j - (ny - 1) / 2) dy), turned by the yaw
+ * and placed at the base; a vertical ray from base z + top finds the highest
+ * terrain surface below within `depth` (closed triangles, FP64 decisions, so a
+ * point on a shared edge finds its surface).  Links are not seen.  Errors:
+ * INVALID_ARG (NULL pointers, n_env < 1, nx or ny outside [1, 4096], dx or dy
+ * not finite and > 0, depth not finite and > 0, top not finite), STATE (no
+ * terrain), DEVICE.  Asynchronous on `stream`. */
+rc_status rc_heightmap(const rc_scene* scene, const rc_heightmap_args* args, rc_stream stream);
+
 /* Downsample rendered frames by block pooling (the paper feeds its policy
  * 240x135 depth downsampled to 48x27, Sec. 4.1; the pooling rule is not
  * stated): output pixel (y, x) of image i is the mean depth of the hit pixels

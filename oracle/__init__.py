@@ -262,6 +262,8 @@ def heightmap(terrain, base_pos, base_yaw, nx=17, ny=11, dx=0.1, dy=0.1, top=1.0
     terrain = _f32(terrain).reshape(-1, 9)
     base_pos = _f32(base_pos).reshape(-1, 3)
     base_yaw = _f32(base_yaw).reshape(-1)
+    # the grid parameters are FP32 numbers, as every input of the method is
+    dx, dy, top, depth = (float(np.float32(v)) for v in (dx, dy, top, depth))
     E = base_pos.shape[0]
     out = np.empty((E, ny, nx), np.float64)
     lib().oracle_heightmap(_p(terrain), ctypes.c_int64(terrain.shape[0]), _p(base_pos), _p(base_yaw),

@@ -896,6 +896,29 @@ rc_status rc_postprocess_batched(rc_post* post, const float* depth_in, const int
     return RC_OK;
 }
 
+rc_status rc_heightmap(const rc_scene* scene, const rc_heightmap_args* a, rc_stream stream) {
+    if (!scene || !a || !a->base_pos || !a->base_yaw || !a->heights)
+        return fail(RC_ERR_INVALID_ARG, "rc_heightmap: NULL pointer");
+    if (!scene->ws) return fail(RC_ERR_STATE, "rc_heightmap: scene has no terrain");
+    if (a->n_env < 1 || a->nx < 1 || a->ny < 1 || a->nx > 4096 || a->ny > 4096)
+        return fail(RC_ERR_INVALID_ARG, "rc_heightmap: need n_env >= 1 and 1 <= nx, ny <= 4096");
+    if (!(a->dx > 0.0f) || !(a->dy > 0.0f) || !std::isfinite(a->dx) || !std::isfinite(a->dy) ||
+        !(a->depth > 0.0f) || !std::isfinite(a->depth) || !std::isfinite(a->top))
+        return fail(RC_ERR_INVALID_ARG, "rc_heightmap: dx, dy, depth must be finite and > 0, top finite");
+    HeightLaunch hl;
+    hl.nodes = (const Node*)(scene->ws + scene->terrain.nodes);
+    hl.tris = (const float*)(scene->ws + scene->terrain.tris);
+    hl.n_prim = (int)scene->terrain.n_prim;
+    hl.base_pos = a->base_pos;
+    hl.base_yaw = a->base_yaw;
+    hl.n_env = a->n_env; hl.nx = a->nx; hl.ny = a->ny;
+    hl.dx = a->dx; hl.dy = a->dy; hl.top = a->top; hl.depth = a->depth; hl.miss = a->miss;
+    hl.heights = a->heights;
+    hipError_t e = launch_heightmap(hl, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "rc_heightmap: launch");
+    return RC_OK;
+}
+
 rc_status rc_downsample(const float* depth_in, const int32_t* inst_in, int64_t n_img, int32_t height,
                         int32_t width, int32_t factor, float far_plane, float* depth_out,
                         rc_stream stream) {

@@ -121,6 +121,15 @@ __device__ __forceinline__ bool slab(float lx, float hx, float ly, float hy, flo
     return a <= b;
 }
 
+// Box test of a ray going straight down from (r.oix, r.oiy, r.oiz) (the
+// vertical rays of the height map): containment in x and y, then the z range
+// over [0, tmax].  Exact in FP32 against the padded boxes.
+__device__ __forceinline__ bool vslab(float lx, float hx, float ly, float hy, float lz, float hz,
+                                      const Slab& r, float tmax, float& tn) {
+    tn = fmaxf(r.oiz - hz, 0.0f);
+    return (lx <= r.oix) & (r.oix <= hx) & (ly <= r.oiy) & (r.oiy <= hy) & (tn <= fminf(r.oiz - lz, tmax));
+}
+
 __device__ __forceinline__ int slab_octant(const Slab& r) {
     return (r.ix < 0.0f ? 1 : 0) | (r.iy < 0.0f ? 2 : 0) | (r.iz < 0.0f ? 4 : 0);
 }
@@ -353,7 +362,7 @@ __device__ __forceinline__ void tri_test(const float* __restrict__ v,
 constexpr int kStack = 12;
 constexpr int kLanes = 64 * kWavesPerBlock;
 
-template <int OCT = -1, typename Cnt, typename Leaf>
+template <int OCT = -1, bool VERT = false, typename Cnt, typename Leaf>
 __device__ __forceinline__ void traverse(const Node* __restrict__ nodes, int n_nodes, int n_prim,
                                          const Slab& r, Hit& h, Cnt& cnt, Leaf&& leaf,
                                          int start = 0, uint32_t* stk = nullptr) {
@@ -368,8 +377,10 @@ __device__ __forceinline__ void traverse(const Node* __restrict__ nodes, int n_n
         const int4 q3 = reinterpret_cast<const int4*>(np)[3];
         cnt.node();
         float tn0, tn1;
-        bool h0 = slab<OCT>(q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, r, h.tmax, tn0);
-        bool h1 = slab<OCT>(q1.z, q1.w, q2.x, q2.y, q2.z, q2.w, r, h.tmax, tn1);
+        bool h0 = VERT ? vslab(q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, r, h.tmax, tn0)
+                       : slab<OCT>(q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, r, h.tmax, tn0);
+        bool h1 = VERT ? vslab(q1.z, q1.w, q2.x, q2.y, q2.z, q2.w, r, h.tmax, tn1)
+                       : slab<OCT>(q1.z, q1.w, q2.x, q2.y, q2.z, q2.w, r, h.tmax, tn1);
         const int c0 = q3.x, c1 = q3.y;
         // non-short-circuit forms: mask arithmetic instead of branches
         h0 = h0 & ((c0 >= 0) | ((unsigned)~c0 < (unsigned)n_prim));
@@ -1120,7 +1131,58 @@ __global__ void __launch_bounds__(64) k_render_exact(RenderLaunch a, const uint3
     }
 }
 
+// Privileged height map (the terrain experts' local grid, Sec. 3.1): one
+// vertical ray per grid point, from base_z + top down to `depth`, against the
+// terrain hierarchy; every triangle test is the FP64 watertight test (closed
+// triangles), so a point on a shared edge or vertex finds its surface.
+__global__ void __launch_bounds__(kLanes) k_heightmap(HeightLaunch hl) {
+    __shared__ uint32_t s_stack[kLanes * kStack];
+    const int64_t n = (int64_t)hl.n_env * hl.nx * hl.ny;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += stride) {
+        const int e = (int)(q / ((int64_t)hl.nx * hl.ny));
+        const int j = (int)((q / hl.nx) % hl.ny), i = (int)(q % hl.nx);
+        const double gx = (i - 0.5 * (hl.nx - 1)) * (double)hl.dx;
+        const double gy = (j - 0.5 * (hl.ny - 1)) * (double)hl.dy;
+        const double c = cos((double)hl.base_yaw[e]), s = sin((double)hl.base_yaw[e]);
+        const double o64[3] = {(double)hl.base_pos[3 * e] + c * gx - s * gy,
+                               (double)hl.base_pos[3 * e + 1] + s * gx + c * gy,
+                               (double)hl.base_pos[3 * e + 2] + (double)hl.top};
+        const double d64[3] = {0.0, 0.0, -1.0};
+        Slab r;  // vertical form: the FP32 origin only
+        r.ix = r.iy = r.iz = 0.0f;
+        r.oix = (float)o64[0];
+        r.oiy = (float)o64[1];
+        r.oiz = (float)o64[2];
+        Hit h;
+        h.tmax = hl.depth;
+        h.key = ~0ull;
+        h.tu = INFINITY;
+        double best = INFINITY;
+        NoCount none;
+        traverse<-1, true>(hl.nodes, hl.n_prim > 1 ? hl.n_prim - 1 : 1, hl.n_prim, r, h, none,
+                           [&](int leaf) {
+                               const float* v = hl.tris + 9 * (int64_t)leaf;
+                               double t;
+                               if (tri_test64(v, o64, d64, t) &&
+                                   t <= (double)hl.depth && t < best) {
+                                   best = t;
+                                   // the FP32 bound must not cut below the FP64 hit
+                                   h.tmax = nextafterf((float)t, INFINITY);
+                               }
+                           }, 0, s_stack + threadIdx.x);
+        hl.heights[q] = best < INFINITY ? (float)((double)hl.top - best) : hl.miss;
+    }
+}
+
 }  // namespace
+
+hipError_t launch_heightmap(const HeightLaunch& hl, hipStream_t s) {
+    const int64_t n = (int64_t)hl.n_env * hl.nx * hl.ny;
+    const unsigned blocks = (unsigned)std::min<int64_t>((n + kLanes - 1) / kLanes, 65535);
+    hipLaunchKernelGGL(k_heightmap, dim3(blocks), dim3(kLanes), 0, s, hl);
+    return hipGetLastError();
+}
 
 // Kernel variant index: 100 * mode + 10 * waves + tiles per wavefront.
 #define RC_MODE_VARIANTS(X, M) X(6, 1, M) X(6, 2, M) X(7, 1, M) X(7, 2, M) X(8, 1, M) X(8, 2, M)

@@ -119,6 +119,18 @@ struct RenderCfg {
     int bodies_flat = 1;         // links found by the top-level walk (0) or by cone culling (1)
 };
 bool render_cfg_ok(const RenderCfg& c);
+
+struct HeightLaunch {
+    const Node* nodes;
+    const float* tris;
+    int n_prim;
+    const float* base_pos;  // [n_env][3]
+    const float* base_yaw;  // [n_env]
+    int n_env, nx, ny;
+    float dx, dy, top, depth, miss;
+    float* heights;  // [n_env][ny][nx]
+};
+hipError_t launch_heightmap(const HeightLaunch& hl, hipStream_t s);
 hipError_t launch_render(const RenderLaunch& a, const RenderCfg& cfg, hipStream_t s);
 hipError_t launch_render_batched(const RenderLaunch& a, const RenderCfg& cfg, uint32_t* tile_start,
                                  uint32_t* queues, uint32_t* status, int persistent_blocks,

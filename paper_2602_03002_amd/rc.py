@@ -28,7 +28,7 @@ EXPORTED = [
     "rc_robot_size", "rc_robot_meshes",
     "rc_render_size", "rc_render", "rc_render_exact_count", "rc_render_counts",
     "rc_post_size", "rc_post_create", "rc_post_reset", "rc_postprocess", "rc_post_destroy",
-    "rc_downsample",
+    "rc_downsample", "rc_heightmap",
     "rc_bvh_layout_of",
     "rc_render_batched_size", "rc_render_batched", "rc_render_batched_status",
     "rc_get_render_config", "rc_set_render_config", "rc_autotune",
@@ -75,6 +75,13 @@ class RenderArgs(ctypes.Structure):
                 ("depth_mode", ctypes.c_int32), ("depth", ctypes.c_void_p),
                 ("inst", ctypes.c_void_p), ("tri", ctypes.c_void_p),
                 ("timing", ctypes.c_void_p), ("cam_rand", ctypes.POINTER(CamRand))]
+
+
+class HeightmapArgs(ctypes.Structure):
+    _fields_ = [("n_env", ctypes.c_int32), ("base_pos", ctypes.c_void_p),
+                ("base_yaw", ctypes.c_void_p), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("dx", ctypes.c_float), ("dy", ctypes.c_float), ("top", ctypes.c_float),
+                ("depth", ctypes.c_float), ("miss", ctypes.c_float), ("heights", ctypes.c_void_p)]
 
 
 class PostParams(ctypes.Structure):
@@ -170,6 +177,7 @@ def lib():
         L.rc_post_create.argtypes = [i32, i32, i32, i32, i32, vp, sz, ctypes.POINTER(vp)]
         L.rc_post_reset.argtypes = [vp]
         L.rc_downsample.argtypes = [vp, vp, i64, i32, i32, i32, ctypes.c_float, vp, vp]
+        L.rc_heightmap.argtypes = [vp, ctypes.POINTER(HeightmapArgs), vp]
         L.rc_postprocess.argtypes = [vp, vp, vp, ctypes.POINTER(PostParams), ctypes.c_uint64, vp,
                                      vp, vp, vp, vp]
         L.rc_post_destroy.argtypes = [vp]
@@ -362,6 +370,20 @@ class Scene:
         check(lib().rc_render_counts(self.handle, ctypes.byref(a), _ptr(counts),
                                      ctypes.c_void_p(ws.ptr), ws.nbytes, _stream(stream)))
         return outs, counts
+
+    def heightmap(self, base_pos, base_yaw, nx=17, ny=11, dx=0.1, dy=0.1, top=1.0, depth=3.0,
+                  miss=float("nan"), out=None, stream=None):
+        """Terrain height minus base height on a local grid [E, ny, nx] around
+        each base (the paper's privileged height map: 17 x 11 at 0.1 m)."""
+        E = base_pos.shape[0]
+        _dev_f32(base_pos, (E, 3), "base_pos")
+        _dev_f32(base_yaw, (E,), "base_yaw")
+        if out is None:
+            out = torch.empty((E, ny, nx), dtype=torch.float32, device=self.device)
+        a = HeightmapArgs(E, _ptr(base_pos), _ptr(base_yaw), nx, ny, dx, dy, top, depth, miss,
+                          _ptr(out))
+        check(lib().rc_heightmap(self.handle, ctypes.byref(a), _stream(stream)))
+        return out
 
     # -- batched uneven form -------------------------------------------------
 
