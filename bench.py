@@ -318,6 +318,67 @@ def bench_table1(sc, w_main, frames=20, warmup=3):
             "runs": out}
 
 
+def bench_randomised(sc, w, step_plain_ms, steps=50, warmup=5):
+    """The main step with the perception randomisation the paper trains with:
+    cameras drawn per launch from the Table 6 ranges (translation, Euler
+    angles, field of view) and random side masking in the sensor model, the
+    mode probabilities chosen by each environment's terrain type."""
+    import numpy as np
+    import torch
+    import scenegen as sg
+    import paper_2602_03002_amd as rc
+    print("[bench] randomised step", file=sys.stderr, flush=True)
+    E, C, H, W = w["E"], w["C"], w["H"], w["W"]
+    terr = w["terrain_obj"]
+    xy = w["link_pos"][0, :, 0, :2]
+    kinds = []
+    for x, y in xy:  # 1 on stepping stones, 0 on slopes and stairs
+        kinds.append(1 if isinstance(terr.tile_at(x, y), sg.StonesTile) else 0)
+    mask_type = torch.tensor(kinds, dtype=torch.uint8, device="cuda")
+
+    def t(a):
+        return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+    lp, lq = t(w["link_pos"][:2]), t(w["link_quat"][:2])
+    cp, cq, K = t(w["cam_pos"]), t(w["cam_quat"]), t(w["intr"])
+    sens = w["sensor"]
+    post = rc.Post(E, C, H, W, sens["lat_max"])
+    p = rc.post_params(seed=0x2602_03002, sigma_abs=sens["sigma_abs"], sigma_rel=sens["sigma_rel"],
+                       p_drop=sens["p_drop"], near=sens["near"], far=sens["far"], fill=sens["fill"],
+                       lat_min=sens["lat_min"], lat_max=sens["lat_max"], side_mask=True,
+                       mask_type=mask_type)
+    depth = torch.empty((E, C, H, W), dtype=torch.float32, device="cuda")
+    inst = torch.empty_like(depth, dtype=torch.int32)
+    tri = torch.empty_like(depth, dtype=torch.int32)
+    pout, drop = torch.empty_like(depth), torch.empty_like(depth, dtype=torch.uint8)
+    lat = torch.empty((E, C), dtype=torch.uint8, device="cuda")
+
+    def step(k):
+        sc.render(cp, cq, K, W, H, w["far"], link_pos=lp[k % 2], link_quat=lq[k % 2],
+                  out=(depth, inst, tri), rand=rc.cam_rand(seed=0x2602, epoch=k // 20))
+        post.process(depth, inst, p, k, out=(pout, drop, lat))
+
+    for k in range(warmup):
+        step(k)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record()
+    for k in range(steps):
+        step(warmup + k)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / steps
+    rays = E * C * H * W
+    r = {"workload": "the main step with Table 6 camera randomisation (per launch, Philox) and "
+                     "random side masking (mode per env by terrain type)",
+         "ms_per_step": round(ms, 4), "mrays_s": round(rays / (ms / 1e3) / 1e6, 1),
+         "plain_ms_per_step": round(step_plain_ms, 4),
+         "overhead": round(ms / step_plain_ms - 1.0, 4),
+         "envs_on_stones": int(sum(kinds))}
+    print(f"[bench] randomised {r}", file=sys.stderr, flush=True)
+    return r
+
+
 def bench_heightmap(sc, w_main, reps=50, warmup=5):
     """The privileged height map (Sec. 3.1): 17 x 11 vertical rays at 0.1 m
     around each base on the same terrain, at the 4096 bases of the scene and
@@ -472,6 +533,8 @@ def main():
     ap.add_argument("--no-table1", action="store_true",
                     help="skip the section on the paper's 240x135 perception setting")
     ap.add_argument("--no-heightmap", action="store_true", help="skip the height-map section")
+    ap.add_argument("--no-randomised", action="store_true",
+                    help="skip the section with camera randomisation and side masking")
     ap.add_argument("--serve-seconds", type=float, default=6.0,
                     help="length of the 50%% and 80%%-of-capacity serving runs")
     ap.add_argument("--serve-stream-seconds", type=float, default=60.0,
@@ -598,6 +661,7 @@ def main():
     serving = None if args.no_serving else bench_serving(sc, w, value, args.serve_seconds,
                                                          args.serve_stream_seconds)
     table1 = None if args.no_table1 else bench_table1(sc, w)
+    randomised = None if args.no_randomised else bench_randomised(sc, w, ms_per_step)
     heightmap = None if args.no_heightmap else bench_heightmap(sc, w)
     cpu = None if args.no_cpu_baseline else cpu_baseline(w)
     out = {
@@ -616,7 +680,7 @@ def main():
                    "compulsory_frac": round(compulsory_frac, 4),
                    "exact_pass_rays_last_step": exact_rays, "schedule": tuned},
         "roofline": roof, "cpu_baseline": cpu, "traversal": trav, "batched": batched,
-        "serving": serving, "table1": table1, "heightmap": heightmap,
+        "serving": serving, "table1": table1, "randomised": randomised, "heightmap": heightmap,
     }
     print(json.dumps(out), flush=True)
 

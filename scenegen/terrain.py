@@ -339,9 +339,17 @@ class TileTerrain:
     def centre(self, i, j):
         return (-self.n * HALF + TILE * i + HALF, -self.n * HALF + TILE * j + HALF)
 
-    def height(self, x, y):
+    def tile_index(self, x, y):
         i = min(self.n - 1, max(0, int(math.floor((x + self.n * HALF) / TILE))))
         j = min(self.n - 1, max(0, int(math.floor((y + self.n * HALF) / TILE))))
+        return i, j
+
+    def tile_at(self, x, y):
+        i, j = self.tile_index(x, y)
+        return self.tiles[i * self.n + j]
+
+    def height(self, x, y):
+        i, j = self.tile_index(x, y)
         cx, cy = self.centre(i, j)
         return self.tiles[i * self.n + j].height(x - cx, y - cy)
 
