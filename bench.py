@@ -462,10 +462,14 @@ def bench_serving(sc, w_main, capacity_mrays, duration_s=6.0, stream_s=60.0):
         arrivals = np.cumsum(rng.exponential(1.0 / rate, int(rate * seconds * 1.5) + 16))
         arrivals = arrivals[arrivals < seconds]
         i = 0
+        done = 0
+        waits, runs_ = [], []
         submitted_rays = 0
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         deadline = seconds + 30.0
+        # the loop only submits, polls and collects: the statistics (a sort of
+        # every latency so far) are read once at the end
         while True:
             now = time.perf_counter() - t0
             while i < len(arrivals) and arrivals[i] <= now:
@@ -480,8 +484,10 @@ def bench_serving(sc, w_main, capacity_mrays, duration_s=6.0, stream_s=60.0):
                 if r is None:
                     break
                 srv.release(r["id"])
-            st = srv.stats()
-            if (i >= len(arrivals) and st["completed"] + st["rejected"] >= len(arrivals)) or now > deadline:
+                waits.append(r["launch_s"] - r["arrival_s"])
+                runs_.append(r["done_s"] - r["launch_s"])
+                done += 1
+            if (i >= len(arrivals) and done >= len(arrivals)) or now > deadline:
                 break
         st = srv.stats()
         srv.close()
@@ -493,7 +499,11 @@ def bench_serving(sc, w_main, capacity_mrays, duration_s=6.0, stream_s=60.0):
                 "served_mrays_s": round(st["rays_completed"] / span / 1e6, 1),
                 "p50_ms": round(st["p50_s"] * 1e3, 3), "p99_ms": round(st["p99_s"] * 1e3, 3),
                 "mean_ms": round(st["mean_s"] * 1e3, 3), "streams": n_streams,
-                "max_batch_rays": max_batch_rays}
+                "max_batch_rays": max_batch_rays,
+                "queue_p50_p99_ms": [round(float(np.percentile(waits, q)) * 1e3, 3) for q in (50, 99)]
+                if waits else None,
+                "batch_p50_p99_ms": [round(float(np.percentile(runs_, q)) * 1e3, 3) for q in (50, 99)]
+                if runs_ else None}
 
     cap_rps = capacity_mrays * 1e6 / mean_rays
     runs = []
@@ -511,7 +521,9 @@ def bench_serving(sc, w_main, capacity_mrays, duration_s=6.0, stream_s=60.0):
     print(f"[bench] serving {base}", file=sys.stderr, flush=True)
     return {"mean_rays_per_request": round(mean_rays), "runs": runs, "plain_per_request": base,
             "speedup_served_vs_plain_per_request": round(lit["served_mrays_s"] /
-                                                         max(base["served_mrays_s"], 1e-9), 3)}
+                                                         max(base["served_mrays_s"], 1e-9), 3),
+            "p50_plain_over_served": round(base["p50_ms"] / max(lit["p50_ms"], 1e-9), 2),
+            "p99_plain_over_served": round(base["p99_ms"] / max(lit["p99_ms"], 1e-9), 2)}
 
 
 def main():
