@@ -376,6 +376,10 @@ rc_status rc_server_next_result(rc_server* srv, rc_result* out);
 /* Return a taken result's output memory to the arena. */
 rc_status rc_server_release(rc_server* srv, int64_t id);
 
+/* Counters and latency statistics (nearest-rank p50 / p99, mean, max over
+ * every completed request).  Sorts a copy of all latencies: O(n log n) in
+ * the requests completed so far, so a serving loop reads it rarely (not on
+ * every poll). */
 rc_status rc_server_stats_get(const rc_server* srv, rc_server_stats* out);
 
 /* Wait for all batches in flight (GPU servers), then free the handle. */
