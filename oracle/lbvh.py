@@ -7,6 +7,10 @@ a stable sort of (code, index), the Karras (2012) hierarchy with duplicate
 codes broken by leaf index, boxes as unions of children, then an outward
 padding of every child box.  All floating-point steps are single FP32
 operations in the stated order, so the results are exact replicas.
+
+A triangle of zero area (edge vectors with an all-zero FP64 cross product)
+is met by no ray: it keeps its Morton code, but its leaf box is empty for
+the unions, and an empty child box is stored as the far point.
 """
 import numpy as np
 
@@ -113,9 +117,19 @@ def karras(keys):
 
 
 def _pad(lo, hi):
+    if np.any(lo > hi):  # empty: only zero-area triangles below
+        far = np.full(3, FAR_POINT, np.float32)
+        return far, far.copy()
     lo = lo - (np.abs(lo) * PAD_REL + PAD_ABS)
     hi = hi + (np.abs(hi) * PAD_REL + PAD_ABS)
     return lo.astype(np.float32), hi.astype(np.float32)
+
+
+def degenerate(tri):
+    """Zero-area triangles: the FP64 cross product of their edges is zero."""
+    t = np.asarray(tri, np.float32).reshape(-1, 3, 3).astype(np.float64)
+    c = np.cross(t[:, 1] - t[:, 0], t[:, 2] - t[:, 0])
+    return np.all(c == 0.0, axis=1)
 
 
 def build(tri):
@@ -124,13 +138,18 @@ def build(tri):
     n = lo.shape[0]
     rec = np.zeros((max(n - 1, 1), 16), np.float32)
     ints = rec.view(np.int32)
+    deg = degenerate(tri)
     if n == 1:
+        if deg[0]:
+            lo, hi = np.full_like(lo, np.inf), np.full_like(hi, -np.inf)
         plo, phi = _pad(lo[0], hi[0])
         rec[0, 0:6:2], rec[0, 1:6:2] = plo, phi
         rec[0, 6:12] = FAR_POINT
         ints[0, 12:16] = [~0, ~0, -1, -1]
         return dict(keys=np.zeros(1, np.uint64), tri_id=np.zeros(1, np.int32), records=rec, depth=0)
     keys = morton_keys(lo, hi)
+    lo, hi = lo.copy(), hi.copy()
+    lo[deg], hi[deg] = np.float32(np.inf), np.float32(-np.inf)
     order = np.argsort(keys, kind="stable").astype(np.int32)
     skeys = keys[order]
     c0, c1, parent, sibling = karras(skeys)

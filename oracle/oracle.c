@@ -89,11 +89,16 @@ static v3 mat_tmul(const double R[9], v3 v) {
     return r;
 }
 
-/* Ray/plane of one triangle: returns 0 when the ray is parallel to its plane.
+/* Ray/plane of one triangle: returns 0 when the ray is parallel to its plane,
+ * or when the triangle has zero area (its edges are parallel: no interior, so
+ * no ray meets it; tested on the cross product of the edges, which is exact
+ * for single-precision vertices).
  * *lam = ray parameter of the plane crossing, *mb = min barycentric there. */
 static int tri_plane(v3 o, v3 d, const float* t9, double* lam, double* mb) {
     v3 p0 = v3f(t9), p1 = v3f(t9 + 3), p2 = v3f(t9 + 6);
     v3 e1 = sub(p1, p0), e2 = sub(p2, p0);
+    v3 n = cross(e1, e2);
+    if (n.x == 0.0 && n.y == 0.0 && n.z == 0.0) return 0;
     v3 P = cross(d, e2);
     double det = dot(e1, P);
     if (det == 0.0) return 0;

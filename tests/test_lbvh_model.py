@@ -84,3 +84,50 @@ def test_boxes_contain_children_and_leaves():
                 clo = np.minimum(rec[c, 0:6:2], rec[c, 6:12:2])
                 chi = np.maximum(rec[c, 1:6:2], rec[c, 7:12:2])
                 assert np.all(clo >= lo) and np.all(chi <= hi), "parents contain their children"
+
+
+def _with_degenerate(n_good=400, seed=2):
+    tri = sg.TileTerrain(1).triangles()[:n_good].copy()
+    rng = np.random.default_rng(seed)
+    p = tri[rng.choice(n_good, 30), 0]  # existing vertices
+    q = tri[rng.choice(n_good, 30), 1]
+    u = np.float32([2.0 ** -6, 0.0, 0.0])
+    deg = np.concatenate([np.stack([p, p, p], 1), np.stack([p, q, p], 1),
+                          np.stack([p - u, p, p + u], 1)], 0).astype(np.float32)
+    return np.concatenate([tri, deg], 0), n_good
+
+
+def test_degenerate_triangles_are_unreachable():
+    """Zero-area triangles (three equal vertices, two equal, three on one
+    line) keep their Morton codes, but their leaf boxes become the far point
+    and every other box is the padded union of the non-degenerate leaves."""
+    tri, n_good = _with_degenerate()
+    assert np.array_equal(np.nonzero(lbvh.degenerate(tri))[0], np.arange(n_good, tri.shape[0]))
+    m = lbvh.build(tri)
+    lo, hi = lbvh.prim_boxes(tri)
+    assert np.array_equal(m["keys"], np.sort(lbvh.morton_keys(lo, hi)))
+    rec, ints = m["records"], m["records"].view(np.int32)
+    t = tri.reshape(-1, 9)[m["tri_id"]].reshape(-1, 3, 3)
+    is_deg = m["tri_id"] >= n_good
+
+    def leaves(c):  # leaf indices below child c
+        if c < 0:
+            return [~c]
+        return leaves(ints[c, 12]) + leaves(ints[c, 13])
+
+    far = np.full(3, lbvh.FAR_POINT, np.float32)
+    for i in range(rec.shape[0]):
+        for h in (0, 1):
+            blo, bhi = rec[i, 6 * h:6 * h + 6:2], rec[i, 6 * h + 1:6 * h + 6:2]
+            good = [k for k in leaves(ints[i, 12 + h]) if not is_deg[k]]
+            if not good:
+                assert np.array_equal(blo, far) and np.array_equal(bhi, far)
+                continue
+            ulo, uhi = t[good].min((0, 1)), t[good].max((0, 1))
+            plo, phi = lbvh._pad(ulo, uhi)
+            assert np.array_equal(blo, plo) and np.array_equal(bhi, phi)
+
+
+def test_single_degenerate_triangle():
+    m = lbvh.build(np.array([[[0, 0, 0], [1, 1, 1], [2, 2, 2]]], np.float32))
+    assert np.all(m["records"][0, :12] == lbvh.FAR_POINT)

@@ -186,6 +186,30 @@ def random_scene(seed, n_tri=40, E=2, C=2, W=9, H=7):
     return terr, link, lp, lq, cp, cq, intr, W, H
 
 
+def test_zero_area_triangles_are_never_hit():
+    """A triangle with no interior (equal or collinear vertices) is met by no
+    ray, also by a ray through its points; a proper triangle through the same
+    point is hit there."""
+    p = np.array([0.25, -0.5, 1.0], np.float32)
+    q = np.array([0.75, 0.5, 1.25], np.float32)
+    u = np.float32([2.0 ** -6, 0.0, 0.0])
+    tris = {"point": [p, p, p], "pair": [p, q, p], "line": [p - u, p, p + u],
+            "slanted line": [p - 2 * (q - p), p, q]}
+    good = np.array([[[-1, -1, 1], [2, -1, 1], [-1, 2, 1]]], np.float32)
+    cam_pos = np.zeros((1, 1, 3), np.float32)
+    # optical axis through p: a 1x1 image whose pixel centre ray is (0.25, -0.5, 1)
+    intr = np.array([[[1.0, 1.0, 0.25, 1.0]]], np.float32)
+    quat = np.array([[[0.0, 0.0, 0.0, 1.0]]], np.float32)
+    empty = (np.zeros((0, 3, 3), np.float32), np.zeros(1, np.int64),
+             np.zeros((1, 0, 3), np.float32), np.zeros((1, 0, 4), np.float32))
+    for name, t in tris.items():
+        t = np.asarray(t, np.float32)[None]
+        r = oracle.render(t, *empty, cam_pos, quat, intr, 1, 1, 3.0)
+        assert r["inst"][0] == -1 and r["depth"][0] == 3.0, name
+        r = oracle.render(np.concatenate([t, good], 0), *empty, cam_pos, quat, intr, 1, 1, 3.0)
+        assert r["inst"][0] == 0 and r["tri"][0] == 1 and r["depth"][0] == pytest.approx(1.0), name
+
+
 def test_permutation_invariance():
     terr, link, lp, lq, cp, cq, intr, W, H = random_scene(1)
     off = np.array([0, link.shape[0]], np.int64)
