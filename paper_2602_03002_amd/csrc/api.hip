@@ -84,11 +84,16 @@ __global__ void k_link_meta(const char* base, LinkMeta* meta, const int64_t* tab
     M.id_base = (int32_t)(t[2] / 4);
     M.n_tri = (int32_t)t[3];
     const Node* root = reinterpret_cast<const Node*>(base + t[0]);
+    // union of the root record's boxes, leaving out the far point (a single
+    // leaf's second box, or a subtree of zero-area triangles)
+    const bool use0 = root->b0[0] != kFarBox;
+    const bool use1 = M.n_tri > 1 && root->b1[0] != kFarBox;
     for (int a = 0; a < 3; ++a) {
-        float lo = root->b0[2 * a], hi = root->b0[2 * a + 1];
-        if (M.n_tri > 1) {
-            lo = fminf(lo, root->b1[2 * a]);
-            hi = fmaxf(hi, root->b1[2 * a + 1]);
+        float lo = kFarBox, hi = kFarBox;
+        if (use0) { lo = root->b0[2 * a]; hi = root->b0[2 * a + 1]; }
+        if (use1) {
+            lo = use0 ? fminf(lo, root->b1[2 * a]) : root->b1[2 * a];
+            hi = use0 ? fmaxf(hi, root->b1[2 * a + 1]) : root->b1[2 * a + 1];
         }
         M.root[2 * a] = lo;
         M.root[2 * a + 1] = hi;

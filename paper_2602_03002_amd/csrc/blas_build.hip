@@ -245,6 +245,28 @@ __device__ __forceinline__ float aload(const float* p) {
     return __uint_as_float(u);
 }
 
+// A triangle of zero area (its edge vectors parallel: coincident or
+// collinear vertices) is met by no ray; its leaf box becomes empty, which the
+// bottom-up union ignores, and the padding step makes it unreachable.  Edges
+// and cross product in FP64 (exact for single-precision vertices of similar
+// magnitude), zero in all three components.
+__global__ void k_drop_degenerate(const float* __restrict__ tri, int64_t n, float* __restrict__ box) {
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i >= n) return;
+    const float* t = tri + 9 * i;
+    const double ux = (double)t[3] - (double)t[0], uy = (double)t[4] - (double)t[1],
+                 uz = (double)t[5] - (double)t[2];
+    const double vx = (double)t[6] - (double)t[0], vy = (double)t[7] - (double)t[1],
+                 vz = (double)t[8] - (double)t[2];
+    const double cx = uy * vz - uz * vy, cy = uz * vx - ux * vz, cz = ux * vy - uy * vx;
+    if (cx == 0.0 && cy == 0.0 && cz == 0.0) {
+        for (int a = 0; a < 3; ++a) {
+            box[6 * i + 2 * a] = INFINITY;
+            box[6 * i + 2 * a + 1] = -INFINITY;
+        }
+    }
+}
+
 __global__ void k_fit(const float* __restrict__ box, const uint32_t* __restrict__ vals, int64_t n,
                       Node* nodes, const int32_t* __restrict__ leaf_parent, uint32_t* flags) {
     int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
@@ -287,18 +309,24 @@ __global__ void k_depth(const Node* __restrict__ nodes, int64_t n_int, int32_t* 
 __device__ __forceinline__ float pad_lo(float x) { return x - (fabsf(x) * kPadRel + kPadAbs); }
 __device__ __forceinline__ float pad_hi(float x) { return x + (fabsf(x) * kPadRel + kPadAbs); }
 
+// Pad a child box outward, or, if it is empty (a subtree of zero-area
+// triangles only), replace it by the far point no ray reaches.
+__device__ __forceinline__ void pad_box(float* b) {
+    const bool empty = (b[0] > b[1]) | (b[2] > b[3]) | (b[4] > b[5]);
+    for (int a = 0; a < 3; ++a) {
+        b[2 * a] = empty ? kFarBox : pad_lo(b[2 * a]);
+        b[2 * a + 1] = empty ? kFarBox : pad_hi(b[2 * a + 1]);
+    }
+}
+
 __global__ void k_pad_and_gather(Node* __restrict__ nodes, int64_t n_int, const float* __restrict__ tri,
                                  const uint32_t* __restrict__ vals, int64_t n,
                                  float* __restrict__ tris, int32_t* __restrict__ tri_id) {
     int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (i < n_int) {
         Node* P = nodes + i;
-        for (int a = 0; a < 3; ++a) {
-            P->b0[2 * a] = pad_lo(P->b0[2 * a]);
-            P->b0[2 * a + 1] = pad_hi(P->b0[2 * a + 1]);
-            P->b1[2 * a] = pad_lo(P->b1[2 * a]);
-            P->b1[2 * a + 1] = pad_hi(P->b1[2 * a + 1]);
-        }
+        pad_box(P->b0);
+        pad_box(P->b1);
     }
     if (i < n) {
         uint32_t v = vals[i];
@@ -314,12 +342,11 @@ __global__ void k_single_leaf(const float* __restrict__ box, Node* __restrict__ 
                               int32_t* __restrict__ tri_id, uint64_t* __restrict__ keys,
                               int32_t* __restrict__ depth) {
     Node* P = nodes;
-    for (int a = 0; a < 3; ++a) {
-        P->b0[2 * a] = pad_lo(box[2 * a]);
-        P->b0[2 * a + 1] = pad_hi(box[2 * a + 1]);
-        P->b1[2 * a] = 1.0e30f;
-        P->b1[2 * a + 1] = 1.0e30f;
+    for (int k = 0; k < 6; ++k) {
+        P->b0[k] = box[k];
+        P->b1[k] = kFarBox;
     }
+    pad_box(P->b0);
     P->c0 = ~0;
     P->c1 = ~0;
     P->parent = -1;
@@ -378,12 +405,15 @@ hipError_t launch_blas_build(const float* tri, int64_t n, char* ws, const BvhLay
 
     hipLaunchKernelGGL(k_prim_bounds, dim3(nblk(n)), dim3(kThreads), 0, s, tri, n, box, partial);
     if (n == 1) {
+        hipLaunchKernelGGL(k_drop_degenerate, dim3(1), dim3(kThreads), 0, s, tri, n, box);
         hipLaunchKernelGGL(k_single_leaf, dim3(1), dim3(1), 0, s, box, nodes, tri, tris, tri_id,
                            keys, depth);
         return hipGetLastError();
     }
     hipLaunchKernelGGL(k_reduce_bounds, dim3(1), dim3(kThreads), 0, s, partial, L.n_blocks_red, cb);
     hipLaunchKernelGGL(k_morton, dim3(nblk(n)), dim3(kThreads), 0, s, box, n, cb, keys, vals);
+    // after the codes (box centres): zero-area triangles get empty leaf boxes
+    hipLaunchKernelGGL(k_drop_degenerate, dim3(nblk(n)), dim3(kThreads), 0, s, tri, n, box);
     const int64_t nb = L.n_blocks_sort;
     uint64_t* kin = keys;
     uint64_t* kout = keys_alt;

@@ -282,6 +282,8 @@ struct RayCount {
 // repeats the test in FP64.  The hit distance is T * rcp(det) (a couple of
 // ulp; the same expression in both passes), the input triangle id is read
 // only for an accepted hit.
+// Zero-area triangles never get here: the hierarchy builder makes them
+// unreachable (their edge functions would be rounding residues of one sign).
 template <bool EXACT>
 __device__ __forceinline__ void tri_test(const float* __restrict__ v,
                                          const int32_t* __restrict__ tri_ids, uint32_t inst,

@@ -14,7 +14,8 @@ namespace rc {
 // then child0, child1, parent, sibling.  child >= 0: internal node; child < 0:
 // leaf ~child.  A BVH over n >= 2 leaves has n - 1 records (root = 0); over one
 // leaf it has one record whose second box is a point at (1e30, 1e30, 1e30),
-// beyond any far plane.
+// beyond any far plane.  The same far point stands for a child subtree that
+// holds only zero-area triangles.
 struct alignas(16) Node {
     float b0[6];
     float b1[6];
@@ -44,6 +45,7 @@ static_assert(sizeof(InstXform) == 48, "instance transform is 48 bytes");
 
 constexpr int kMaxLinks = 64;
 constexpr int kMaxDepth = 64;          // bits in the traversal trail
+constexpr float kFarBox = 1.0e30f;               // the unreachable box (a far point)
 constexpr float kPadRel = 9.5367431640625e-07f;  // 2^-20, outward box padding
 constexpr float kPadAbs = 1.0e-5f;               // metres
 constexpr float kInstPadRel = 9.5367431640625e-07f;

@@ -17,7 +17,6 @@ namespace rc {
 namespace {
 
 constexpr int kWaves = 4;
-constexpr float kFarPoint = 1.0e30f;
 
 __device__ __forceinline__ uint32_t spread10(uint32_t v) {
     uint32_t x = v & 0x3FFu;
@@ -168,7 +167,7 @@ k_tlas(const float* __restrict__ link_pos, const float* __restrict__ link_quat, 
     if (B == 1) {
         if (lane == 0) {
             Node P;
-            for (int k = 0; k < 6; ++k) { P.b0[k] = sbox[w][0][k]; P.b1[k] = kFarPoint; }
+            for (int k = 0; k < 6; ++k) { P.b0[k] = sbox[w][0][k]; P.b1[k] = kFarBox; }
             P.c0 = ~0; P.c1 = ~0; P.parent = -1; P.sibling = -1;
             out[0] = P;
         }

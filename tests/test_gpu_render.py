@@ -77,13 +77,21 @@ def check_bvh(buf, lay, tri):
     assert lay.max_depth == model["depth"]
 
 
-@pytest.mark.parametrize("which", ["profile", "tiles2", "single"])
+@pytest.mark.parametrize("which", ["profile", "tiles2", "single", "degenerate", "single_degenerate"])
 def test_terrain_bvh_bit_exact(which):
     say(f"[bvh] terrain {which}")
     if which == "profile":
         tri = sg.small_plain_case()["terrain"]
     elif which == "tiles2":
         tri = sg.TileTerrain(2).triangles()
+    elif which == "degenerate":
+        # zero-area triangles among proper ones: unreachable leaves
+        t = sg.TileTerrain(1).triangles()[:5000]
+        p = t[::97, 0]
+        u = np.float32([2.0 ** -6, 0.0, 0.0])
+        tri = np.concatenate([t, np.stack([p, p, p], 1), np.stack([p - u, p, p + u], 1)], 0)
+    elif which == "single_degenerate":
+        tri = np.array([[[0, 0, 0], [1, 1, 1], [2, 2, 2]]], np.float32)
     else:
         tri = np.array([[[0, 0, 0], [1, 0, 0], [0, 1, 0]]], np.float32)
     sc = rc().Scene(dev(tri))
