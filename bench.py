@@ -78,6 +78,7 @@ def measured_issue():
     if sq.get("kernel_source_sha256") == kernel_sha():
         out["valu_issue_frac"] = float(sq["valu_issue_per_cu_cycle"])
         out["salu_issue_frac"] = float(sq["salu_issue_per_cu_cycle"])
+        out["valu_insts_per_launch"] = float(sq["SQ_INSTS_VALU"])
     if l2.get("kernel_source_sha256") == kernel_sha():
         out["l2_hit_rate"] = float(l2["l2_hit_rate"])
     return out
@@ -657,6 +658,15 @@ def main():
                 "kernel_ms": round(r_ms, 4), "copy_gbs": round(copy_gbs, 1),
                 "frac_of_copy": round(achieved / copy_gbs, 4)}
         roof.update(measured_issue())
+        if "valu_insts_per_launch" in roof:
+            # VALU utilisation beside the FP32 vector peak (157.3 TFLOP/s counts an
+            # FMA as two and packed FP32, which this build leaves off); one wave64
+            # VALU instruction per CU-cycle is 256 x 64 x 2.4 GHz = 39.3 T lane-ops/s
+            lane_ops = roof.pop("valu_insts_per_launch") * 64 / (r_ms / 1e3) / 1e12
+            roof["valu"] = {"achieved_t_lane_ops_s": round(lane_ops, 2),
+                            "issue_peak_t_lane_ops_s": 39.32,
+                            "frac_of_issue_peak": round(lane_ops / 39.32, 4),
+                            "fp32_vector_peak_tflops": 157.3}
     # bytes a step cannot avoid: the scene read once, top levels written and
     # read, poses, render outputs, sensor-model traffic
     lay = sc.bvh_layout(-1)
