@@ -457,7 +457,9 @@ def bench_serving(sc, w_main, capacity_mrays, duration_s=6.0, stream_s=60.0):
     sample = [draw() for _ in range(20000)]
     mean_rays = float(np.mean([n * k * r[0] * r[1] for n, k, r, _ in sample]))
 
-    def run(rate, seconds, n_streams=4, max_batch_rays=1 << 24):
+    # 16 streams and batches of at most 4M rays: the best tail of a sweep over
+    # 2-16 streams and 4M-32M rays at 80% load and at 2000 req/s
+    def run(rate, seconds, n_streams=16, max_batch_rays=1 << 22):
         srv = rc.Server(sc, n_streams=n_streams, max_batch_rays=max_batch_rays,
                         out_pixels=1 << 26, scratch_bytes=1 << 30, far_plane=w["far"])
         arrivals = np.cumsum(rng.exponential(1.0 / rate, int(rate * seconds * 1.5) + 16))

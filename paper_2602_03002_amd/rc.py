@@ -623,7 +623,7 @@ class Server:
     batches and starts new ones; next_result() hands back finished requests whose
     outputs stay valid until release()."""
 
-    def __init__(self, scene, n_streams=4, max_batch_rays=1 << 24, out_pixels=1 << 26,
+    def __init__(self, scene, n_streams=8, max_batch_rays=1 << 22, out_pixels=1 << 26,
                  scratch_bytes=1 << 30, far_plane=3.0, depth_mode=RC_DEPTH_PLANAR, _sim=None):
         L = lib()
         self.cfg = ServerConfig(n_streams, int(max_batch_rays), int(out_pixels), float(far_plane),

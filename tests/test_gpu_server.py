@@ -63,7 +63,7 @@ def test_result_same_alone_and_in_mix():
         srv = m.Server(sc, n_streams=1, out_pixels=1 << 22, scratch_bytes=1 << 27)
         alone.update(run(srv, reqs, [k]))
         srv.close()
-    for n_streams, cap in ((1, 1 << 24), (3, 20000)):
+    for n_streams, cap in ((1, 1 << 24), (3, 20000), (16, 1 << 22)):
         srv = m.Server(sc, n_streams=n_streams, max_batch_rays=cap, out_pixels=1 << 22,
                        scratch_bytes=1 << 27)
         mixed = run(srv, reqs, [2, 0, 1])
