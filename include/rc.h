@@ -382,7 +382,8 @@ rc_status rc_server_release(rc_server* srv, int64_t id);
  * every poll). */
 rc_status rc_server_stats_get(const rc_server* srv, rc_server_stats* out);
 
-/* Wait for all batches in flight (GPU servers), then free the handle. */
+/* Wait for all batches in flight (GPU servers), then free the handle.  The
+ * handle is freed in every case; DEVICE reports an error the wait met. */
 rc_status rc_server_destroy(rc_server* srv);
 
 /* ---------------------------------------------------------------------

@@ -634,8 +634,8 @@ rc_status rc_autotune(rc_scene* scene, const rc_render_args* plain, const rc_bat
                 ms /= (float)reps;
                 if (e == hipSuccess && ms < win_ms) { win_ms = ms; win = c; }
             }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (e != hipSuccess) return hip_fail(e, "rc_autotune");
     (plain ? scene->cfg : scene->cfg_batched) = win;
     if (best) *best = from_cfg(win);
@@ -668,7 +668,7 @@ rc_status rc_graph_capture_batched(const rc_scene* scene, const rc_batch_args* a
     }
     if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
     if (e != hipSuccess) {
-        if (g->graph) hipGraphDestroy(g->graph);
+        if (g->graph) (void)hipGraphDestroy(g->graph);
         delete g;
         return hip_fail(e, "rc_graph_capture_batched");
     }
@@ -685,8 +685,8 @@ rc_status rc_graph_launch(rc_graph* graph, rc_stream stream) {
 
 rc_status rc_graph_destroy(rc_graph* graph) {
     if (!graph) return RC_OK;
-    if (graph->exec) hipGraphExecDestroy(graph->exec);
-    if (graph->graph) hipGraphDestroy(graph->graph);
+    if (graph->exec) (void)hipGraphExecDestroy(graph->exec);
+    if (graph->graph) (void)hipGraphDestroy(graph->graph);
     delete graph;
     return RC_OK;
 }

@@ -330,13 +330,15 @@ rc_status rc_server_create(const rc_scene* scene, const rc_server_config* cfg, v
     s->tri = (int32_t*)(a + 2 * plane);
     s->scratch = a + 3 * plane;
     for (int k = 0; k < cfg->n_streams; ++k) {
-        hipStream_t st;
-        hipEvent_t ev;
-        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess ||
-            hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+        hipStream_t st = nullptr;
+        hipEvent_t ev = nullptr;
+        const bool st_ok = hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess;
+        const bool ev_ok = st_ok && hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess;
+        if (!ev_ok) {  // release what was made (cleanup is best effort)
+            if (st_ok) (void)hipStreamDestroy(st);
             for (size_t j = 0; j < s->streams.size(); ++j) {
-                hipStreamDestroy(s->streams[j]);
-                hipEventDestroy(s->events[j]);
+                (void)hipStreamDestroy(s->streams[j]);
+                (void)hipEventDestroy(s->events[j]);
             }
             delete s;
             return fail_s(RC_ERR_DEVICE, "rc_server_create: stream or event creation failed");
@@ -453,12 +455,16 @@ rc_status rc_server_stats_get(const rc_server* s, rc_server_stats* out) {
 
 rc_status rc_server_destroy(rc_server* s) {
     if (!s) return RC_OK;
+    hipError_t first = hipSuccess;  // everything is released even after a device error
     for (size_t k = 0; k < s->streams.size(); ++k) {
-        hipStreamSynchronize(s->streams[k]);
-        hipStreamDestroy(s->streams[k]);
-        hipEventDestroy(s->events[k]);
+        const hipError_t e = hipStreamSynchronize(s->streams[k]);
+        if (first == hipSuccess) first = e;
+        (void)hipStreamDestroy(s->streams[k]);
+        (void)hipEventDestroy(s->events[k]);
     }
     delete s;
+    if (first != hipSuccess) return fail_s(RC_ERR_DEVICE, std::string("rc_server_destroy: ") +
+                                                              hipGetErrorString(first));
     return RC_OK;
 }
 

@@ -689,8 +689,8 @@ class Server:
 
     def close(self):
         if self.handle:
-            lib().rc_server_destroy(self.handle)
-            self.handle = None
+            h, self.handle = self.handle, None
+            check(lib().rc_server_destroy(h))  # freed either way; raises on a device error
 
     def __del__(self):
         try:
