@@ -46,19 +46,17 @@ __device__ __forceinline__ int side_mask_cols(const PostLaunch& a, int env, int 
     return (int)floorf(__fmul_rn(a.mask_frac[mode], (float)width) + 0.5f);
 }
 
-// Sensor model of packed pixel p: pixel `pix` of its image (width `width`),
-// camera `uid`, whose latency at this step is k frames; mask_m side columns
-// of the image are masked.
-__device__ __forceinline__ void post_pixel(const PostLaunch& a, int64_t p, uint32_t pix, uint32_t uid,
-                                           int k, int mask_m, int width) {
-    const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
-    const uint64_t s = a.step;
+// The draw of pixel `pix` of camera `uid` at this step.
+__device__ __forceinline__ uint4 pixel_draw(const PostLaunch& a, uint32_t pix, uint32_t uid) {
+    return philox4x32_10(make_uint4(pix, uid, (uint32_t)a.step, step_hi(a.step)), (uint32_t)a.seed,
+                         (uint32_t)(a.seed >> 32));
+}
 
-    // capture of this step
-    const float z = a.depth_in[p];
-    const bool hit = a.inst_in ? (a.inst_in[p] >= 0) : (z < a.far_plane);
-    const uint4 wd = philox4x32_10(make_uint4(pix, uid, (uint32_t)s, step_hi(s)), k0, k1);
-    const bool drop = (a.flags & RC_POST_DROPOUT) && ((uint64_t)wd.x < a.drop_thr);
+// Capture of one pixel at this step: noise on hits, clamp to [near, far],
+// dropout (the capture is then the fill value).
+__device__ __forceinline__ float capture(const PostLaunch& a, float z, bool hit, const uint4& wd,
+                                         bool& drop) {
+    drop = (a.flags & RC_POST_DROPOUT) && ((uint64_t)wd.x < a.drop_thr);
     float zz;
     if (hit) {
         float g = 0.0f;
@@ -72,13 +70,39 @@ __device__ __forceinline__ void post_pixel(const PostLaunch& a, int64_t p, uint3
         zz = a.far_plane;
     }
     zz = fminf(fmaxf(zz, a.near_plane), a.far_plane);
-    const float cap = drop ? a.fill : zz;
+    return drop ? a.fill : zz;
+}
+
+// Frames back to the capture shown at this step: max(s - k, s0) (k < ring_len).
+__device__ __forceinline__ int delay(const PostLaunch& a, int k) {
+    return (a.step - a.s0 >= (uint64_t)k) ? k : (int)(a.step - a.s0);
+}
+
+// Side masking: is column x masked, and the fill from word 3 of the draw.
+__device__ __forceinline__ bool masked_col(uint32_t pix, int mask_m, int width) {
+    const int x = (int)(pix % (uint32_t)width);
+    return x < mask_m || x >= width - mask_m;
+}
+__device__ __forceinline__ float mask_fill(const PostLaunch& a, const uint4& wd) {
+    const float u = (float)(wd.w >> 8) * 5.9604644775390625e-08f;
+    return __fmaf_rn(a.far_plane - a.near_plane, u, a.near_plane);
+}
+
+// Sensor model of packed pixel p: pixel `pix` of its image (width `width`),
+// camera `uid`, whose latency at this step is k frames; mask_m side columns
+// of the image are masked.
+__device__ __forceinline__ void post_pixel(const PostLaunch& a, int64_t p, uint32_t pix, uint32_t uid,
+                                           int k, int mask_m, int width) {
+    const float z = a.depth_in[p];
+    const bool hit = a.inst_in ? (a.inst_in[p] >= 0) : (z < a.far_plane);
+    const uint4 wd = pixel_draw(a, pix, uid);
+    bool drop;
+    const float cap = capture(a, z, hit, wd, drop);
     const int64_t here = (int64_t)a.slot * a.n_pix + p;
     a.ring[here] = cap;
     a.ring_drop[here] = drop ? 1 : 0;
 
-    // frame shown at this step: the capture of step max(s - k, s0), k < ring_len
-    const int d = (s - a.s0 >= (uint64_t)k) ? k : (int)(s - a.s0);
+    const int d = delay(a, k);
     float out = cap;
     bool out_drop = drop;
     if (d > 0) {
@@ -87,20 +111,64 @@ __device__ __forceinline__ void post_pixel(const PostLaunch& a, int64_t p, uint3
         out = a.ring[there];
         out_drop = a.ring_drop[there] != 0;
     }
-    if (mask_m > 0) {  // random side masking of the frame shown
-        const int x = (int)(pix % (uint32_t)width);
-        if (x < mask_m || x >= width - mask_m) {
-            const float u = (float)(wd.w >> 8) * 5.9604644775390625e-08f;
-            out = __fmaf_rn(a.far_plane - a.near_plane, u, a.near_plane);
-            out_drop = false;
-        }
+    if (mask_m > 0 && masked_col(pix, mask_m, width)) {  // random side masking of the frame shown
+        out = mask_fill(a, wd);
+        out_drop = false;
     }
     a.depth_out[p] = out;
     if (a.drop_out) a.drop_out[p] = out_drop ? 1 : 0;
 }
 
+// The same for four consecutive pixels p .. p+3 of one image (p a multiple of
+// 4, arrays aligned for 16-byte and 4-byte accesses): wide loads and stores,
+// four independent draws per thread.
+__device__ __forceinline__ void post_quad(const PostLaunch& a, int64_t p, uint32_t pix, uint32_t uid,
+                                          int k, int mask_m, int width) {
+    const float4 z4 = *reinterpret_cast<const float4*>(a.depth_in + p);
+    const float z[4] = {z4.x, z4.y, z4.z, z4.w};
+    int4 i4 = make_int4(0, 0, 0, 0);
+    if (a.inst_in) i4 = *reinterpret_cast<const int4*>(a.inst_in + p);
+    const int id[4] = {i4.x, i4.y, i4.z, i4.w};
+    uint4 wd[4];
+    float cap[4];
+    uint32_t bits = 0u;
+    for (int j = 0; j < 4; ++j) {
+        wd[j] = pixel_draw(a, pix + (uint32_t)j, uid);
+        const bool hit = a.inst_in ? (id[j] >= 0) : (z[j] < a.far_plane);
+        bool drop;
+        cap[j] = capture(a, z[j], hit, wd[j], drop);
+        bits |= (drop ? 1u : 0u) << (8 * j);
+    }
+    const int64_t here = (int64_t)a.slot * a.n_pix + p;
+    *reinterpret_cast<float4*>(a.ring + here) = make_float4(cap[0], cap[1], cap[2], cap[3]);
+    *reinterpret_cast<uint32_t*>(a.ring_drop + here) = bits;
+
+    const int d = delay(a, k);
+    float out[4] = {cap[0], cap[1], cap[2], cap[3]};
+    uint32_t obits = bits;
+    if (d > 0) {
+        const int slot = a.slot >= d ? a.slot - d : a.slot - d + a.ring_len;
+        const int64_t there = (int64_t)slot * a.n_pix + p;
+        const float4 o4 = *reinterpret_cast<const float4*>(a.ring + there);
+        out[0] = o4.x; out[1] = o4.y; out[2] = o4.z; out[3] = o4.w;
+        obits = *reinterpret_cast<const uint32_t*>(a.ring_drop + there);
+    }
+    if (mask_m > 0) {
+        for (int j = 0; j < 4; ++j) {
+            if (masked_col(pix + (uint32_t)j, mask_m, width)) {
+                out[j] = mask_fill(a, wd[j]);
+                obits &= ~(0xFFu << (8 * j));
+            }
+        }
+    }
+    *reinterpret_cast<float4*>(a.depth_out + p) = make_float4(out[0], out[1], out[2], out[3]);
+    if (a.drop_out) *reinterpret_cast<uint32_t*>(a.drop_out + p) = obits;
+}
+
 // Plain layout [env][cam][height][width]: block row x = image (env, cam), the
 // blocks of a row stride over its pixels.
+// QUAD: four pixels per thread (the image size a multiple of 4).
+template <bool QUAD>
 __global__ void __launch_bounds__(256) k_post(PostLaunch a) {
     const int64_t ec = blockIdx.x;
     const int64_t hw = (int64_t)a.height * a.width;
@@ -108,9 +176,12 @@ __global__ void __launch_bounds__(256) k_post(PostLaunch a) {
     const int k = latency_draw(a, uid);
     const int mask_m = side_mask_cols(a, (int)(ec / a.n_cam), a.width);
     if (a.lat_out && blockIdx.y == 0 && threadIdx.x == 0) a.lat_out[ec] = (uint8_t)k;
-    for (int64_t q = (int64_t)blockIdx.y * blockDim.x + threadIdx.x; q < hw;
-         q += (int64_t)gridDim.y * blockDim.x)
-        post_pixel(a, ec * hw + q, (uint32_t)q, uid, k, mask_m, a.width);
+    const int64_t n = QUAD ? hw / 4 : hw;
+    for (int64_t q = (int64_t)blockIdx.y * blockDim.x + threadIdx.x; q < n;
+         q += (int64_t)gridDim.y * blockDim.x) {
+        if (QUAD) post_quad(a, ec * hw + 4 * q, (uint32_t)(4 * q), uid, k, mask_m, a.width);
+        else post_pixel(a, ec * hw + q, (uint32_t)q, uid, k, mask_m, a.width);
+    }
 }
 
 // Packed batch: block row x = camera descriptor, the blocks of a row stride
@@ -171,9 +242,14 @@ hipError_t launch_downsample(const float* depth, const int32_t* inst, int64_t n_
 
 hipError_t launch_post(const PostLaunch& a, hipStream_t s) {
     const int64_t hw = (int64_t)a.height * a.width;
-    const unsigned per_image = (unsigned)std::min<int64_t>((hw + 255) / 256, 1024);
-    hipLaunchKernelGGL(k_post, dim3((unsigned)((int64_t)a.n_env * a.n_cam), per_image), dim3(256), 0,
-                       s, a);
+    auto al = [](const void* q, uintptr_t m) { return ((uintptr_t)q & (m - 1)) == 0; };
+    const bool quad = hw % 4 == 0 && al(a.depth_in, 16) && al(a.inst_in, 16) && al(a.ring, 16) &&
+                      al(a.depth_out, 16) && al(a.ring_drop, 4) && al(a.drop_out, 4);
+    const int64_t items = quad ? hw / 4 : hw;
+    const unsigned per_image = (unsigned)std::min<int64_t>((items + 255) / 256, 1024);
+    const dim3 grid((unsigned)((int64_t)a.n_env * a.n_cam), per_image);
+    if (quad) hipLaunchKernelGGL(k_post<true>, grid, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(k_post<false>, grid, dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

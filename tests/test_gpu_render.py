@@ -270,10 +270,13 @@ def run_post(depth, inst, params_kw, s0=0, cam_uid=None, max_latency=3):
     return np.stack(outs), np.stack(drops), np.stack(lats)
 
 
-@pytest.mark.parametrize("s0,with_uid", [(0, False), (5, True)])
-def test_post_matches_oracle(s0, with_uid):
-    say(f"[post] 3 envs x 2 cams 29x37, 9 steps from {s0}, uid table {with_uid}")
-    depth, inst = sg.synthetic_frames(3, 2, 29, 37, 9)
+@pytest.mark.parametrize("s0,with_uid,hw", [(0, False, (29, 37)), (5, True, (29, 37)),
+                                             (0, False, (24, 36)), (5, True, (24, 36))])
+def test_post_matches_oracle(s0, with_uid, hw):
+    """Odd image sizes take the one-pixel-per-thread form, sizes divisible by
+    four the four-pixel form."""
+    say(f"[post] 3 envs x 2 cams {hw[0]}x{hw[1]}, 9 steps from {s0}, uid table {with_uid}")
+    depth, inst = sg.synthetic_frames(3, 2, hw[0], hw[1], 9)
     kw = dict(seed=0x1234_5678_9ABC, sigma_abs=0.01, sigma_rel=0.02, p_drop=0.02, near=0.05,
               far=3.0, fill=0.0, lat_min=1, lat_max=3)
     uid = (np.arange(6, dtype=np.uint32) * 7 + 100) if with_uid else None
