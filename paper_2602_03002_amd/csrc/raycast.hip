@@ -802,8 +802,10 @@ __device__ void cam_randomize(const rc_cam_rand& p, uint32_t uid, double* b) {
     }
 }
 
-// Ray bases of every camera of the launch (randomised when asked).
-__global__ void k_cam_prep(RenderLaunch a, int64_t n) {
+// Ray bases of every camera of the launch (randomised when asked); `zero`:
+// the exact-pass counters to reset first (plain form), or NULL.
+__global__ void k_cam_prep(RenderLaunch a, int64_t n, uint32_t* zero) {
+    if (zero && blockIdx.x == 0 && threadIdx.x == 0) zero[0] = zero[1] = 0u;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
         double* b = a.cam_basis + kCamBasis * i;
@@ -1093,7 +1095,6 @@ __device__ __forceinline__ void resolve_one(const RenderLaunch& a, const uint4 h
     write_out(a, head.x, h, cam, x, y);
 }
 
-__global__ void k_zero_count(uint32_t* c) { c[0] = c[1] = 0u; }
 
 __global__ void __launch_bounds__(64) k_render_exact(RenderLaunch a, const uint32_t* tile_start) {
     const uint32_t n_res = a.exact_count[0], n_full = a.exact_count[1];
@@ -1208,10 +1209,12 @@ hipError_t launch_render(const RenderLaunch& a, const RenderCfg& cfg, hipStream_
     const int64_t n_logical = (tiles + kWavesPerBlock - 1) / kWavesPerBlock;
     const int64_t per_xcd = (n_logical + 7) / 8;
     const dim3 grid((unsigned)(per_xcd * 8)), block(64 * kWavesPerBlock);
-    hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(1), 0, s, a.exact_count);
     const int64_t n_cams = (int64_t)a.n_env * a.n_cam;
-    hipLaunchKernelGGL(k_cam_prep, dim3((unsigned)std::min<int64_t>((n_cams + 255) / 256, 4096)),
-                       dim3(256), 0, s, a, n_cams);
+    // one camera per lane, 64-lane blocks: a short FP64 chain per camera, so
+    // spread the cameras over many compute units; it also resets the exact-pass
+    // counters
+    hipLaunchKernelGGL(k_cam_prep, dim3((unsigned)std::min<int64_t>((n_cams + 63) / 64, 16384)),
+                       dim3(64), 0, s, a, n_cams, a.exact_count);
     if (a.ev_begin) hipEventRecord(a.ev_begin, s);
     if (a.counts) {
         switch (cfg_mode(cfg)) {
@@ -1244,8 +1247,8 @@ hipError_t launch_render_batched(const RenderLaunch& a, const RenderCfg& cfg, ui
                                  hipStream_t s) {
     TileCfg c{cfg.tile_w, cfg.tile_h, cfg.rays_per_lane};
     hipLaunchKernelGGL(k_batch_prep, dim3(1), dim3(1024), 0, s, a, c, tile_start, queues, status);
-    hipLaunchKernelGGL(k_cam_prep, dim3((unsigned)std::min<int64_t>((a.n_desc + 255) / 256, 4096)),
-                       dim3(256), 0, s, a, (int64_t)a.n_desc);
+    hipLaunchKernelGGL(k_cam_prep, dim3((unsigned)std::min<int64_t>((a.n_desc + 63) / 64, 16384)),
+                       dim3(64), 0, s, a, (int64_t)a.n_desc, (uint32_t*)nullptr);
     if (a.ev_begin) hipEventRecord(a.ev_begin, s);
     const dim3 block(64 * kWavesPerBlock);
     if (cfg.persistent) {
