@@ -1138,7 +1138,8 @@ __global__ void __launch_bounds__(64) k_render_exact(RenderLaunch a, const uint3
 // vertical ray per grid point, from base_z + top down to `depth`, against the
 // terrain hierarchy; every triangle test is the FP64 watertight test (closed
 // triangles), so a point on a shared edge or vertex finds its surface.
-__global__ void __launch_bounds__(kLanes) k_heightmap(HeightLaunch hl) {
+__global__ void __launch_bounds__(kLanes) __attribute__((amdgpu_waves_per_eu(8, 8)))
+k_heightmap(HeightLaunch hl) {
     __shared__ uint32_t s_stack[kLanes * kStack];
     const int64_t n = (int64_t)hl.n_env * hl.nx * hl.ny;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
