@@ -522,11 +522,26 @@ def bench_serving(sc, w_main, capacity_mrays, duration_s=6.0, stream_s=60.0):
     base = run(2000.0, stream_s, n_streams=1, max_batch_rays=1)
     base["load"] = "2000 req/s, one request per launch on one stream (plain per-request)"
     print(f"[bench] serving {base}", file=sys.stderr, flush=True)
+    # the plain per-request form at 80% load, and both forms past capacity,
+    # where the served rate is each form's capacity
+    base80 = run(0.8 * cap_rps, duration_s, n_streams=1, max_batch_rays=1)
+    base80["load"] = "80% of capacity, one request per launch on one stream"
+    print(f"[bench] serving {base80}", file=sys.stderr, flush=True)
+    over = run(1.3 * cap_rps, duration_s)
+    over["load"] = "130% of the plain renderer's measured capacity"
+    print(f"[bench] serving {over}", file=sys.stderr, flush=True)
+    over_plain = run(1.3 * cap_rps, duration_s, n_streams=1, max_batch_rays=1)
+    over_plain["load"] = "130% of capacity, one request per launch on one stream"
+    print(f"[bench] serving {over_plain}", file=sys.stderr, flush=True)
     return {"mean_rays_per_request": round(mean_rays), "runs": runs, "plain_per_request": base,
+            "plain_per_request_80pct": base80, "overload": over, "overload_plain_per_request": over_plain,
             "speedup_served_vs_plain_per_request": round(lit["served_mrays_s"] /
                                                          max(base["served_mrays_s"], 1e-9), 3),
+            "speedup_served_vs_plain_at_overload": round(over["served_mrays_s"] /
+                                                         max(over_plain["served_mrays_s"], 1e-9), 3),
             "p50_plain_over_served": round(base["p50_ms"] / max(lit["p50_ms"], 1e-9), 2),
-            "p99_plain_over_served": round(base["p99_ms"] / max(lit["p99_ms"], 1e-9), 2)}
+            "p99_plain_over_served": round(base["p99_ms"] / max(lit["p99_ms"], 1e-9), 2),
+            "p99_plain_over_served_at_80pct": round(base80["p99_ms"] / max(runs[1]["p99_ms"], 1e-9), 2)}
 
 
 def main():
