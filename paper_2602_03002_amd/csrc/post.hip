@@ -43,7 +43,8 @@ __device__ __forceinline__ int side_mask_cols(const PostLaunch& a, int env, int 
     const float* pk = a.mask_p[type];
     if (u < pk[0]) return 0;
     const int mode = u < pk[0] + pk[1] ? 0 : 1;
-    return (int)floorf(__fmul_rn(a.mask_frac[mode], (float)width) + 0.5f);
+    const float band = a.mask_frac[mode] * (float)width;
+    return (int)floorf(band + 0.5f);
 }
 
 // The draw of pixel `pix` of camera `uid` at this step.
