@@ -203,3 +203,39 @@ def test_render_rejects_bad_arguments_and_leaves_outputs():
     assert call() == 0
     torch.cuda.synchronize()
     assert not torch.all(depth == 123.0)
+
+
+def test_largest_width_and_many_envs():
+    """The largest image width (65535, three rows: a ragged tile row) and
+    16,384 environments (a grid far beyond one block per compute unit, an
+    uneven last run per XCD), sampled against the oracle."""
+    say("[edge] width 65535 and 16384 envs")
+    w = sg.robot_scene(2, 1, 4.0, 1, 16, 12, steps=1, label="widest")
+    W, H = 65535, 3
+    w["intr"] = np.array([[sg.intrinsics_from_fov(W, H, 120.0, 0.01)]], np.float32)
+    w["W"], w["H"] = W, H
+    dd, ii, tt = _render_only(w)
+    rays = np.sort(np.random.default_rng(3).choice(W * H, 300, replace=False))
+    ref = oracle.render(w["terrain"], w["link_tri"], w["link_off"], w["link_pos"][0],
+                        w["link_quat"][0], w["cam_pos"], w["cam_quat"], w["intr"], W, H, w["far"],
+                        rays=rays)
+    assert_parity(dd.ravel()[rays], ii.ravel()[rays], tt.ravel()[rays], ref, w["far"], label="width 65535")
+
+    w = sg.robot_scene(2, 128, 0.06, 1, 8, 8, steps=1, label="manyenvs")
+    assert w["E"] == 16384
+    dd, ii, tt = _render_only(w)
+    rays = np.sort(np.random.default_rng(4).choice(dd.size, 400, replace=False))
+    ref = oracle.render(w["terrain"], w["link_tri"], w["link_off"], w["link_pos"][0],
+                        w["link_quat"][0], w["cam_pos"], w["cam_quat"], w["intr"], 8, 8, w["far"],
+                        rays=rays)
+    assert_parity(dd.ravel()[rays], ii.ravel()[rays], tt.ravel()[rays], ref, w["far"], label="16384 envs")
+
+
+def _render_only(w):
+    m = rc()
+    sc = m.Scene(dev(w["terrain"]))
+    sc.set_robot(dev(w["link_tri"]), w["link_off"].tolist())
+    d, i, t = sc.render(dev(w["cam_pos"]), dev(w["cam_quat"]), dev(w["intr"]), w["W"], w["H"],
+                        w["far"], link_pos=dev(w["link_pos"][0]), link_quat=dev(w["link_quat"][0]))
+    torch.cuda.synchronize()
+    return d.cpu().numpy(), i.cpu().numpy(), t.cpu().numpy()
