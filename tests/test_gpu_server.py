@@ -80,3 +80,36 @@ def test_result_same_alone_and_in_mix():
         torch.cuda.synchronize()
         assert np.array_equal(d.cpu().numpy(), alone[k][0])
         assert np.array_equal(i.cpu().numpy(), alone[k][1])
+
+
+def test_memory_admission_waits_for_space():
+    """An output arena that holds the largest request only: requests queue
+    for memory in arrival order (the large one waits for the first one's
+    release, the next waits behind it) and every result equals the request
+    rendered alone."""
+    import paper_2602_03002_amd as m
+    print("[server] admission by memory with an arena of one large request", flush=True)
+    w = sg.robot_scene(2, 3, 3.0, 4, 16, 12, steps=1, label="serve")
+    sc = m.Scene(dev(w["terrain"]))
+    sc.set_robot(dev(w["link_tri"]), w["link_off"].tolist())
+    reqs = requests_for(w)
+    alone = {}
+    for k in range(3):
+        srv = m.Server(sc, n_streams=1, out_pixels=1 << 22, scratch_bytes=1 << 27)
+        alone.update(run(srv, reqs, [k]))
+        srv.close()
+    big = max(q["n_env"] * q["n_cam"] * q["width"] * q["height"] for q in reqs)
+    srv = m.Server(sc, n_streams=4, max_batch_rays=1 << 22, out_pixels=big, scratch_bytes=1 << 27)
+    got = run(srv, reqs, [0, 2, 1])
+    st = srv.stats()
+    srv.close()
+    assert st["completed"] == 3 and st["rejected"] == 0
+    for k in range(3):
+        for x, y in zip(alone[k], got[k]):
+            assert np.array_equal(x, y), f"request {k} differs under memory pressure"
+    # a request larger than the arena is refused at submission
+    srv = m.Server(sc, n_streams=1, out_pixels=big - 1, scratch_bytes=1 << 27)
+    with pytest.raises(m.RcError):
+        srv.submit(0.0, **reqs[2])
+    assert srv.stats()["rejected"] == 1
+    srv.close()
