@@ -248,3 +248,32 @@ def test_batched_4096_uneven_sampled():
                       link_quat=lq[e:e + 1])
         for x, y in zip(host(r), got):
             assert np.array_equal(x.ravel(), y[o:o + W * H])
+
+
+def test_batched_range_depth():
+    """Range depth (distance along the ray) in the batched form: equal to each
+    camera rendered alone in range mode, and to the oracle's range depth."""
+    say("[batched] range depth")
+    w, desc, n_pix = uneven_scene(label="range")
+    sc = make_scene(w)
+    d = dev(desc.view(np.uint8))
+    b = sc.batch(d, n_pix, 106, 60, w["far"], link_pos=dev(w["link_pos"][0]),
+                 link_quat=dev(w["link_quat"][0]), depth_mode=1)
+    got = host(b.render())
+    rng = np.random.default_rng(8)
+    for k in (0, len(desc) // 2, len(desc) - 1):
+        dk = desc[k]
+        e, W, H, o = int(dk["env"]), int(dk["width"]), int(dk["height"]), int(dk["out_offset"])
+        r = sc.render(dev(dk["pos"].reshape(1, 1, 3)), dev(dk["quat"].reshape(1, 1, 4)),
+                      dev(dk["intr"].reshape(1, 1, 4)), W, H, w["far"],
+                      link_pos=dev(w["link_pos"][0][e:e + 1]), link_quat=dev(w["link_quat"][0][e:e + 1]),
+                      depth_mode=1)
+        for x, y in zip(host(r), got):
+            assert np.array_equal(x.ravel(), y[o:o + W * H])
+        rays = np.sort(rng.choice(W * H, size=min(150, W * H), replace=False))
+        oref = oracle.render(w["terrain"], w["link_tri"], w["link_off"], w["link_pos"][0][e:e + 1],
+                             w["link_quat"][0][e:e + 1], dk["pos"].reshape(1, 1, 3),
+                             dk["quat"].reshape(1, 1, 4), dk["intr"].reshape(1, 1, 4), W, H, w["far"],
+                             depth_mode=1, rays=rays)
+        assert_parity(got[0][o + rays], got[1][o + rays], got[2][o + rays], oref, w["far"],
+                      label=f"batched range camera {k}")
