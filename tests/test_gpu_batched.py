@@ -277,3 +277,32 @@ def test_batched_range_depth():
                              depth_mode=1, rays=rays)
         assert_parity(got[0][o + rays], got[1][o + rays], got[2][o + rays], oref, w["far"],
                       label=f"batched range camera {k}")
+
+
+def test_batched_terrain_only_scene():
+    """A scene without robot links (terrain only): cameras of different sizes
+    in one batched launch equal each camera rendered alone, and the oracle."""
+    say("[batched] terrain-only scene")
+    w = sg.small_plain_case()
+    sc = rc().Scene(dev(w["terrain"]))
+    rows, off = [], 0
+    for k, (W, H) in enumerate(((32, 24), (17, 13), (64, 48))):
+        K = sg.intrinsics_from_fov(W, H, 87.0, 58.0)
+        rows.append((0, W, H, off, k, w["cam_pos"][0, 0], w["cam_quat"][0, 0], K))
+        off += W * H
+    desc = np.array(rows, dtype=sg.CAM_DESC)
+    b = sc.batch(dev(desc.view(np.uint8)), off, 64, 48, w["far"])
+    got = host(b.render())
+    assert b.status()[0] == 0
+    none3 = np.zeros((0, 3, 3), np.float32)
+    for dk in desc:
+        W, H, o = int(dk["width"]), int(dk["height"]), int(dk["out_offset"])
+        r = sc.render(dev(dk["pos"].reshape(1, 1, 3)), dev(dk["quat"].reshape(1, 1, 4)),
+                      dev(dk["intr"].reshape(1, 1, 4)), W, H, w["far"])
+        for x, y in zip(host(r), got):
+            assert np.array_equal(x.ravel(), y[o:o + W * H])
+        oref = oracle.render(w["terrain"], none3, np.zeros(1, np.int64), np.zeros((1, 0, 3), np.float32),
+                             np.zeros((1, 0, 4), np.float32), dk["pos"].reshape(1, 1, 3),
+                             dk["quat"].reshape(1, 1, 4), dk["intr"].reshape(1, 1, 4), W, H, w["far"])
+        assert_parity(got[0][o:o + W * H], got[1][o:o + W * H], got[2][o:o + W * H], oref, w["far"],
+                      label=f"terrain-only batched {W}x{H}")
