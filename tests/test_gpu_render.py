@@ -287,6 +287,29 @@ def test_post_matches_oracle(s0, with_uid, hw):
     assert np.max(np.abs(out - ro)) <= 1e-5
 
 
+def test_post_reset_starts_a_new_sequence():
+    """After rc_post_reset the next step starts a new sequence: frames captured
+    before the reset are never shown (the oracle started at that step)."""
+    say("[post] reset between two sequences")
+    m = rc()
+    depth, inst = sg.synthetic_frames(2, 2, 12, 16, 8)
+    kw = dict(seed=99, sigma_abs=0.01, p_drop=0.05, near=0.05, far=3.0, lat_min=1, lat_max=3)
+    post = m.Post(2, 2, 12, 16, 3)
+    p = m.post_params(**kw)
+    for s in range(4):  # first sequence, steps 0..3
+        post.process(dev(depth[s]), dev(inst[s]), p, s)
+    post.reset()
+    outs, drops = [], []
+    for k, s in enumerate(range(20, 24)):  # new sequence from step 20, frames 4..7
+        o, dr, _ = post.process(dev(depth[4 + k]), dev(inst[4 + k]), p, s)
+        torch.cuda.synchronize()
+        outs.append(o.cpu().numpy())
+        drops.append(dr.cpu().numpy())
+    ro, rd, _ = oracle.post(depth[4:], inst[4:], oracle.make_params(**kw), s0=20)
+    assert np.array_equal(np.stack(drops), rd)
+    assert np.max(np.abs(np.stack(outs) - ro)) <= 1e-5
+
+
 def test_post_identity_and_errors():
     say("[post] everything off; out-of-order step")
     depth, inst = sg.synthetic_frames(2, 1, 8, 8, 2)
