@@ -453,8 +453,8 @@ static int persistent_blocks(const RenderCfg& cfg) {
         else
             cus = 256;
     }
-    // one block = 4 wavefronts, `waves` resident wavefronts per SIMD, 4 SIMDs per CU
-    int b = cus * cfg.waves;
+    // `waves` resident wavefronts per SIMD, 4 SIMDs per CU, kWavesPerBlock per block
+    int b = cus * 4 * cfg.waves / kWavesPerBlock;
     return (b + 7) / 8 * 8;
 }
 

@@ -31,7 +31,6 @@ namespace rc {
 
 namespace {
 
-constexpr int kWavesPerBlock = 4;
 constexpr int kChunk = 8;  // tiles a wavefront of the batched launch takes at a time
 
 struct TileCfg {
@@ -906,14 +905,14 @@ __device__ __forceinline__ void plain_tile(const RenderLaunch& a, const TileCfg&
 // selects the body culling and terrain walk variants.  The autotuner picks
 // them and the tile schedule.
 template <int WAVES, int RPL, int MODE>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES, 8)))
+__global__ void __launch_bounds__(64 * kWavesPerBlock) __attribute__((amdgpu_waves_per_eu(WAVES, 8)))
 k_render(RenderLaunch a, TileCfg c, int64_t n_logical, int64_t per_xcd) {
     plain_tile<RPL, MODE, NoCount>(a, c, n_logical, per_xcd);
 }
 
 // The fast pass with per-ray work counters (diagnostic render).
 template <int MODE>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8)))
+__global__ void __launch_bounds__(64 * kWavesPerBlock) __attribute__((amdgpu_waves_per_eu(6, 8)))
 k_render_counts(RenderLaunch a, TileCfg c, int64_t n_logical, int64_t per_xcd) {
     plain_tile<1, MODE, RayCount>(a, c, n_logical, per_xcd);
 }
@@ -970,7 +969,7 @@ __global__ void __launch_bounds__(1024) k_batch_prep(RenderLaunch a, TileCfg c, 
 // the XCD that runs it) until the tiles run out; the tile table maps a tile
 // to its camera descriptor by binary search.
 template <int WAVES, int RPL, int MODE>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES, 8)))
+__global__ void __launch_bounds__(64 * kWavesPerBlock) __attribute__((amdgpu_waves_per_eu(WAVES, 8)))
 k_render_batched(RenderLaunch a, TileCfg c, const uint32_t* __restrict__ tile_start,
                  uint32_t* queue) {
     const int lane = threadIdx.x & 63;
@@ -1004,7 +1003,7 @@ k_render_batched(RenderLaunch a, TileCfg c, const uint32_t* __restrict__ tile_st
 // count exit at once.  No loop around the tile, so no state is carried
 // between tiles (the persistent form's loop costs registers).
 template <int WAVES, int RPL, int MODE>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES, 8)))
+__global__ void __launch_bounds__(64 * kWavesPerBlock) __attribute__((amdgpu_waves_per_eu(WAVES, 8)))
 k_render_flat(RenderLaunch a, TileCfg c, const uint32_t* __restrict__ tile_start, int tiles_per_cam,
               int64_t n_logical, int64_t per_xcd) {
     const int64_t bid = blockIdx.x;
