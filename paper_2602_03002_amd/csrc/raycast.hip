@@ -879,14 +879,28 @@ __device__ __forceinline__ void cast_tile(const RenderLaunch& a, const TileCfg& 
 }
 
 // Fast pass over the plain [env][cam][H][W] layout, one wavefront tile.
+// XCD-aware order: hardware deals blocks round-robin over the 8 XCDs.  The
+// logical tiles go out in chunks of kXcdChunk consecutive tiles, chunk g to
+// XCD g mod 8, so neighbouring environments share terrain nodes in one XCD's
+// L2 while every XCD keeps a share of the whole launch to its end (192 tiles,
+// two environments' four 64x48 images: 2% faster than one contiguous run per
+// XCD; 24 tiles lose the L2 reuse).  Block bid of a grid of 8 * xcd_blocks(n)
+// blocks maps to logical tile xcd_logical(bid); those >= n do nothing.
+constexpr int64_t kXcdChunk = 192;
+
+__device__ __forceinline__ int64_t xcd_logical(int64_t bid) {
+    const int64_t j = bid >> 3;
+    return ((j / kXcdChunk) * 8 + (bid & 7)) * kXcdChunk + (j % kXcdChunk);
+}
+
+inline int64_t xcd_blocks(int64_t n_logical) {
+    return ((n_logical + 7) / 8 + kXcdChunk - 1) / kXcdChunk * kXcdChunk;
+}
+
 template <int RPL, int MODE, typename Cnt>
 __device__ __forceinline__ void plain_tile(const RenderLaunch& a, const TileCfg& c, int64_t n_logical,
                                            int64_t per_xcd) {
-    // XCD-aware order: hardware deals blocks round-robin over the 8 XCDs, so
-    // give each XCD a contiguous run of tiles (neighbouring environments share
-    // terrain nodes in that XCD's L2).
-    const int64_t bid = blockIdx.x;
-    const int64_t lb = (bid & 7) * per_xcd + (bid >> 3);
+    const int64_t lb = xcd_logical(blockIdx.x);
     if (lb >= n_logical) return;
     const int64_t tile = (int64_t)uni((int)(lb * kWavesPerBlock)) + uni(threadIdx.x >> 6);
     const int span_h = c.th * c.rpl;
@@ -1006,8 +1020,7 @@ template <int WAVES, int RPL, int MODE>
 __global__ void __launch_bounds__(64 * kWavesPerBlock) __attribute__((amdgpu_waves_per_eu(WAVES, 8)))
 k_render_flat(RenderLaunch a, TileCfg c, const uint32_t* __restrict__ tile_start, int tiles_per_cam,
               int64_t n_logical, int64_t per_xcd) {
-    const int64_t bid = blockIdx.x;
-    const int64_t lb = (bid & 7) * per_xcd + (bid >> 3);
+    const int64_t lb = xcd_logical(blockIdx.x);
     if (lb >= n_logical) return;
     const int64_t w = (int64_t)uni((int)(lb * kWavesPerBlock)) + uni(threadIdx.x >> 6);
     const int d = (int)(w / tiles_per_cam);
@@ -1207,7 +1220,7 @@ hipError_t launch_render(const RenderLaunch& a, const RenderCfg& cfg, hipStream_
     const int tiles_y = (a.height + span_h - 1) / span_h;
     const int64_t tiles = (int64_t)a.n_env * a.n_cam * tiles_x * tiles_y;
     const int64_t n_logical = (tiles + kWavesPerBlock - 1) / kWavesPerBlock;
-    const int64_t per_xcd = (n_logical + 7) / 8;
+    const int64_t per_xcd = xcd_blocks(n_logical);
     const dim3 grid((unsigned)(per_xcd * 8)), block(64 * kWavesPerBlock);
     const int64_t n_cams = (int64_t)a.n_env * a.n_cam;
     // one camera per lane, 64-lane blocks: a short FP64 chain per camera, so
@@ -1267,7 +1280,7 @@ hipError_t launch_render_batched(const RenderLaunch& a, const RenderCfg& cfg, ui
         const int tiles_per_cam = ((a.max_width + c.tw - 1) / c.tw) * ((a.max_height + span_h - 1) / span_h);
         const int64_t waves = (int64_t)a.n_desc * tiles_per_cam;
         const int64_t n_logical = (waves + kWavesPerBlock - 1) / kWavesPerBlock;
-        const int64_t per_xcd = (n_logical + 7) / 8;
+        const int64_t per_xcd = xcd_blocks(n_logical);
         const dim3 grid((unsigned)(per_xcd * 8));
         switch (variant(cfg, c.rpl)) {
 #define RC_FLAT(W, R, P)                                                                         \
