@@ -31,8 +31,13 @@
  *  - flags (ambiguous within FP32 resolution, counted and checked weakly):
  *    EDGE  some candidate at lambda <= lambda* + 1e-4 m has min barycentric
  *          in [-1e-6, 1e-6];
- *    FAR   |depth* - far| <= 1e-5 m;
+ *    FAR   a hit with |depth* - far| <= 1e-5 m, or a miss that passes a
+ *          surface in (far, far + 1e-5 m];
  *    TIE   another hit surface within 1e-5 m (depth) of the closest one.
+ *  - candidates (what a weak check may accept for a flagged ray): every
+ *    triangle with lambda > 0, lambda <= lambda* + 1e-4 m (lambda_far + 1e-4 m
+ *    for a miss), depth <= far + 1e-5 m and min barycentric >= -1e-6, the K
+ *    nearest in increasing depth (ties in input order: links, then terrain).
  *  - a triangle is closed: min barycentric >= -1e-12 counts as a hit (FP64
  *    rounding allowance; such rays are in the EDGE band anyway).
  */
@@ -206,7 +211,10 @@ static void render_ray(const scene_t* s, int64_t p, double* depth, int32_t* inst
     int f = 0, nc = 0;
     double lam_lim = (best.inst >= 0 ? best.lam : lam_far) + EDGE_DEPTH / m;
     for (int q = 0; q < K; ++q) { cand[2 * q] = -1; cand[2 * q + 1] = -1; cand_d[q] = NAN; }
-    if (fabs(dstar - s->far) <= FAR_BAND) f |= ORC_FAR;
+    /* the far band: the closest hit lies within FAR_BAND of the far plane, or a
+     * miss passes a surface just beyond it (hit or miss then hinges on FP32
+     * rounding); a miss with no surface near the far plane is not flagged */
+    if (best.inst >= 0 && fabs(dstar - s->far) <= FAR_BAND) f |= ORC_FAR;
     for (int k = 0; k <= s->n_links; ++k) {
         v3 ro, rd; const float* tris; int64_t nt;
         body_ray(s, env, k, o, d, &ro, &rd, &tris, &nt);
@@ -216,6 +224,7 @@ static void render_ray(const scene_t* s, int64_t p, double* depth, int32_t* inst
                 lam * m > s->far + FAR_BAND || mb < -EDGE_BARY)
                 continue;
             int is_best = (k == best.inst && (int)t == best.tri);
+            if (best.inst < 0 && lam * m > s->far) f |= ORC_FAR;
             if (mb <= EDGE_BARY) f |= ORC_EDGE;
             if (!is_best && mb >= -CLOSED_EPS && best.inst >= 0 && fabs(lam - best.lam) * m <= TIE_BAND)
                 f |= ORC_TIE;

@@ -171,6 +171,97 @@ def test_tie_rules():
     assert r["flags"][0] & oracle.FLAG_TIE
 
 
+def flat_tri(z, shift=-1.0):
+    """A horizontal right triangle at height z whose edge x = shift passes at
+    lateral distance |shift| from the vertical ray through (0, 0): at that ray
+    its barycentrics are (-shift/4, 1/4, 3/4 + shift/4), so the default
+    contains the ray well inside (1/4 from every edge)."""
+    s = np.float32(shift)
+    return [[s, -1, z], [s + 4, -1, z], [s, 3, z]]
+
+
+def test_candidate_list_contents_and_order():
+    """The band candidates (what the weak check may accept) of a hit ray are
+    exactly the closed-enough surfaces within 1e-4 m beyond the hit, nearest
+    first: the depths come from the triangles' heights (ray from z = 2 going
+    straight down), the ids from their input order."""
+    z_b = np.float32(-0.5e-4)   # 2.00005 m: inside the 1e-4 m band
+    z_c = np.float32(-2e-4)     # 2.0002 m: beyond it
+    z_e = np.float32(-0.3e-4)   # 2.00003 m, but min barycentric -5e-7 (edge band)
+    z_m = np.float32(-0.2e-4)   # 2.00002 m, min barycentric -2e-6 (outside the edge band)
+    tris = np.array([flat_tri(z_c),            # 0: too deep
+                     flat_tri(z_b),            # 1: candidate, second nearest
+                     flat_tri(z_m, 8e-6),      # 2: misses by more than the band
+                     flat_tri(0.0),            # 3: the hit
+                     flat_tri(z_e, 2e-6),      # 4: edge-band candidate
+                     flat_tri(3.0)],           # 5: behind the origin (lambda < 0)
+                    np.float32)
+    r = render_points(tris, [((0, 0, 2), (0, 0, -1))], far=10.0)
+    assert r["inst"][0] == 0 and r["tri"][0] == 3 and r["depth"][0] == pytest.approx(2.0, abs=1e-12)
+    cand, cd = r["cand"][0], r["cand_depth"][0]
+    got = [tuple(c) for c in cand if c[0] >= 0]
+    assert got == [(0, 3), (0, 4), (0, 1)]
+    np.testing.assert_allclose(cd[:3], [2.0, 2.0 - float(z_e), 2.0 - float(z_b)], rtol=0, atol=1e-12)
+    assert np.all(np.isnan(cd[3:])) and np.all(cand[3:] == -1)
+    # the edge-band candidate sets EDGE; no TIE (1e-5 m) and no FAR
+    assert r["flags"][0] == oracle.FLAG_EDGE
+    # without the edge-band triangle the ray is unflagged and keeps two candidates
+    r = render_points(tris[[0, 1, 2, 3, 5]], [((0, 0, 2), (0, 0, -1))], far=10.0)
+    assert r["flags"][0] == 0
+    assert [tuple(c) for c in r["cand"][0] if c[0] >= 0] == [(0, 3), (0, 1)]
+    # a candidate list holds the K nearest only
+    r = oracle.render(tris, np.zeros((0, 3, 3), np.float32), np.zeros(1, np.int64),
+                      np.zeros((1, 0, 3)), np.zeros((1, 0, 4)), np.float32([[[0, 0, 2]]]),
+                      np.float32([[look_quat((0, 0, -1))]]), np.float32([[[1, 1, .5, .5]]]),
+                      1, 1, 10.0, K=2)
+    assert [tuple(c) for c in r["cand"][0]] == [(0, 3), (0, 4)]
+
+
+def test_candidate_list_of_a_link_hit_lists_links_before_terrain():
+    """Equal depths: the link's candidate comes first (links precede the
+    terrain in the order of Algorithm 1's queries), and the pair is a TIE."""
+    A = flat_tri(0.0)
+    link = (np.array([A], np.float32), np.array([0, 1], np.int64),
+            np.zeros((1, 1, 3), np.float32), np.array([[[0, 0, 0, 1]]], np.float32))
+    r = render_points(np.array([A, flat_tri(np.float32(-0.5e-4))], np.float32),
+                      [((0, 0, 2), (0, 0, -1))], link=link)
+    assert r["inst"][0] == 0 and r["tri"][0] == 0
+    assert [tuple(c) for c in r["cand"][0] if c[0] >= 0] == [(0, 0), (1, 0), (1, 1)]
+    assert r["flags"][0] == oracle.FLAG_TIE
+
+
+@pytest.mark.parametrize("dz,hit,flag", [
+    (0.0, True, True),          # a hit exactly at the far plane counts and is in the band
+    (-0.5e-5, True, True),      # 0.5e-5 m before it: a hit, in the band
+    (+0.5e-5, False, True),     # 0.5e-5 m beyond it: a miss, in the band
+    (-2e-5, True, False),       # 2e-5 m before: a plain hit
+    (+2e-5, False, False),      # 2e-5 m beyond: a plain miss
+])
+def test_far_band_flag(dz, hit, flag):
+    far = 2.0
+    z = np.float32(-np.float32(dz))    # the ray goes down from z = 2: depth = 2 - z
+    # quaternion (1, 0, 0, 0): a half turn about x, so optical z is exactly -z
+    r = oracle.render(np.array([flat_tri(z)], np.float32), np.zeros((0, 3, 3), np.float32),
+                      np.zeros(1, np.int64), np.zeros((1, 0, 3)), np.zeros((1, 0, 4)),
+                      np.float32([[[0, 0, 2]]]), np.float32([[[1, 0, 0, 0]]]),
+                      np.float32([[[1, 1, .5, .5]]]), 1, 1, far)
+    depth = 2.0 - float(z)
+    assert (r["inst"][0] == 0) == hit
+    assert r["depth"][0] == (depth if hit else far)
+    assert bool(r["flags"][0] & oracle.FLAG_FAR) == flag
+    assert r["flags"][0] & ~oracle.FLAG_FAR == 0
+    # the band's surface is a candidate; a plain miss has none
+    cands = [tuple(c) for c in r["cand"][0] if c[0] >= 0]
+    assert cands == ([(0, 0)] if (hit or flag) else [])
+
+
+def test_far_band_not_set_for_a_miss_into_empty_space():
+    tri = np.array([flat_tri(0.0)], np.float32)
+    r = render_points(tri, [((0, 0, 2), (0, 0, 1))], far=3.0)   # looking up, away from it
+    assert r["inst"][0] == -1 and r["depth"][0] == 3.0 and r["flags"][0] == 0
+    assert np.all(r["cand"][0] == -1)
+
+
 def random_scene(seed, n_tri=40, E=2, C=2, W=9, H=7):
     rng = np.random.default_rng(seed)
     c = rng.uniform(-1, 1, (n_tri, 1, 3)) * [2, 2, 0.3] + [2.0, 0, 0]
