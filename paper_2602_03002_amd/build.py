@@ -1,7 +1,13 @@
-"""Compile the HIP sources in csrc/ for gfx950 into paper_2602_03002_amd/librc.so."""
+"""Compile the HIP sources in csrc/ for gfx950 into paper_2602_03002_amd/librc.so.
+
+Each source is compiled to its own object (in parallel; the device code of a
+file is self-contained, no relocatable device code), then linked once.
+"""
 import os
 import subprocess
 import sys
+import tempfile
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
@@ -10,7 +16,7 @@ SOURCES = ["api.hip", "blas_build.hip", "tlas_build.hip", "raycast.hip", "post.h
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
-    "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
+    "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
     # packed FP32 instructions stay disabled: they have given silently wrong
     # results on this hardware in some forms
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -18,17 +24,26 @@ FLAGS = [
 ]
 
 
-def build(verbose=False, extra=()):
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC] + FLAGS + list(extra) + ["-o", tmp] + srcs
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed")
-    os.replace(tmp, LIB)
+        raise RuntimeError("hipcc failed: " + " ".join(cmd))
+    return res
+
+
+def build(verbose=False, extra=()):
+    with tempfile.TemporaryDirectory(prefix="rc_build_") as tmpdir:
+        objs = [os.path.join(tmpdir, os.path.splitext(s)[0] + ".o") for s in SOURCES]
+        cmds = [[HIPCC] + FLAGS + list(extra) + ["-c", "-o", o, os.path.join(CSRC, s)]
+                for s, o in zip(SOURCES, objs)]
+        with ThreadPoolExecutor(max_workers=min(len(cmds), os.cpu_count() or 1)) as pool:
+            list(pool.map(lambda c: _run(c, verbose), cmds))
+        tmp = LIB + ".tmp"
+        _run([HIPCC, "--offload-arch=gfx950", "-fPIC", "-shared", "-o", tmp] + objs, verbose)
+        os.replace(tmp, LIB)
     return LIB
 
 
