@@ -164,6 +164,22 @@ static int lex_less(double lam, int inst, int tri, const hit_t* h) {
     return tri < h->tri;
 }
 
+/* A link pose that places the mesh nowhere: a non-finite position or
+ * quaternion component, or a zero quaternion.  Algorithm 1 assumes valid
+ * poses; the reading here is that such a link is absent from its environment
+ * (no triangle of it is ever hit), while the other links and the terrain are
+ * unaffected. */
+static int pose_ok(const float* t3, const float* q4) {
+    for (int i = 0; i < 3; ++i)
+        if (!isfinite(t3[i])) return 0;
+    double n2 = 0.0;
+    for (int i = 0; i < 4; ++i) {
+        if (!isfinite(q4[i])) return 0;
+        n2 += (double)q4[i] * q4[i];
+    }
+    return n2 > 0.0;
+}
+
 /* Body k of a ray: link k (k < B) in its local frame, or the terrain (k == B)
  * in the world frame.  Gives the ray in that frame and the triangle list. */
 static void body_ray(const scene_t* s, int env, int k, v3 o, v3 d, v3* ro, v3* rd,
@@ -171,6 +187,13 @@ static void body_ray(const scene_t* s, int env, int k, v3 o, v3 d, v3* ro, v3* r
     if (k < s->n_links) {
         double Rb[9];
         int64_t eb = (int64_t)env * s->n_links + k;
+        if (!pose_ok(s->link_pos + 3 * eb, s->link_quat + 4 * eb)) {
+            *ro = o;
+            *rd = d;
+            *tris = s->link_tri;
+            *ntri = 0;
+            return;
+        }
         quat_to_mat(s->link_quat + 4 * eb, Rb);
         v3 tb = v3f(s->link_pos + 3 * eb);
         *ro = mat_tmul(Rb, sub(o, tb));

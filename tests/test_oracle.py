@@ -336,6 +336,42 @@ def test_body_transform_matches_world_placement():
         assert np.array_equal(r_w["tri"][same], r_link["tri"][sl][same])
 
 
+@pytest.mark.parametrize("bad", ["nan_pos", "inf_pos", "nan_quat", "inf_quat", "zero_quat"])
+def test_link_with_non_finite_pose_is_absent(bad):
+    """A link whose pose places it nowhere (a non-finite component, a zero
+    quaternion) is absent: env 0 renders as the scene without that link
+    (instance ids of the later links and the terrain shift down by one), env 1
+    is unchanged."""
+    terr, link, lp, lq, cp, cq, intr, W, H = random_scene(5)
+    lp2 = np.concatenate([lp, lp + np.float32([0.1, 0.25, 0.0])], 1)
+    lq2 = np.concatenate([lq, lq[:, :, [1, 0, 3, 2]]], 1)
+    links = np.concatenate([link, link], 0)
+    off2 = np.array([0, link.shape[0], 2 * link.shape[0]], np.int64)
+    full = oracle.render(terr, links, off2, lp2, lq2, cp, cq, intr, W, H, 5.0)
+    assert (full["inst"] == 0).sum() > 5
+    bp, bq = lp2.copy(), lq2.copy()
+    if bad == "nan_pos":
+        bp[0, 0, 1] = np.nan
+    elif bad == "inf_pos":
+        bp[0, 0, 0] = np.inf
+    elif bad == "nan_quat":
+        bq[0, 0, 2] = np.nan
+    elif bad == "inf_quat":
+        bq[0, 0, 3] = -np.inf
+    else:
+        bq[0, 0] = 0.0
+    r = oracle.render(terr, links, off2, bp, bq, cp, cq, intr, W, H, 5.0)
+    off1 = np.array([0, link.shape[0]], np.int64)
+    one = oracle.render(terr, link, off1, lp2[:, 1:], lq2[:, 1:], cp, cq, intr, W, H, 5.0)
+    n0 = 2 * W * H  # env 0's rays come first
+    exp_inst = np.where(one["inst"][:n0] >= 0, one["inst"][:n0] + 1, -1)
+    assert np.array_equal(r["inst"][:n0], exp_inst)
+    assert np.array_equal(r["tri"][:n0], one["tri"][:n0])
+    assert np.array_equal(r["depth"][:n0], one["depth"][:n0])
+    for k in ("inst", "tri", "depth", "flags"):
+        assert np.array_equal(r[k][n0:], full[k][n0:])
+
+
 def test_quaternion_sign_invariance():
     terr, link, lp, lq, cp, cq, intr, W, H = random_scene(4)
     off = np.array([0, link.shape[0]], np.int64)
