@@ -20,6 +20,35 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 REF_VISITS = os.path.join(ROOT, "tests", "golden", "ref_visits_4096x2_64x48.json")
 
+# Vector-ALU issue peak: 256 CUs x 4 SIMDs x 16 lanes (64 lane operations per
+# CU-cycle) x 2.4 GHz, an FMA counted as one operation and no packed FP32 (the
+# 157.3 TFLOP/s vector figure counts both twice over).
+ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+
+# Algorithmic VALU lane operations of the ray-cast kernel: the minimal
+# instruction forms on gfx950 of each unit of work, priced per reference
+# traversal count (so a worse hierarchy or wasted issue cannot raise the
+# fraction).
+#   node: two child slab tests with the ray's octant known, each 6 FMA, near
+#         max3 + max, far min3 + min, one compare (11), plus the nearer-first
+#         choice (1)
+#   tri:  watertight shear test with the ray's axis permutation known: 9 vertex
+#         subtractions, 6 FMA (sheared x, y), 3 MUL (sheared z), edge functions
+#         3 x (MUL + FMA), sign test min3, max3, 2 compares, AND (5),
+#         determinant 2 ADD, distance numerator MUL + 2 FMA, RCP, MUL, bound
+#         test 2
+#   inst: ray to the link frame (3 SUB + 9 for the origin, 9 for the
+#         direction), slab set-up (3 RCP + 3 MUL), shear set-up (dominant axis
+#         4, RCP, 2 MUL)
+#   ray:  pixel ray from the camera basis (4 + 6 FP64 FMA, 6 conversions),
+#         slab (6) and shear (7) set-up, the hit test of the output (1)
+OPS_PER = {"ray": 30, "node": 23, "tri": 38, "inst": 34}
+
+
+def ops_per_ray(counts):
+    return (OPS_PER["ray"] + OPS_PER["node"] * counts["node"] + OPS_PER["tri"] * counts["tri"]
+            + OPS_PER["inst"] * counts["inst"])
+
 
 def bytes_per_ray():
     """Algorithmic bytes per ray of the ray-cast kernel, from reference visit
@@ -85,7 +114,8 @@ def measured_issue():
 
 
 def _oracle_rate(w, budget_s, seed):
-    """Rays per second of the oracle over growing random ray samples of step 0."""
+    """Rays per second of the oracle over growing random ray samples of step 0,
+    and the last (largest) sample with the oracle's answer for it."""
     import numpy as np
     import oracle
     total = w["E"] * w["C"] * w["H"] * w["W"]
@@ -96,13 +126,13 @@ def _oracle_rate(w, budget_s, seed):
     while True:
         rays = np.sort(rng.choice(total, size=n, replace=False))
         t0 = time.perf_counter()
-        oracle.render(w["terrain"], w["link_tri"], w["link_off"], w["link_pos"][0],
-                      w["link_quat"][0], w["cam_pos"], w["cam_quat"], w["intr"], w["W"], w["H"],
-                      w["far"], rays=rays)
+        ref = oracle.render(w["terrain"], w["link_tri"], w["link_off"], w["link_pos"][0],
+                            w["link_quat"][0], w["cam_pos"], w["cam_quat"], w["intr"], w["W"],
+                            w["H"], w["far"], rays=rays)
         elapsed += time.perf_counter() - t0
         done += n
         if elapsed > budget_s / 3:
-            return done, elapsed
+            return done, elapsed, rays, ref
         n *= 2
 
 
@@ -116,9 +146,10 @@ def _cpu_model():
     return None
 
 
-def cpu_baseline(w, budget_s=15.0, seed=5):
+def cpu_baseline(w, budget_s=30.0, seed=5):
     """The FP64 oracle timed on the host's cores over a bounded ray sample of
-    step 0, then on one core."""
+    step 0, then on one core.  Also returns the largest sample and the
+    oracle's answer for it (the bench's parity check reuses them)."""
     import oracle
     cores = os.cpu_count()
     try:
@@ -128,16 +159,35 @@ def cpu_baseline(w, budget_s=15.0, seed=5):
     omp = os.environ.get("OMP_NUM_THREADS")
     threads = min(int(omp), cores) if omp and omp.isdigit() else cores
     oracle.set_threads(threads)
-    done, elapsed = _oracle_rate(w, budget_s, seed)
+    done, elapsed, rays, ref = _oracle_rate(w, budget_s, seed)
     oracle.set_threads(1)
-    done1, elapsed1 = _oracle_rate(w, budget_s / 3, seed + 1)
+    done1, elapsed1, _, _ = _oracle_rate(w, budget_s / 4, seed + 1)
     oracle.set_threads(threads)
-    return {"value": done / elapsed / 1e6, "unit": "Mrays/s", "cores": threads, "kind": "oracle",
-            "sample": f"{done} random pixel rays of step 0 (all {w['terrain'].shape[0]} terrain "
-                      f"+ {w['link_tri'].shape[0]} link triangles each, FP64 brute force + band flags)",
-            "single_core_value": done1 / elapsed1 / 1e6, "single_core_sample": f"{done1} rays",
-            "cpu_model": _cpu_model(),
-            "full_step_s_extrapolated": round(w["E"] * w["C"] * w["H"] * w["W"] / (done / elapsed), 1)}
+    out = {"value": done / elapsed / 1e6, "unit": "Mrays/s", "cores": threads, "kind": "oracle",
+           "sample": f"{done} random pixel rays of step 0 in doubling batches (all "
+                     f"{w['terrain'].shape[0]} terrain + {w['link_tri'].shape[0]} link triangles "
+                     f"each, FP64 brute force + band flags), {elapsed:.1f} s",
+           "single_core_value": done1 / elapsed1 / 1e6,
+           "single_core_sample": f"{done1} rays, {elapsed1:.1f} s",
+           "cpu_model": _cpu_model(),
+           "full_step_s_extrapolated": round(w["E"] * w["C"] * w["H"] * w["W"] / (done / elapsed), 1)}
+    return out, rays, ref
+
+
+def parity_report(d, i, t, rays, ref, far):
+    """The GPU's step-0 render against the oracle on the CPU baseline's largest
+    sample: strict failures, id mismatches, the largest depth error of the
+    strictly checked rays, and the band counts apart (edge band: a candidate
+    within 1e-6 barycentric of an edge; tie band; far band)."""
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from parity import compare
+    r = compare(d.ravel()[rays].cpu().numpy(), i.ravel()[rays].cpu().numpy(),
+                t.ravel()[rays].cpu().numpy(), ref, far=far)
+    r.pop("bad_idx")
+    r["max_abs_dd_m"] = r.pop("max_depth_err")
+    r["sample"] = f"{len(rays)} rays of step 0 (the CPU baseline's largest sample)"
+    r["bar"] = "strict: |dd| <= 1e-4 m and bit-exact (inst, tri); banded: one of the oracle's band candidates"
+    return r
 
 
 def traversal_report(sc, kw, ref):
@@ -248,9 +298,73 @@ def bench_batched(sc, steps, warmup):
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / steps
 
+    # plain per-environment path: one rc_render per environment and image size
+    # (its cameras of that size), argument blocks built once, outputs packed
+    # like the batched form's
+    import ctypes
+    import paper_2602_03002_amd as rc
+    from paper_2602_03002_amd import rc as rcmod
+    L = rc.lib()
+    flat = tuple(torch.empty(n_pix, dtype=dt, device=dev)
+                 for dt in (torch.float32, torch.int32, torch.int32))
+    cp_all, cq_all, K_all = t(desc["pos"]), t(desc["quat"]), t(desc["intr"])
+    calls = []
+    order = np.lexsort((desc["width"], desc["env"]))
+    i0 = 0
+    while i0 < order.size:
+        e_, wd, hd = desc["env"][order[i0]], desc["width"][order[i0]], desc["height"][order[i0]]
+        i1 = i0
+        while (i1 < order.size and desc["env"][order[i1]] == e_ and desc["width"][order[i1]] == wd):
+            i1 += 1
+        sel = order[i0:i1]
+        k = sel.size
+        # the cameras of one call must be consecutive in the inputs and the output
+        cpk = cp_all[torch.from_numpy(sel).to(dev)].view(1, k, 3).contiguous()
+        cqk = cq_all[torch.from_numpy(sel).to(dev)].view(1, k, 4).contiguous()
+        Kk = K_all[torch.from_numpy(sel).to(dev)].view(1, k, 4).contiguous()
+        off = int(desc["out_offset"][sel[0]]) if k == 1 else None
+        outs = (tuple(f[off:off + k * wd * hd].view(1, k, hd, wd) for f in flat) if off is not None
+                else None)
+        a, outs, ws = sc._plain_args(cpk, cqk, Kk, int(wd), int(hd), w["far"],
+                                     lp[e_:e_ + 1], lq[e_:e_ + 1], rcmod.RC_DEPTH_PLANAR, outs, True)
+        calls.append((a, ws, (cpk, cqk, Kk, outs)))
+        i0 = i1
+
+    def per_env_step(k):
+        lp.copy_(lp_steps[k % 3])
+        lq.copy_(lq_steps[k % 3])
+        s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+        for a, ws, _ in calls:
+            rcmod.check(L.rc_render(sc.handle, ctypes.byref(a), ctypes.c_void_p(ws.ptr), ws.nbytes, s))
+
     ms_b = timed(batched_step)
     status, exact = b.status()
     ms_p = timed(plain_step)
+    print(f"[bench] batched: per-env path, {len(calls)} rc_render calls per step", file=sys.stderr,
+          flush=True)
+    steps_pe = max(2, min(steps, 5))
+    t0 = time.perf_counter()
+    per_env_step(0)
+    torch.cuda.synchronize()
+    for k in range(steps_pe):
+        per_env_step(k)
+    torch.cuda.synchronize()
+    ms_pe = (time.perf_counter() - t0) / (steps_pe + 1) * 1e3
+    # the same calls captured into one graph (launch overhead removed)
+    cg = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(cg, stream=side):
+            per_env_step(0)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+
+    def per_env_graph(k):
+        cg.replay()
+
+    ms_pg = timed(per_env_graph)
+    del cg
     g.close()
     return {"workload": f"{w['E']} envs, {desc.shape[0]} cameras (1-4 per env, sizes "
                         f"{sg.RES_SET}), {n_pix} rays per step, per-step poses",
@@ -259,7 +373,15 @@ def bench_batched(sc, steps, warmup):
             "schedule": cfg, "status": status, "exact_pass_rays": exact,
             "plain_grouped_ms_per_step": round(ms_p, 4),
             "plain_grouped_value": round(n_pix / (ms_p / 1e3) / 1e6, 1),
-            "speedup_vs_plain_grouped": round(ms_p / ms_b, 3)}
+            "speedup_vs_plain_grouped": round(ms_p / ms_b, 3),
+            "plain_per_env": {"calls_per_step": len(calls),
+                              "what": "one rc_render per environment and image size",
+                              "eager_ms_per_step": round(ms_pe, 3),
+                              "eager_value": round(n_pix / (ms_pe / 1e3) / 1e6, 1),
+                              "graph_ms_per_step": round(ms_pg, 3),
+                              "graph_value": round(n_pix / (ms_pg / 1e3) / 1e6, 1)},
+            "speedup_vs_plain_per_env_eager": round(ms_pe / ms_b, 2),
+            "speedup_vs_plain_per_env_graph": round(ms_pg / ms_b, 2)}
 
 
 def bench_table1(sc, w_main, frames=20, warmup=3):
@@ -519,29 +641,44 @@ def bench_serving(sc, w_main, capacity_mrays, duration_s=6.0, stream_s=60.0):
     lit["load"] = "2000 req/s (the stated stream)"
     runs.append(lit)
     print(f"[bench] serving {lit}", file=sys.stderr, flush=True)
-    base = run(2000.0, stream_s, n_streams=1, max_batch_rays=1)
-    base["load"] = "2000 req/s, one request per launch on one stream (plain per-request)"
-    print(f"[bench] serving {base}", file=sys.stderr, flush=True)
-    # the plain per-request form at 80% load, and both forms past capacity,
-    # where the served rate is each form's capacity
-    base80 = run(0.8 * cap_rps, duration_s, n_streams=1, max_batch_rays=1)
-    base80["load"] = "80% of capacity, one request per launch on one stream"
-    print(f"[bench] serving {base80}", file=sys.stderr, flush=True)
+    base_s = min(stream_s, 20.0)
+    # One request per launch on the same 16 streams: the plain per-request
+    # form with the same device concurrency, so the ratio to it is the gain of
+    # batching alone; the 1-stream form adds the gain of concurrency.
+    plain = {}
+    for streams in (16, 1):
+        for name, rate, secs in (("2000", 2000.0, base_s), ("80pct", 0.8 * cap_rps, duration_s),
+                                 ("130pct", 1.3 * cap_rps, duration_s)):
+            r = run(rate, secs, n_streams=streams, max_batch_rays=1)
+            r["load"] = (f"{name} load, one request per launch on {streams} stream"
+                         f"{'s' if streams > 1 else ''}")
+            plain[(streams, name)] = r
+            print(f"[bench] serving {r}", file=sys.stderr, flush=True)
     over = run(1.3 * cap_rps, duration_s)
     over["load"] = "130% of the plain renderer's measured capacity"
     print(f"[bench] serving {over}", file=sys.stderr, flush=True)
-    over_plain = run(1.3 * cap_rps, duration_s, n_streams=1, max_batch_rays=1)
-    over_plain["load"] = "130% of capacity, one request per launch on one stream"
-    print(f"[bench] serving {over_plain}", file=sys.stderr, flush=True)
-    return {"mean_rays_per_request": round(mean_rays), "runs": runs, "plain_per_request": base,
-            "plain_per_request_80pct": base80, "overload": over, "overload_plain_per_request": over_plain,
-            "speedup_served_vs_plain_per_request": round(lit["served_mrays_s"] /
-                                                         max(base["served_mrays_s"], 1e-9), 3),
-            "speedup_served_vs_plain_at_overload": round(over["served_mrays_s"] /
-                                                         max(over_plain["served_mrays_s"], 1e-9), 3),
-            "p50_plain_over_served": round(base["p50_ms"] / max(lit["p50_ms"], 1e-9), 2),
-            "p99_plain_over_served": round(base["p99_ms"] / max(lit["p99_ms"], 1e-9), 2),
-            "p99_plain_over_served_at_80pct": round(base80["p99_ms"] / max(runs[1]["p99_ms"], 1e-9), 2)}
+
+    def ratio(x, y):
+        return round(x / max(y, 1e-9), 3)
+
+    p16, p1 = plain[(16, "2000")], plain[(1, "2000")]
+    return {"mean_rays_per_request": round(mean_rays), "runs": runs, "overload": over,
+            "plain_per_request_16_streams": {k: plain[(16, k)] for k in ("2000", "80pct", "130pct")},
+            "plain_per_request_1_stream": {k: plain[(1, k)] for k in ("2000", "80pct", "130pct")},
+            "batching_gain": {
+                "what": "served form vs one request per launch, both on 16 streams",
+                "p50_at_2000": ratio(p16["p50_ms"], lit["p50_ms"]),
+                "p99_at_2000": ratio(p16["p99_ms"], lit["p99_ms"]),
+                "p99_at_80pct": ratio(plain[(16, "80pct")]["p99_ms"], runs[1]["p99_ms"]),
+                "served_throughput_at_130pct": ratio(over["served_mrays_s"],
+                                                     plain[(16, "130pct")]["served_mrays_s"])},
+            "concurrency_gain": {
+                "what": "one request per launch on 16 streams vs on 1 stream",
+                "p50_at_2000": ratio(p1["p50_ms"], p16["p50_ms"]),
+                "p99_at_2000": ratio(p1["p99_ms"], p16["p99_ms"]),
+                "p99_at_80pct": ratio(plain[(1, "80pct")]["p99_ms"], plain[(16, "80pct")]["p99_ms"]),
+                "served_throughput_at_130pct": ratio(plain[(16, "130pct")]["served_mrays_s"],
+                                                     plain[(1, "130pct")]["served_mrays_s"])}}
 
 
 def main():
@@ -663,27 +800,43 @@ def main():
     value = rays * args.steps / (gpu_ms / 1e3) / 1e6
 
     exact_rays = sc.exact_count(E, C, W, H)
+    # step 0 rendered with the timed schedule, for the parity check against the
+    # oracle's sample below
+    out0 = (torch.empty_like(depth), torch.empty_like(inst), torch.empty_like(tri))
+    sc.render(cp, cq, K, W, H, w["far"], link_pos=lp_all[0], link_quat=lq_all[0], out=out0)
+    torch.cuda.synchronize()
     bpr, ref = bytes_per_ray()
     copy_gbs = copy_bandwidth()
     roof = None
     if bpr is not None:
         r_ms = statistics.mean(fast_ms)
-        achieved = bpr * rays / (r_ms / 1e3) / 1e9
-        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
-                "kernel": "k_render (fast pass)", "bytes_per_ray": round(bpr, 1),
-                "kernel_ms": round(r_ms, 4), "copy_gbs": round(copy_gbs, 1),
-                "frac_of_copy": round(achieved / copy_gbs, 4)}
-        roof.update(measured_issue())
-        if "valu_insts_per_launch" in roof:
-            # VALU utilisation beside the FP32 vector peak (157.3 TFLOP/s counts an
-            # FMA as two and packed FP32, which this build leaves off); one wave64
-            # VALU instruction per CU-cycle is 256 x 64 x 2.4 GHz = 39.3 T lane-ops/s
-            lane_ops = roof.pop("valu_insts_per_launch") * 64 / (r_ms / 1e3) / 1e12
-            roof["valu"] = {"achieved_t_lane_ops_s": round(lane_ops, 2),
-                            "issue_peak_t_lane_ops_s": 39.32,
-                            "frac_of_issue_peak": round(lane_ops / 39.32, 4),
-                            "fp32_vector_peak_tflops": 157.3}
+        ops = ops_per_ray(ref["mean_counts"])
+        achieved = ops * rays / (r_ms / 1e3) / 1e12
+        hbm_alg = bpr * rays / (r_ms / 1e3) / 1e9
+        traffic = measured_traffic()
+        roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(ALU_PEAK_TOPS, 2),
+                "unit": "TOP/s", "frac": round(achieved / ALU_PEAK_TOPS, 4), "traffic": traffic,
+                "kernel": "k_render (fast pass)", "kernel_ms": round(r_ms, 4),
+                "ops_per_ray": round(ops, 1), "ops_per_unit": OPS_PER,
+                "op": "one lane of one VALU instruction (an FMA is one); peak 256 CUs x 64 lanes "
+                      "x 2.4 GHz, no packed FP32",
+                "hbm": {"measured_gbs": round(traffic / (r_ms / 1e3) / 1e9, 1) if traffic else None,
+                        "measured_frac": round(traffic / (r_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
+                        if traffic else None,
+                        "peak_gbs": HBM_PEAK_GBS, "copy_gbs": round(copy_gbs, 1),
+                        "algorithmic_bytes_per_ray": round(bpr, 1),
+                        "algorithmic_gbs": round(hbm_alg, 1),
+                        "note": "algorithmic bytes price every node record read as HBM traffic; "
+                                "most are served by L2 and the Infinity Cache, so their rate "
+                                "exceeds HBM's and bounds nothing; measured_frac is the HBM "
+                                "fraction"}}
+        iss = measured_issue()
+        if "valu_insts_per_launch" in iss:
+            issued = iss.pop("valu_insts_per_launch") * 64 / (r_ms / 1e3) / 1e12
+            roof["issued_t_lane_ops_s"] = round(issued, 2)
+            roof["issued_frac"] = round(issued / ALU_PEAK_TOPS, 4)
+            roof["algorithmic_over_issued"] = round(achieved / issued, 4)
+        roof.update(iss)
     # bytes a step cannot avoid: the scene read once, top levels written and
     # read, poses, render outputs, sensor-model traffic
     lay = sc.bvh_layout(-1)
@@ -702,7 +855,11 @@ def main():
     table1 = None if args.no_table1 else bench_table1(sc, w)
     randomised = None if args.no_randomised else bench_randomised(sc, w, ms_per_step)
     heightmap = None if args.no_heightmap else bench_heightmap(sc, w)
-    cpu = None if args.no_cpu_baseline else cpu_baseline(w)
+    cpu, parity = None, None
+    if not args.no_cpu_baseline:
+        cpu, s_rays, s_ref = cpu_baseline(w)
+        parity = parity_report(*out0, s_rays, s_ref, w["far"])
+        print(f"[bench] parity {parity}", file=sys.stderr, flush=True)
     out = {
         "metric": "depth Mrays/s at 4096 envs x 2 cams 64x48 vs plain; p50/p99 request latency",
         "value": round(value, 1), "unit": "Mrays/s", "n_gpus": 1, "steps": args.steps,
@@ -718,7 +875,7 @@ def main():
                    "compulsory_bytes_per_step": int(compulsory),
                    "compulsory_frac": round(compulsory_frac, 4),
                    "exact_pass_rays_last_step": exact_rays, "schedule": tuned},
-        "roofline": roof, "cpu_baseline": cpu, "traversal": trav, "batched": batched,
+        "roofline": roof, "cpu_baseline": cpu, "parity": parity, "traversal": trav, "batched": batched,
         "serving": serving, "table1": table1, "randomised": randomised, "heightmap": heightmap,
     }
     print(json.dumps(out), flush=True)

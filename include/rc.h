@@ -23,6 +23,13 @@
  *    anything; an error leaves outputs untouched.  No C++ exception crosses
  *    this interface.  rc_last_error() gives the text of the last error of
  *    the calling thread.
+ *  - Threads: a scene's meshes and hierarchies are read-only after
+ *    creation, and renders on different streams with their own outputs and
+ *    workspaces may run concurrently from several threads.  The one mutable
+ *    part of a scene is its pair of launch schedules (rc_set_render_config,
+ *    rc_autotune), each stored as one word: a render reads a whole schedule,
+ *    old or new, never a mix.  rc_robot_meshes and rc_scene_destroy must not
+ *    overlap any other call on the same scene.
  *  - Frames: quaternions are (x, y, z, w) and rotate local vectors to world;
  *    they are normalised before use.  A camera's optical frame has x right,
  *    y down, z forward.  Intrinsics are (fx, fy, cx, cy) in pixels; pixel
@@ -282,7 +289,10 @@ rc_status rc_autotune(rc_scene* scene, const rc_render_args* plain, const rc_bat
                       rc_render_config* best, float* best_ms);
 
 /* ---------------------------------------------------------------------
- * Graph capture of the batched launch.
+ * Graph capture of the batched launch.  Sec. 3.2.2 replays its ray-casting
+ * kernel from a captured graph to cut launch overhead across many
+ * environments; here the whole batched render is captured once and
+ * replayed per step.
  * ------------------------------------------------------------------- */
 
 typedef struct rc_graph rc_graph;
@@ -364,6 +374,14 @@ rc_status rc_server_create_simulated(const rc_server_config* cfg, size_t arena_b
  * pointers must stay valid until the request's result is released.  Errors:
  * INVALID_ARG, WORKSPACE (the request can never fit the arena). */
 rc_status rc_server_submit(rc_server* srv, const rc_request* req, double now_s, int64_t* id);
+
+/* Failure injection for testing a caller's error handling: the next
+ * n_batches batches whose device work completes are reported as failed
+ * (status RC_ERR_DEVICE on each of their requests, rc_last_error names the
+ * injection) although the device did its work.  Nothing else changes: the
+ * batch's memory is released as for any finished batch, and the resident
+ * scene and later requests are unaffected.  n_batches = 0 cancels it. */
+rc_status rc_server_fail_next(rc_server* server, int32_t n_batches);
 
 /* Advance the server at time now_s: collect finished batches (non-blocking
  * event queries), then start new batches on free streams from the queue
@@ -463,6 +481,19 @@ rc_status rc_postprocess(rc_post* post, const float* depth_in, const int32_t* in
 rc_status rc_post_size_packed(int64_t n_pixels, int32_t max_latency, size_t* ws_bytes);
 rc_status rc_post_create_packed(int64_t n_pixels, int32_t max_latency, void* ws, size_t ws_bytes,
                                 rc_post** out);
+
+/* rc_postprocess that also writes, for checking, the raw Philox4x32-10 words
+ * of every pixel's draw at this step into words_out (device, 16-byte
+ * aligned, uint32 [n_env][n_cam][height][width][4]): w0 decides dropout, w1
+ * and w2 feed Box-Muller, w3 the side-mask fill.  The words come from the
+ * same code that computes the outputs, so they can be compared bit for bit
+ * with an independent Philox (Salmon et al., SC'11) at the documented
+ * counters; the outputs equal rc_postprocess's.  Errors as rc_postprocess,
+ * plus INVALID_ARG for a NULL or misaligned words_out. */
+rc_status rc_postprocess_words(rc_post* post, const float* depth_in, const int32_t* inst_in,
+                               const rc_post_params* params, uint64_t step, const uint32_t* cam_uid,
+                               float* depth_out, uint8_t* drop_out, uint8_t* lat_out,
+                               uint32_t* words_out, rc_stream stream);
 
 /* rc_postprocess over a batch: pixel p of camera d is packed at
  * desc[d].out_offset + p and uses desc[d].cam_uid; lat_out is [n_desc]. */

@@ -12,6 +12,8 @@ A triangle of zero area (edge vectors with an all-zero FP64 cross product)
 is met by no ray: it keeps its Morton code, but its leaf box is empty for
 the unions, and an empty child box is stored as the far point.
 """
+import math
+
 import numpy as np
 
 PAD_REL = np.float32(2.0 ** -20)
@@ -185,3 +187,133 @@ def build(tri):
             p = parent[p]
         depth[i] = d
     return dict(keys=skeys, tri_id=order, records=rec, depth=int(depth.max()))
+
+
+# ---------------------------------------------------------------------------
+# Per-environment top level over the link instances (rebuilt every step)
+# ---------------------------------------------------------------------------
+
+INST_PAD_REL = np.float32(2.0 ** -20)
+INST_PAD_ABS = np.float32(1e-4)
+
+
+def _spread10(v):
+    x = int(v) & 0x3FF
+    x = (x | (x << 16)) & 0x030000FF
+    x = (x | (x << 8)) & 0x0300F00F
+    x = (x | (x << 4)) & 0x030C30C3
+    x = (x | (x << 2)) & 0x09249249
+    return x
+
+
+def _f(x):
+    return np.float32(x)
+
+
+def instance(pos, quat, root):
+    """Transform (R^T row-major, t) and padded world box (lo.x, hi.x, ...) of
+    one link instance, or None for a pose that places the link nowhere (a
+    non-finite component or a zero quaternion).  The rotation is evaluated in
+    FP64 and rounded once to FP32; every other step is one FP32 operation in
+    the order written."""
+    q64 = [float(np.float32(v)) for v in quat]
+    t = [_f(v) for v in pos]
+    with np.errstate(over="ignore", invalid="ignore"):
+        nn = math.sqrt(((q64[0] * q64[0] + q64[1] * q64[1]) + q64[2] * q64[2]) + q64[3] * q64[3]) \
+            if all(math.isfinite(v) for v in q64) else float("nan")
+    if not (all(np.isfinite(t)) and nn > 0 and math.isfinite(nn)):
+        return None
+    qx, qy, qz, qw = (v / nn for v in q64)
+    R = [_f(1.0 - 2.0 * (qy * qy + qz * qz)), _f(2.0 * (qx * qy - qz * qw)), _f(2.0 * (qx * qz + qy * qw)),
+         _f(2.0 * (qx * qy + qz * qw)), _f(1.0 - 2.0 * (qx * qx + qz * qz)), _f(2.0 * (qy * qz - qx * qw)),
+         _f(2.0 * (qx * qz - qy * qw)), _f(2.0 * (qy * qz + qx * qw)), _f(1.0 - 2.0 * (qx * qx + qy * qy))]
+    one, two, half = _f(1), _f(2), _f(0.5)
+    m = [R[3 * c + r] for r in range(3) for c in range(3)]
+    box, cw = [], []
+    for a in range(3):
+        c, h = _f(0), _f(0)
+        for k in range(3):
+            lc = (_f(root[2 * k]) + _f(root[2 * k + 1])) * half
+            lh = (_f(root[2 * k + 1]) - _f(root[2 * k])) * half
+            c = c + R[3 * a + k] * lc
+            h = h + abs(R[3 * a + k]) * lh
+        w = c + t[a]
+        pad = abs(w) * INST_PAD_REL + INST_PAD_ABS
+        box += [(w - h) - pad, (w + h) + pad]
+        cw.append(w)
+    return np.array(m + t, np.float32), np.array(box, np.float32), np.array(cw, np.float32)
+
+
+def tlas(link_pos, link_quat, root):
+    """Top level of one environment: link_pos [B, 3], link_quat [B, 4] (x, y,
+    z, w), root [B, 6] padded local root boxes of the link meshes.  Returns
+    (xf [B, 12] f32: R^T row-major then t; records [max(B - 1, 1), 16] f32
+    with the int32 refs in the last four words).  Instance boxes come from the
+    local box's centre and half extents under the pose, padded outward; keys
+    are 30-bit Morton codes of the box centres quantised per axis over the
+    environment's centre bounds, ranked by (key, instance); the hierarchy is
+    Karras's over the ranked keys, a node's box the union of its leaf range.
+    An absent instance (see instance()) gets the identity rotation, t at the
+    far point, a box that is the far point, and the largest key."""
+    B = len(link_pos)
+    xf = np.zeros((B, 12), np.float32)
+    box = np.zeros((B, 6), np.float32)
+    cw = np.zeros((B, 3), np.float32)
+    ok = np.zeros(B, bool)
+    for b in range(B):
+        r = instance(link_pos[b], link_quat[b], root[b])
+        if r is None:
+            xf[b] = [1, 0, 0, 0, 1, 0, 0, 0, 1, FAR_POINT, FAR_POINT, FAR_POINT]
+            box[b] = FAR_POINT
+        else:
+            xf[b], box[b], cw[b] = r
+            ok[b] = True
+    m = max(B - 1, 1)
+    rec = np.zeros((m, 16), np.float32)
+    ints = rec.view(np.int32)
+    if B == 1:
+        rec[0, 0:6] = box[0]
+        rec[0, 6:12] = FAR_POINT
+        ints[0, 12:16] = [~0, ~0, -1, -1]
+        return xf, rec
+    keys = np.full(B, 0xFFFFFFFF, np.uint64)
+    if ok.any():
+        cmin, cmax = cw[ok].min(0), cw[ok].max(0)
+        for b in np.nonzero(ok)[0]:
+            q = []
+            for a in range(3):
+                ext = cmax[a] - cmin[a]
+                s = _f(1024) / ext if ext > 0 else _f(0)
+                f = min(max((cw[b, a] - cmin[a]) * s, _f(0)), _f(1023))
+                q.append(int(f))
+            keys[b] = (_spread10(q[0]) << 2) | (_spread10(q[1]) << 1) | _spread10(q[2])
+    order = np.lexsort((np.arange(B), keys))
+    # 30-bit keys in 64-bit words: every prefix length shifts by the same 32,
+    # so the hierarchy is the one over the 32-bit words
+    c0, c1, parent, sibling = karras(keys[order])
+    sbox = box[order]
+    for i in range(B - 1):
+        for h, c in enumerate((c0[i], c1[i])):
+            if c < 0:
+                rec[i, 6 * h:6 * h + 6] = sbox[~c]
+            else:
+                lo, hi = _leaf_range(c0, c1, c)
+                u = sbox[lo:hi + 1]
+                rec[i, 6 * h:6 * h + 6] = [u[:, 0].min(), u[:, 1].max(), u[:, 2].min(),
+                                           u[:, 3].max(), u[:, 4].min(), u[:, 5].max()]
+        ints[i, 12] = ~order[~c0[i]] if c0[i] < 0 else c0[i]
+        ints[i, 13] = ~order[~c1[i]] if c1[i] < 0 else c1[i]
+    ints[:, 14] = parent
+    # a leaf sibling is stored by its instance; the root has none (-1)
+    ints[:, 15] = [-1 if i == 0 else (~order[~c] if c < 0 else c) for i, c in enumerate(sibling)]
+    return xf, rec
+
+
+def _leaf_range(c0, c1, i):
+    """First and last sorted leaf below internal node i."""
+    lo, hi = i, i
+    while lo >= 0:
+        lo = c0[lo]
+    while hi >= 0:
+        hi = c1[hi]
+    return ~lo, ~hi

@@ -3,6 +3,7 @@
 // turns HIP failures into RC_ERR_DEVICE with a message for rc_last_error().
 #include "rc_internal.h"
 
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -18,8 +19,18 @@ struct rc_scene {
     size_t meta_off = 0;
     std::vector<rc::BvhLayout> links;
     std::vector<int32_t> link_depth;
-    rc::RenderCfg cfg;          // fast-pass schedule of rc_render (set by rc_autotune)
-    rc::RenderCfg cfg_batched;  // ... of rc_render_batched
+    // Fast-pass schedules of rc_render and rc_render_batched, packed into one
+    // word each: rc_autotune and rc_set_render_config may replace them while
+    // renders run on other threads, and each render reads one whole schedule.
+    std::atomic<uint64_t> cfg_word{rc::pack_cfg(rc::RenderCfg())};
+    std::atomic<uint64_t> cfg_batched_word{rc::pack_cfg(rc::RenderCfg())};
+    rc::RenderCfg cfg() const { return rc::unpack_cfg(cfg_word.load(std::memory_order_acquire)); }
+    rc::RenderCfg cfg_batched() const {
+        return rc::unpack_cfg(cfg_batched_word.load(std::memory_order_acquire));
+    }
+    void set_cfg(bool batched, const rc::RenderCfg& c) {
+        (batched ? cfg_batched_word : cfg_word).store(rc::pack_cfg(c), std::memory_order_release);
+    }
 };
 
 struct rc_graph {
@@ -338,7 +349,8 @@ static void set_cam_rand(RenderLaunch& L, const rc_cam_rand* r) {
 }
 
 static rc_status prep_plain(const rc_scene* scene, const rc_render_args* a, void* ws,
-                            size_t ws_bytes, RenderLaunch& L, const char* who) {
+                            size_t ws_bytes, RenderLaunch& L, const char* who,
+                            int64_t cap_rays = -1) {
     const std::string w(who);
     if (!scene || !a) return fail(RC_ERR_INVALID_ARG, w + ": NULL scene or args");
     if (!scene->ws) return fail(RC_ERR_STATE, w + ": scene has no terrain");
@@ -357,7 +369,8 @@ static rc_status prep_plain(const rc_scene* scene, const rc_render_args* a, void
         return fail(RC_ERR_INVALID_ARG, w + ": camera randomisation ranges must be finite and "
                                             ">= 0, dfov_deg < 90");
     const int64_t n_rays = (int64_t)a->n_env * a->n_cam * a->width * a->height;
-    const RenderWs W = render_layout(a->n_env, n_rays, scene->n_links, 0, (int64_t)a->n_env * a->n_cam);
+    const RenderWs W = render_layout(a->n_env, n_rays, scene->n_links, 0, (int64_t)a->n_env * a->n_cam,
+                                     cap_rays);
     if (!ws || ws_bytes < W.end || !aligned(ws))
         return fail(RC_ERR_WORKSPACE, w + ": workspace needs " + std::to_string(W.end) +
                                           " bytes, 256-byte aligned");
@@ -398,7 +411,7 @@ static hipError_t run_plain(const rc_scene* scene, const RenderLaunch& L, void* 
     hipError_t e = hipSuccess;
     if (scene->n_links > 0)
         e = launch_tlas_build(L.link_pos, L.link_quat, L.n_env, scene->n_links, L.link_meta,
-                              (Node*)ws, (InstXform*)L.xf, s);
+                              (Node*)ws, (InstXform*)L.xf, !cfg.bodies_flat, s);
     if (e == hipSuccess) e = launch_render(L, cfg, s);
     return e;
 }
@@ -408,7 +421,7 @@ rc_status rc_render(const rc_scene* scene, const rc_render_args* a, void* ws, si
     RenderLaunch L;
     rc_status st = prep_plain(scene, a, ws, ws_bytes, L, "rc_render");
     if (st != RC_OK) return st;
-    hipError_t e = run_plain(scene, L, ws, scene->cfg, (hipStream_t)stream);
+    hipError_t e = run_plain(scene, L, ws, scene->cfg(), (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "rc_render: launch");
     return RC_OK;
 }
@@ -421,7 +434,7 @@ rc_status rc_render_counts(const rc_scene* scene, const rc_render_args* a, uint3
     rc_status st = prep_plain(scene, a, ws, ws_bytes, L, "rc_render_counts");
     if (st != RC_OK) return st;
     L.counts = counts;
-    hipError_t e = run_plain(scene, L, ws, scene->cfg, (hipStream_t)stream);
+    hipError_t e = run_plain(scene, L, ws, scene->cfg(), (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "rc_render_counts: launch");
     return RC_OK;
 }
@@ -444,14 +457,18 @@ rc_status rc_render_batched_size(const rc_scene* scene, int32_t n_env, int32_t n
 }
 
 static int persistent_blocks(const RenderCfg& cfg) {
-    static int cus = 0;
-    if (cus == 0) {
-        int dev = 0, n = 0;
-        if (hipGetDevice(&dev) == hipSuccess &&
-            hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0)
-            cus = n;
-        else
-            cus = 256;
+    // compute units of the current device, asked once per device (a function-
+    // local array of atomics: concurrent first calls may both ask, and agree)
+    static std::atomic<int> cus_of[64];
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess && dev >= 0 && dev < 64) {
+        cus = cus_of[dev].load(std::memory_order_relaxed);
+        if (cus == 0) {
+            int n = 0;
+            cus = hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+                          n > 0 ? n : 256;
+            cus_of[dev].store(cus, std::memory_order_relaxed);
+        }
     }
     // `waves` resident wavefronts per SIMD, 4 SIMDs per CU, kWavesPerBlock per block
     int b = cus * 4 * cfg.waves / kWavesPerBlock;
@@ -517,7 +534,7 @@ static hipError_t run_batched(const rc_scene* scene, const RenderLaunch& L, void
     hipError_t e = hipSuccess;
     if (scene->n_links > 0)
         e = launch_tlas_build(L.link_pos, L.link_quat, L.n_env, scene->n_links, L.link_meta,
-                              (Node*)ws, (InstXform*)L.xf, s);
+                              (Node*)ws, (InstXform*)L.xf, !cfg.bodies_flat, s);
     if (e == hipSuccess)
         e = launch_render_batched(L, cfg, (uint32_t*)((char*)ws + W.tiles),
                                   (uint32_t*)((char*)ws + W.queues), (uint32_t*)((char*)ws + W.status),
@@ -531,7 +548,7 @@ rc_status rc_render_batched(const rc_scene* scene, const rc_batch_args* a, void*
     RenderWs W;
     rc_status st = prep_batched(scene, a, ws, ws_bytes, L, W, "rc_render_batched");
     if (st != RC_OK) return st;
-    hipError_t e = run_batched(scene, L, ws, W, scene->cfg_batched, (hipStream_t)stream);
+    hipError_t e = run_batched(scene, L, ws, W, scene->cfg_batched(), (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "rc_render_batched: launch");
     return RC_OK;
 }
@@ -575,7 +592,7 @@ static rc_render_config from_cfg(const RenderCfg& c) {
 
 rc_status rc_get_render_config(const rc_scene* scene, int32_t batched, rc_render_config* cfg) {
     if (!scene || !cfg) return fail(RC_ERR_INVALID_ARG, "rc_get_render_config: NULL pointer");
-    *cfg = from_cfg(batched ? scene->cfg_batched : scene->cfg);
+    *cfg = from_cfg(batched ? scene->cfg_batched() : scene->cfg());
     return RC_OK;
 }
 
@@ -586,7 +603,7 @@ rc_status rc_set_render_config(rc_scene* scene, int32_t batched, const rc_render
         return fail(RC_ERR_INVALID_ARG, "rc_set_render_config: need tile_w * tile_h = 64, "
                                         "rays_per_lane in {1, 2}, waves in {6, 7, 8}, "
                                         "terrain_packet and bodies_flat in {0, 1}");
-    (batched ? scene->cfg_batched : scene->cfg) = c;
+    scene->set_cfg(batched != 0, c);
     return RC_OK;
 }
 
@@ -637,7 +654,7 @@ rc_status rc_autotune(rc_scene* scene, const rc_render_args* plain, const rc_bat
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (e != hipSuccess) return hip_fail(e, "rc_autotune");
-    (plain ? scene->cfg : scene->cfg_batched) = win;
+    scene->set_cfg(plain == nullptr, win);
     if (best) *best = from_cfg(win);
     if (best_ms) *best_ms = win_ms;
     return RC_OK;
@@ -659,10 +676,10 @@ rc_status rc_graph_capture_batched(const rc_scene* scene, const rc_batch_args* a
         return fail(RC_ERR_STATE, "rc_graph_capture_batched: stream is already capturing");
     rc_graph* g = new (std::nothrow) rc_graph();
     if (!g) return fail(RC_ERR_DEVICE, "rc_graph_capture_batched: out of host memory");
-    persistent_blocks(scene->cfg_batched);  // device query outside the capture
+    persistent_blocks(scene->cfg_batched());  // device query outside the capture
     hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        hipError_t er = run_batched(scene, L, ws, W, scene->cfg_batched, s);
+        hipError_t er = run_batched(scene, L, ws, W, scene->cfg_batched(), s);
         e = hipStreamEndCapture(s, &g->graph);
         if (er != hipSuccess) e = er;
     }
@@ -848,6 +865,29 @@ rc_status rc_postprocess(rc_post* post, const float* depth_in, const int32_t* in
     return RC_OK;
 }
 
+rc_status rc_postprocess_words(rc_post* post, const float* depth_in, const int32_t* inst_in,
+                               const rc_post_params* pp, uint64_t step, const uint32_t* cam_uid,
+                               float* depth_out, uint8_t* drop_out, uint8_t* lat_out,
+                               uint32_t* words_out, rc_stream stream) {
+    if (!words_out || ((uintptr_t)words_out % 16) != 0)
+        return fail(RC_ERR_INVALID_ARG, "rc_postprocess_words: words_out must be a 16-byte aligned "
+                                        "device pointer");
+    PostLaunch L;
+    rc_status st = post_common(post, depth_in, pp, step, depth_out, L, "rc_postprocess_words");
+    if (st != RC_OK) return st;
+    if (post->packed)
+        return fail(RC_ERR_STATE, "rc_postprocess_words: state was created packed");
+    L.inst_in = inst_in;
+    L.cam_uid = cam_uid;
+    L.drop_out = drop_out;
+    L.lat_out = lat_out;
+    L.words_out = reinterpret_cast<uint4*>(words_out);
+    hipError_t e = launch_post(L, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "rc_postprocess_words: launch");
+    post_advance(post, step);
+    return RC_OK;
+}
+
 rc_status rc_post_size_packed(int64_t n_pixels, int32_t max_latency, size_t* ws_bytes) {
     if (!ws_bytes) return fail(RC_ERR_INVALID_ARG, "rc_post_size_packed: ws_bytes is NULL");
     if (n_pixels < 1 || n_pixels > (int64_t)0xFFFFFFFF || max_latency < 0 || max_latency > 255)
@@ -986,7 +1026,7 @@ rc_status enqueue_batched(const rc_scene* scene, const rc_batch_args* a, int64_t
     rc_status st = prep_batched(scene, a, ws, ws_bytes, L, W, "serving batch", cap_rays);
     if (st != RC_OK) return st;
     L.ev_begin = L.ev_end = nullptr;
-    hipError_t e = run_batched(scene, L, ws, W, scene->cfg_batched, s);
+    hipError_t e = run_batched(scene, L, ws, W, scene->cfg_batched(), s);
     if (e != hipSuccess) return hip_fail(e, "serving batch: launch");
     return RC_OK;
 }

@@ -97,6 +97,7 @@ __device__ __forceinline__ void post_pixel(const PostLaunch& a, int64_t p, uint3
     const float z = a.depth_in[p];
     const bool hit = a.inst_in ? (a.inst_in[p] >= 0) : (z < a.far_plane);
     const uint4 wd = pixel_draw(a, pix, uid);
+    if (a.words_out) a.words_out[p] = wd;
     bool drop;
     const float cap = capture(a, z, hit, wd, drop);
     const int64_t here = (int64_t)a.slot * a.n_pix + p;
@@ -135,6 +136,7 @@ __device__ __forceinline__ void post_quad(const PostLaunch& a, int64_t p, uint32
     uint32_t bits = 0u;
     for (int j = 0; j < 4; ++j) {
         wd[j] = pixel_draw(a, pix + (uint32_t)j, uid);
+        if (a.words_out) a.words_out[p + j] = wd[j];
         const bool hit = a.inst_in ? (id[j] >= 0) : (z[j] < a.far_plane);
         bool drop;
         cap[j] = capture(a, z[j], hit, wd[j], drop);

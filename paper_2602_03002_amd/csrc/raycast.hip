@@ -36,13 +36,39 @@ constexpr int kChunk = 8;  // tiles a wavefront of the batched launch takes at a
 struct TileCfg {
     int tw, th, rpl;  // tile width and height (tw * th = 64), tiles per wavefront
 };
-// FP32 edge decisions are trusted when every edge function is farther than
-// kappa * (|U| + |V| + |W|) from zero.  Measured on the 4096-env workload, the
-// FP32 error of the normalised edge functions is at most 3.7e-6 for terrain
-// triangles (world frame) and 5.5e-6 for link triangles (through the FP32 link
-// transform); the margins below are over 30 times larger.
-constexpr float kTerrainKappa = 1.0f / 8192.0f;
-constexpr float kLinkKappa = 1.0f / 2048.0f;
+// Error bounds of the FP32 triangle test (u = 2^-24).  The decision and the
+// depth are taken in FP32 only when they cannot differ from exact arithmetic
+// on the exact (FP64) ray; otherwise the exact pass repeats the test in FP64.
+// With p = v - o, P = max |p| over the vertices' coordinates, (X, Y) the
+// sheared vertex coordinates and S = sum |X| + |Y|:
+//  - in the world frame each computed X or Y is within e = 8u P + u |X| of
+//    its exact value (rounding of v - o and of the shear product, the FP32
+//    ray direction and the hardware reciprocal in the shear constant: 5u);
+//    a rounded ray origin (randomised cameras) adds twice its rounding;
+//  - in a link frame (R rounded once from FP64, the link-frame ray computed in
+//    FP64 from the exact pixel ray and rounded once) each direction component
+//    is within 1.87u |d_b| and each origin component within 1.87u |o_b| of
+//    exact (max norms), so the shear constant is within 7u and
+//    e <= u |X| + 10u P + 3.74u |o_b|;
+//  - an edge function U = C_x B_y - C_y B_x then errs by at most
+//    u |U| + 1.25u S^2 + 8u P S (in the world frame), so every edge function
+//    is within thr = 4u (|U| + |V| + |W|) + S (2u S + k_P P + e_O) of exact,
+//    with k_P = 16u (world) or 32u (link frame) and e_O the origin term
+//    (16u |o_b| in the link frame), each at least twice its bound.
+// A certain hit's depth t is the height Z of the triangle's plane over the
+// ray in sheared coordinates; vertex errors of e in X and Y move it by about
+// |grad Z|_1 e, grad Z = -(n_x, n_y) / n_z for the plane's normal n in
+// sheared coordinates (n_z = det), and FP32 keeps the depth only when that is
+// below kDepthTol (a fifth of the depth bar, which also covers the rounding
+// of Z itself, a few ulp of t).  A triangle seen almost edge-on (grazing
+// incidence) or a sliver has tiny edge functions but not tiny errors; these
+// bounds, not a margin relative to the edge functions alone, keep its
+// decisions and depths exact.
+constexpr float kU = 5.9604644775390625e-08f;  // 2^-24
+constexpr float kTerrainKP = 16.0f * kU;
+constexpr float kLinkKP = 32.0f * kU;
+constexpr float kLinkKO = 16.0f * kU;         // per unit of |o_b| (max norm)
+constexpr float kDepthTol = 2.0e-5f;          // a fifth of the 1e-4 m depth bar
 
 struct Slab {  // box-test form of a ray: t = b * (1/d) - o * (1/d)
     float ix, iy, iz, oix, oiy, oiz;
@@ -239,6 +265,7 @@ struct PixelRef {  // what the exact-decision path needs to rebuild the ray
     const float* link_quat;
     int x, y, e, n_links;
     uint2* cand;  // fast pass: this lane's two LDS slots for FP32-undecided triangles
+    float eo;     // 4 x the rounding of the FP32 ray origin (0 when it is exact)
 };
 
 // FP32-undecided triangles the fast pass keeps per ray (in LDS), for the exact
@@ -286,7 +313,8 @@ struct RayCount {
 template <bool EXACT>
 __device__ __forceinline__ void tri_test(const float* __restrict__ v,
                                          const int32_t* __restrict__ tri_ids, uint32_t inst,
-                                         float ox, float oy, float oz, const Shear& m, float kappa,
+                                         float ox, float oy, float oz, const Shear& m, float k_p,
+                                         float e_o,
                                          Hit& h, const PixelRef& px, int link, int leaf) {
     const float p0x = v[0] - ox, p0y = v[1] - oy, p0z = v[2] - oz;
     const float p1x = v[3] - ox, p1y = v[4] - oy, p1z = v[5] - oz;
@@ -300,29 +328,47 @@ __device__ __forceinline__ void tri_test(const float* __restrict__ v,
     const float U = __fmaf_rn(Cx, By, -(Cy * Bx));
     const float V = __fmaf_rn(Ax, Cy, -(Ay * Cx));
     const float W = __fmaf_rn(Bx, Ay, -(By * Ax));
-    const float thr = (fabsf(U) + fabsf(V) + fabsf(W)) * kappa;
+    const float P = fmaxf(fmaxf(fmaxf(fmaxf(fabsf(p0x), fabsf(p0y)), fmaxf(fabsf(p0z), fabsf(p1x))),
+                                fmaxf(fmaxf(fabsf(p1y), fabsf(p1z)), fmaxf(fabsf(p2x), fabsf(p2y)))),
+                          fabsf(p2z));
+    const float S = ((fabsf(Ax) + fabsf(Ay)) + (fabsf(Bx) + fabsf(By))) + (fabsf(Cx) + fabsf(Cy));
+    const float inner = __fmaf_rn(S, 2.0f * kU, __fmaf_rn(P, k_p, e_o));  // twice the X, Y error
+    const float thr = __fmaf_rn(fabsf(U) + fabsf(V) + fabsf(W), 4.0f * kU, S * inner);
     const float lo = fminf(fminf(U, V), W), hi = fmaxf(fmaxf(U, V), W);
     if ((lo < -thr) & (hi > thr)) return;  // certainly outside
     // certain hit only when all three clear the margin with the same sign
     const bool sure = (thr > 0.0f) & ((lo > thr) | (hi < -thr));
-    float t;
-    if (EXACT && !sure) {
-        double t64;
-        if (!refine(v, px.cam.b, px.x, px.y, link, px.e, px.n_links,
-                    px.link_pos, px.link_quat, &t64))
-            return;
-        t = (float)t64;
-    } else {
+    // FP32 also gives the depth of a certain hit unless the triangle is seen
+    // almost edge-on (the depth bound above); then the exact pass computes it
+    bool fp32 = sure;
+    float t = 0.0f, det = 0.0f;
+    if (!EXACT || sure) {
         const float Az = __fmaf_rn(m.m3z, p0z, __fmaf_rn(m.m3y, p0y, m.m3x * p0x));
         const float Bz = __fmaf_rn(m.m3z, p1z, __fmaf_rn(m.m3y, p1y, m.m3x * p1x));
         const float Cz = __fmaf_rn(m.m3z, p2z, __fmaf_rn(m.m3y, p2y, m.m3x * p2x));
-        const float det = U + V + W;
+        det = U + V + W;
         const float T = __fmaf_rn(W, Cz, __fmaf_rn(V, Bz, U * Az));
         t = T * __builtin_amdgcn_rcpf(det);
-        if (!EXACT && !sure) {
-            // undecided in FP32: keep the triangle for the exact pass unless its
-            // plane is behind the origin (well conditioned) or beyond the bound
-            const bool cond = fabsf(det) > thr;
+        if (sure) {
+            const float dX1 = Bx - Ax, dY1 = By - Ay, dZ1 = Bz - Az;
+            const float dX2 = Cx - Ax, dY2 = Cy - Ay, dZ2 = Cz - Az;
+            const float gx = __fmaf_rn(dY1, dZ2, -(dZ1 * dY2));
+            const float gy = __fmaf_rn(dZ1, dX2, -(dX1 * dZ2));
+            fp32 = (fabsf(gx) + fabsf(gy)) * (0.5f * inner) <= kDepthTol * fabsf(det);
+        }
+    }
+    if (!fp32) {
+        if (EXACT) {
+            double t64;
+            if (!refine(v, px.cam.b, px.x, px.y, link, px.e, px.n_links,
+                        px.link_pos, px.link_quat, &t64))
+                return;
+            t = (float)t64;
+        } else {
+            // undecided in FP32 (the test, or the depth of a certain hit): keep
+            // the triangle for the exact pass unless its plane is behind the
+            // origin (well conditioned) or beyond the bound
+            const bool cond = !sure && fabsf(det) > thr;
             if (cond && t < -1e-3f) return;
             const float tu = (cond && t > 0.0f) ? t : 0.0f;
             const float lim = h.tmax * kUndecidedSlack;
@@ -445,22 +491,30 @@ __device__ __forceinline__ void enter_link(const RenderLaunch& a, int e, int b, 
                                            const PixelRef& px, Cnt& cnt, uint32_t* stk) {
     cnt.inst();
     const InstXform X = a.xf[(int64_t)e * a.n_links + b];
-    const float px_ = ox - X.t[0], py_ = oy - X.t[1], pz_ = oz - X.t[2];
-    const float lox = __fmaf_rn(X.m[2], pz_, __fmaf_rn(X.m[1], py_, X.m[0] * px_));
-    const float loy = __fmaf_rn(X.m[5], pz_, __fmaf_rn(X.m[4], py_, X.m[3] * px_));
-    const float loz = __fmaf_rn(X.m[8], pz_, __fmaf_rn(X.m[7], py_, X.m[6] * px_));
-    const float ldx = __fmaf_rn(X.m[2], dz, __fmaf_rn(X.m[1], dy, X.m[0] * dx));
-    const float ldy = __fmaf_rn(X.m[5], dz, __fmaf_rn(X.m[4], dy, X.m[3] * dx));
-    const float ldz = __fmaf_rn(X.m[8], dz, __fmaf_rn(X.m[7], dy, X.m[6] * dx));
+    // the link-frame ray in FP64 from the exact pixel ray, rounded once: each
+    // component is then within 1.87u of the exact one (max norm; R is rounded
+    // from FP64 as well), which is what the link-frame error bound uses
+    double o64[3], d64[3], rx, ry;
+    pixel_ray64(px.cam, px.x, px.y, o64, d64, rx, ry);
+    const double qx = o64[0] - (double)X.t[0], qy = o64[1] - (double)X.t[1], qz = o64[2] - (double)X.t[2];
+    const float lox = (float)((double)X.m[0] * qx + (double)X.m[1] * qy + (double)X.m[2] * qz);
+    const float loy = (float)((double)X.m[3] * qx + (double)X.m[4] * qy + (double)X.m[5] * qz);
+    const float loz = (float)((double)X.m[6] * qx + (double)X.m[7] * qy + (double)X.m[8] * qz);
+    const float ldx = (float)((double)X.m[0] * d64[0] + (double)X.m[1] * d64[1] + (double)X.m[2] * d64[2]);
+    const float ldy = (float)((double)X.m[3] * d64[0] + (double)X.m[4] * d64[1] + (double)X.m[5] * d64[2]);
+    const float ldz = (float)((double)X.m[6] * d64[0] + (double)X.m[7] * d64[1] + (double)X.m[8] * d64[2]);
+    (void)ox; (void)oy; (void)oz; (void)dx; (void)dy; (void)dz;
     const Slab ls = make_slab(lox, loy, loz, ldx, ldy, ldz);
     const Shear lm = make_shear(ldx, ldy, ldz);
+    // origin term of the link-frame error bound (grows with |o_b|)
+    const float e_o = fmaxf(fmaxf(fabsf(lox), fabsf(loy)), fabsf(loz)) * kLinkKO;
     const LinkMeta M = a.link_meta[b];
     const float* __restrict__ tris = a.link_tris + M.tri_base;
     const int32_t* __restrict__ ids = a.link_tri_id + M.id_base;
     const uint32_t n0 = cnt.nodes();
     traverse(a.link_nodes + M.node_base, M.n_tri > 1 ? M.n_tri - 1 : 1, M.n_tri, ls, h, cnt, [&](int i) {
         cnt.tri();
-        tri_test<EXACT>(tris + 9 * (int64_t)i, ids, (uint32_t)b, lox, loy, loz, lm, kLinkKappa, h,
+        tri_test<EXACT>(tris + 9 * (int64_t)i, ids, (uint32_t)b, lox, loy, loz, lm, kLinkKP, e_o, h,
                         px, b, i);
     }, 0, stk);
     cnt.link_nodes(cnt.nodes() - n0);
@@ -518,16 +572,32 @@ __device__ __forceinline__ Hit cast_ray(const RenderLaunch& a, const CamRef& cam
                    bound);
     h.key = ~0ull;
     h.tu = INFINITY;
-    const PixelRef px{cam, a.link_pos, a.link_quat, x, y, e, a.n_links, cand};
+    // a rounded origin (randomised cameras) moves every sheared coordinate by
+    // up to twice its rounding
+    const double r_o = fmax(fmax(fabs(o64[0] - (double)ox), fabs(o64[1] - (double)oy)),
+                            fabs(o64[2] - (double)oz));
+    const PixelRef px{cam, a.link_pos, a.link_quat, x, y, e, a.n_links, cand, (float)(4.0 * r_o)};
 
     if (a.n_links > 0) {
         const int n_rec = a.n_links > 1 ? a.n_links - 1 : 1;
         const Node* __restrict__ tl = a.tlas + (int64_t)e * n_rec;
         if (!WAVE) {
-            const Slab ws = make_slab(ox, oy, oz, dx, dy, dz);
-            traverse(tl, n_rec, a.n_links, ws, h, cnt, [&](int b) {
-                enter_link<EXACT>(a, e, b, ox, oy, oz, dx, dy, dz, h, px, cnt, nullptr);
-            });
+            // one lane alone (the exact pass): every link's bounding sphere
+            // against the lane's segment [o, o + tmax d]; the result does not
+            // depend on the order, since hits are ranked by (depth, inst, tri)
+            const float dd = __fmaf_rn(dz, dz, __fmaf_rn(dy, dy, dx * dx));
+            for (int b = 0; b < a.n_links; ++b) {
+                float sx, sy, sz, sr;
+                link_sphere(a, e, b, sx, sy, sz, sr);
+                const float wx = sx - ox, wy = sy - oy, wz = sz - oz;
+                const float tc = fminf(fmaxf(__fmaf_rn(wz, dz, __fmaf_rn(wy, dy, wx * dx)) *
+                                                 __builtin_amdgcn_rcpf(dd), 0.0f),
+                                       h.tmax);
+                const float qx = __fmaf_rn(-tc, dx, wx), qy = __fmaf_rn(-tc, dy, wy),
+                            qz = __fmaf_rn(-tc, dz, wz);
+                if (__fmaf_rn(qz, qz, __fmaf_rn(qy, qy, qx * qx)) <= sr * sr)
+                    enter_link<EXACT>(a, e, b, ox, oy, oz, dx, dy, dz, h, px, cnt, nullptr);
+            }
         } else if (MODE & kFlatBodies) {
             // cone of the wavefront's rays (common apex o): unit axis and the
             // cosine of its half-angle, widened for rounding
@@ -573,7 +643,9 @@ __device__ __forceinline__ Hit cast_ray(const RenderLaunch& a, const CamRef& cam
                     enter_link<EXACT>(a, e, b, ox, oy, oz, dx, dy, dz, h, px, cnt, stk);
             }
         } else {
-            uint32_t trail = 0;
+            // 64-bit trail: a Karras hierarchy over 64 instances can be deeper
+            // than 32 levels when Morton codes tie
+            uint64_t trail = 0;
             int cur = 0;
             int budget = 2 * n_rec + 2;
             for (;;) {
@@ -600,7 +672,7 @@ __device__ __forceinline__ Hit cast_ray(const RenderLaunch& a, const CamRef& cam
                 if (G0 && G1) {
                     const int want1 = __popcll(__ballot(g1 && (!g0 || tn1 < tn0)));
                     const int want0 = __popcll(__ballot(g0 && (!g1 || tn0 <= tn1)));
-                    trail = (trail << 1) | 1u;
+                    trail = (trail << 1) | 1ull;
                     cur = want1 > want0 ? c1 : c0;
                     continue;
                 }
@@ -612,8 +684,8 @@ __device__ __forceinline__ Hit cast_ray(const RenderLaunch& a, const CamRef& cam
                 int par = N.parent, sib = N.sibling;
                 bool done = false;
                 for (;;) {
-                    if (trail == 0u) { done = true; break; }
-                    if (trail & 1u) { trail ^= 1u; cur = sib; break; }
+                    if (trail == 0ull) { done = true; break; }
+                    if (trail & 1ull) { trail ^= 1ull; cur = sib; break; }
                     trail >>= 1;
                     par = uni(par);
                     if ((unsigned)par >= (unsigned)n_rec || --budget < 0) { done = true; break; }
@@ -663,7 +735,7 @@ __device__ __forceinline__ Hit cast_ray(const RenderLaunch& a, const CamRef& cam
             auto leaf = [&](int i) {
                 cnt.tri();
                 tri_test<EXACT>(a.terrain_tris + 9 * (int64_t)i, a.terrain_tri_id,
-                                (uint32_t)a.n_links, ox, oy, oz, wm, kTerrainKappa, h, px, -1, i);
+                                (uint32_t)a.n_links, ox, oy, oz, wm, kTerrainKP, px.eo, h, px, -1, i);
             };
             if (!(MODE & kPacketTerrain)) {
                 // a wavefront whose rays share one direction octant (the common

@@ -74,9 +74,11 @@ BvhLayout bvh_layout(int64_t n, size_t base);
 // Host-side launchers (each returns a hipError_t of its enqueue).
 hipError_t launch_blas_build(const float* tri, int64_t n, char* ws, const BvhLayout& L,
                              hipStream_t s);
+// with_nodes = false: only the instance transforms (the renderer's sphere
+// culling never walks the top level)
 hipError_t launch_tlas_build(const float* link_pos, const float* link_quat, int n_env,
                              int n_links, const LinkMeta* meta, Node* tlas, InstXform* xf,
-                             hipStream_t s);
+                             bool with_nodes, hipStream_t s);
 
 struct RenderLaunch {
     const Node* terrain_nodes;
@@ -127,6 +129,25 @@ struct RenderCfg {
     int bodies_flat = 1;         // links found by the top-level walk (0) or by cone culling (1)
 };
 bool render_cfg_ok(const RenderCfg& c);
+// One word per schedule (fields of 8 bits each), so a schedule can be read and
+// replaced atomically.
+inline uint64_t pack_cfg(const RenderCfg& c) {
+    return (uint64_t)(c.tile_w & 0xFF) | (uint64_t)(c.tile_h & 0xFF) << 8 |
+           (uint64_t)(c.rays_per_lane & 0xFF) << 16 | (uint64_t)(c.waves & 0xFF) << 24 |
+           (uint64_t)(c.persistent & 0xFF) << 32 | (uint64_t)(c.terrain_packet & 0xFF) << 40 |
+           (uint64_t)(c.bodies_flat & 0xFF) << 48;
+}
+inline RenderCfg unpack_cfg(uint64_t v) {
+    RenderCfg c;
+    c.tile_w = (int)(v & 0xFF);
+    c.tile_h = (int)((v >> 8) & 0xFF);
+    c.rays_per_lane = (int)((v >> 16) & 0xFF);
+    c.waves = (int)((v >> 24) & 0xFF);
+    c.persistent = (int)((v >> 32) & 0xFF);
+    c.terrain_packet = (int)((v >> 40) & 0xFF);
+    c.bodies_flat = (int)((v >> 48) & 0xFF);
+    return c;
+}
 
 struct HeightLaunch {
     const Node* nodes;
@@ -166,6 +187,7 @@ struct PostLaunch {
     float mask_p[4][3];
     uint64_t mask_epoch;
     const uint8_t* mask_type;
+    uint4* words_out = nullptr;  // debug: the raw Philox words of each pixel's draw
 };
 hipError_t launch_post(const PostLaunch& a, hipStream_t s);
 hipError_t launch_downsample(const float* depth, const int32_t* inst, int64_t n_img, int H, int W,

@@ -126,6 +126,7 @@ struct rc_server {
     std::deque<rc_result> ready;
     std::unordered_map<int64_t, Taken> out_of;  // finished results -> their output range
     int64_t next_id = 1;
+    int32_t fail_next = 0;  // batches still to report an injected failure
     std::vector<double> lat;
     rc_server_stats st{};
 
@@ -392,17 +393,35 @@ rc_status rc_server_submit(rc_server* s, const rc_request* r, double now_s, int6
     return RC_OK;
 }
 
+// A batch that finished on the device, or failed on purpose when a failure
+// was injected (rc_server_fail_next).
+static void finish_ok(rc_server* s, Batch& b, double now_s) {
+    if (s->fail_next > 0) {
+        s->fail_next -= 1;
+        set_error("serving batch: injected failure (rc_server_fail_next)");
+        finish_batch(s, b, now_s, RC_ERR_DEVICE);
+        return;
+    }
+    finish_batch(s, b, now_s, RC_OK);
+}
+
+rc_status rc_server_fail_next(rc_server* s, int32_t n_batches) {
+    if (!s || n_batches < 0) return fail_s(RC_ERR_INVALID_ARG, "rc_server_fail_next: bad args");
+    s->fail_next = n_batches;
+    return RC_OK;
+}
+
 rc_status rc_server_poll(rc_server* s, double now_s, int32_t* n_done) {
     if (!s) return fail_s(RC_ERR_INVALID_ARG, "rc_server_poll: NULL");
     for (size_t k = 0; k < s->slots.size(); ++k) {
         Batch& b = s->slots[k];
         if (!b.active) continue;
         if (s->sim) {
-            if (now_s >= b.sim_done) finish_batch(s, b, now_s, RC_OK);
+            if (now_s >= b.sim_done) finish_ok(s, b, now_s);
             continue;
         }
         const hipError_t q = hipEventQuery(s->events[k]);
-        if (q == hipSuccess) finish_batch(s, b, now_s, RC_OK);
+        if (q == hipSuccess) finish_ok(s, b, now_s);
         else if (q != hipErrorNotReady) {
             set_error(std::string("serving batch: ") + hipGetErrorString(q));
             finish_batch(s, b, now_s, RC_ERR_DEVICE);

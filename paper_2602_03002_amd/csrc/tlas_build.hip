@@ -8,6 +8,14 @@
 // (keys broken by instance index), builds the Karras hierarchy from the
 // ranked keys, and boxes every internal node as the union of its leaf range.
 // Everything stays in LDS; no atomics, so the result is deterministic.
+//
+// A link whose pose is not finite (or whose quaternion is zero) is absent from
+// its environment for this render: its transform places it at
+// the far point (identity rotation, t = 1e30) and its instance box is that
+// point, so no ray reaches it; the other links and the terrain are unaffected.
+// When the renderer culls links by their bounding spheres (the default
+// schedule) it never walks the top level, and only the transforms are
+// written.
 #include "rc_internal.h"
 
 #pragma clang fp contract(off)
@@ -36,7 +44,8 @@ __device__ __forceinline__ int tdelta(const uint32_t* k, int n, int i, int j) {
 
 __global__ void __launch_bounds__(256)
 k_tlas(const float* __restrict__ link_pos, const float* __restrict__ link_quat, int n_env, int B,
-       const LinkMeta* __restrict__ meta, Node* __restrict__ tlas, InstXform* __restrict__ xf) {
+       const LinkMeta* __restrict__ meta, Node* __restrict__ tlas, InstXform* __restrict__ xf,
+       int with_nodes) {
     __shared__ float sbox[kWaves][kMaxLinks][6];
     __shared__ float nbox[kWaves][kMaxLinks][6];
     __shared__ uint32_t skey[kWaves][kMaxLinks];
@@ -53,23 +62,42 @@ k_tlas(const float* __restrict__ link_pos, const float* __restrict__ link_quat, 
 
     float box[6] = {0, 0, 0, 0, 0, 0};
     float cw[3] = {0, 0, 0};
+    bool pose_ok = false;  // an instance with a usable pose
     if (inst_ok) {
         const int64_t eb = (int64_t)e * B + lane;
         const float* q = link_quat + 4 * eb;
         const float* t = link_pos + 3 * eb;
-        float qx = q[0], qy = q[1], qz = q[2], qw = q[3];
-        float nn = __fsqrt_rn(qx * qx + qy * qy + qz * qz + qw * qw);
-        qx = __fdiv_rn(qx, nn); qy = __fdiv_rn(qy, nn); qz = __fdiv_rn(qz, nn); qw = __fdiv_rn(qw, nn);
+        const double qx = q[0], qy = q[1], qz = q[2], qw = q[3];
+        const double nn = sqrt(qx * qx + qy * qy + qz * qz + qw * qw);
+        pose_ok = isfinite(t[0]) && isfinite(t[1]) && isfinite(t[2]) && nn > 0.0 && isfinite(nn);
+        if (!pose_ok) {
+            InstXform X;
+            for (int k = 0; k < 9; ++k) X.m[k] = (k % 4 == 0) ? 1.0f : 0.0f;
+            X.t[0] = X.t[1] = X.t[2] = kFarBox;
+            xf[eb] = X;
+            for (int k = 0; k < 6; ++k) box[k] = kFarBox;
+        }
+    }
+    if (pose_ok) {
+        const int64_t eb = (int64_t)e * B + lane;
+        const float* q = link_quat + 4 * eb;
+        const float* t = link_pos + 3 * eb;
+        // the rotation in FP64, rounded once: each FP32 entry is within half an
+        // ulp of the exact R(q_b), which bounds the error of the FP32 link-frame
+        // rays the renderer's triangle margins account for
+        double qx = q[0], qy = q[1], qz = q[2], qw = q[3];
+        const double nn = sqrt(qx * qx + qy * qy + qz * qz + qw * qw);
+        qx /= nn; qy /= nn; qz /= nn; qw /= nn;
         float R[9];
-        R[0] = 1.0f - 2.0f * (qy * qy + qz * qz);
-        R[1] = 2.0f * (qx * qy - qz * qw);
-        R[2] = 2.0f * (qx * qz + qy * qw);
-        R[3] = 2.0f * (qx * qy + qz * qw);
-        R[4] = 1.0f - 2.0f * (qx * qx + qz * qz);
-        R[5] = 2.0f * (qy * qz - qx * qw);
-        R[6] = 2.0f * (qx * qz - qy * qw);
-        R[7] = 2.0f * (qy * qz + qx * qw);
-        R[8] = 1.0f - 2.0f * (qx * qx + qy * qy);
+        R[0] = (float)(1.0 - 2.0 * (qy * qy + qz * qz));
+        R[1] = (float)(2.0 * (qx * qy - qz * qw));
+        R[2] = (float)(2.0 * (qx * qz + qy * qw));
+        R[3] = (float)(2.0 * (qx * qy + qz * qw));
+        R[4] = (float)(1.0 - 2.0 * (qx * qx + qz * qz));
+        R[5] = (float)(2.0 * (qy * qz - qx * qw));
+        R[6] = (float)(2.0 * (qx * qz - qy * qw));
+        R[7] = (float)(2.0 * (qy * qz + qx * qw));
+        R[8] = (float)(1.0 - 2.0 * (qx * qx + qy * qy));
         InstXform X;
         for (int r = 0; r < 3; ++r)
             for (int c = 0; c < 3; ++c) X.m[3 * r + c] = R[3 * c + r];
@@ -91,18 +119,19 @@ k_tlas(const float* __restrict__ link_pos, const float* __restrict__ link_quat, 
             box[2 * a + 1] = cw[a] + h + pad;
         }
     }
+    if (!with_nodes) return;  // uniform over the block
     // centre bounds of this environment's instances (wave reduction)
     float cmin[3], cmax[3];
     for (int a = 0; a < 3; ++a) {
-        cmin[a] = inst_ok ? cw[a] : INFINITY;
-        cmax[a] = inst_ok ? cw[a] : -INFINITY;
+        cmin[a] = pose_ok ? cw[a] : INFINITY;
+        cmax[a] = pose_ok ? cw[a] : -INFINITY;
         for (int off = 32; off >= 1; off >>= 1) {
             cmin[a] = fminf(cmin[a], __shfl_xor(cmin[a], off, 64));
             cmax[a] = fmaxf(cmax[a], __shfl_xor(cmax[a], off, 64));
         }
     }
-    uint32_t key = 0;
-    if (inst_ok) {
+    uint32_t key = 0xFFFFFFFFu;  // absent instances sort last
+    if (pose_ok) {
         uint32_t q[3];
         for (int a = 0; a < 3; ++a) {
             float ext = cmax[a] - cmin[a];
@@ -199,10 +228,11 @@ k_tlas(const float* __restrict__ link_pos, const float* __restrict__ link_quat, 
 }  // namespace
 
 hipError_t launch_tlas_build(const float* link_pos, const float* link_quat, int n_env, int n_links,
-                             const LinkMeta* meta, Node* tlas, InstXform* xf, hipStream_t s) {
+                             const LinkMeta* meta, Node* tlas, InstXform* xf, bool with_nodes,
+                             hipStream_t s) {
     unsigned blocks = (unsigned)((n_env + kWaves - 1) / kWaves);
     hipLaunchKernelGGL(k_tlas, dim3(blocks), dim3(64 * kWaves), 0, s, link_pos, link_quat, n_env,
-                       n_links, meta, tlas, xf);
+                       n_links, meta, tlas, xf, with_nodes ? 1 : 0);
     return hipGetLastError();
 }
 

@@ -28,6 +28,7 @@ EXPORTED = [
     "rc_robot_size", "rc_robot_meshes",
     "rc_render_size", "rc_render", "rc_render_exact_count", "rc_render_counts",
     "rc_post_size", "rc_post_create", "rc_post_reset", "rc_postprocess", "rc_post_destroy",
+    "rc_postprocess_words",
     "rc_downsample", "rc_heightmap",
     "rc_bvh_layout_of",
     "rc_render_batched_size", "rc_render_batched", "rc_render_batched_status",
@@ -36,6 +37,7 @@ EXPORTED = [
     "rc_post_size_packed", "rc_post_create_packed", "rc_postprocess_batched",
     "rc_server_arena_size", "rc_server_create", "rc_server_create_simulated", "rc_server_submit",
     "rc_server_poll", "rc_server_next_result", "rc_server_release", "rc_server_stats_get",
+    "rc_server_fail_next",
     "rc_server_destroy",
 ]
 
@@ -180,6 +182,8 @@ def lib():
         L.rc_heightmap.argtypes = [vp, ctypes.POINTER(HeightmapArgs), vp]
         L.rc_postprocess.argtypes = [vp, vp, vp, ctypes.POINTER(PostParams), ctypes.c_uint64, vp,
                                      vp, vp, vp, vp]
+        L.rc_postprocess_words.argtypes = [vp, vp, vp, ctypes.POINTER(PostParams), ctypes.c_uint64, vp,
+                                     vp, vp, vp, vp, vp]
         L.rc_post_destroy.argtypes = [vp]
         L.rc_bvh_layout_of.argtypes = [vp, i32, ctypes.POINTER(BvhLayout)]
         L.rc_render_batched_size.argtypes = [vp, i32, i32, i64, ctypes.POINTER(sz)]
@@ -205,6 +209,7 @@ def lib():
         L.rc_server_submit.argtypes = [vp, ctypes.POINTER(Request), ctypes.c_double,
                                        ctypes.POINTER(i64)]
         L.rc_server_poll.argtypes = [vp, ctypes.c_double, ctypes.POINTER(i32)]
+        L.rc_server_fail_next.argtypes = [vp, i32]
         L.rc_server_next_result.argtypes = [vp, ctypes.POINTER(Result)]
         L.rc_server_release.argtypes = [vp, i64]
         L.rc_server_stats_get.argtypes = [vp, ctypes.POINTER(ServerStats)]
@@ -604,6 +609,19 @@ class Post:
                                    _stream(stream)))
         return d, drop, lat
 
+    def process_words(self, depth, inst, params, step, cam_uid=None, stream=None):
+        """process() plus the raw Philox words of every pixel's draw: returns
+        (depth_out, drop, lat, words uint32 [E,C,H,W,4] as int32 storage)."""
+        _dev_f32(depth, self.shape, "depth")
+        d = torch.empty(self.shape, dtype=torch.float32, device=depth.device)
+        drop = torch.empty(self.shape, dtype=torch.uint8, device=depth.device)
+        lat = torch.empty(self.shape[:2], dtype=torch.uint8, device=depth.device)
+        words = torch.empty(tuple(self.shape) + (4,), dtype=torch.int32, device=depth.device)
+        check(lib().rc_postprocess_words(self.handle, _ptr(depth), _ptr(inst), ctypes.byref(params),
+                                         int(step), _ptr(cam_uid), _ptr(d), _ptr(drop), _ptr(lat),
+                                         _ptr(words), _stream(stream)))
+        return d, drop, lat, words
+
     def close(self):
         if self.handle:
             lib().rc_post_destroy(self.handle)
@@ -655,6 +673,10 @@ class Server:
         check(lib().rc_server_submit(self.handle, ctypes.byref(r), float(now), ctypes.byref(i)))
         self._inputs[i.value] = (link_pos, link_quat, cam_pos, cam_quat, intr)
         return i.value
+
+    def fail_next(self, n_batches=1):
+        """Report the next n_batches completed batches as failed (testing aid)."""
+        check(lib().rc_server_fail_next(self.handle, int(n_batches)))
 
     def poll(self, now):
         n = ctypes.c_int32()

@@ -109,6 +109,63 @@ def test_link_bvh_bit_exact():
         check_bvh(buf, sc.bvh_layout(b), lt[off[b]:off[b + 1]])
 
 
+def _align(x, a=256):
+    return (x + a - 1) // a * a
+
+
+@pytest.mark.parametrize("bodies_flat", [0, 1])
+def test_tlas_bit_exact(bodies_flat):
+    """The per-step top level (instance transforms, and with the top-level walk
+    schedule the node records) against the CPU model, for given poses,
+    including absent links (non-finite poses, a zero quaternion)."""
+    say(f"[tlas] 64 envs x 30 links, bodies_flat {bodies_flat}")
+    w = sg.robot_scene(2, 8, 2.5, 2, 16, 12, steps=1, label="tlas")
+    lp, lq = w["link_pos"][0].copy(), w["link_quat"][0].copy()
+    lp[3, 7, 0] = np.nan
+    lq[5, 0] = 0.0
+    lq[9, 29, 2] = np.inf
+    lp[9, 12, 2] = -np.inf
+    sc = make_scene(w)
+    sc.set_config(batched=False, bodies_flat=bodies_flat)
+    E, B = lp.shape[0], lp.shape[1]
+    sc.render(dev(w["cam_pos"]), dev(w["cam_quat"]), dev(w["intr"]), w["W"], w["H"], w["far"],
+              link_pos=dev(lp), link_quat=dev(lq))
+    buf = ws_bytes(sc.render_workspace(E, 2, w["W"], w["H"]))
+    meta = ws_bytes(sc.robot_ws)[:64 * B].view(np.float32).reshape(B, 16)
+    root = meta[:, 4:10]
+    n_rec = B - 1
+    nodes = buf[:E * n_rec * 64].view(np.float32).reshape(E, n_rec, 16)
+    x0 = _align(E * n_rec * 64)
+    xf = buf[x0:x0 + E * B * 48].view(np.float32).reshape(E, B, 12)
+    for e in range(E):
+        mx, mrec = lbvh.tlas(lp[e], lq[e], root)
+        assert np.array_equal(xf[e].view(np.uint32), mx.view(np.uint32)), f"transforms of env {e}"
+        if bodies_flat == 0:
+            g, mm = nodes[e].view(np.uint32), mrec.view(np.uint32)
+            bad = np.argwhere(g != mm)
+            assert bad.size == 0, (f"top level of env {e}: {len(bad)} words differ, first "
+                                   f"{[(int(r), int(c), nodes[e][r, c], mrec[r, c], g[r, c], mm[r, c]) for r, c in bad[:6]]}")
+
+
+def test_non_finite_link_poses_render_as_absent_links():
+    """Links with a non-finite pose or a zero quaternion are absent from their
+    environment (the oracle's reading); every schedule agrees."""
+    say("[render] 4 envs x 2 cams 37x29, links with non-finite poses")
+    w = sg.robot_scene(2, 2, 4.0, 2, 37, 29, steps=1, label="parity-ragged")
+    w["link_pos"] = w["link_pos"].copy()
+    w["link_quat"] = w["link_quat"].copy()
+    w["link_pos"][0, 0, 0:30:3, 1] = np.nan
+    w["link_quat"][0, 1, 1:30:2] = 0.0
+    w["link_quat"][0, 2, :, 3] = np.inf
+    sc = make_scene(w)
+    ref = oracle_render(w)
+    for flat in (1, 0):
+        sc.set_config(batched=False, bodies_flat=flat)
+        d, i, t = render(sc, w)
+        assert_parity(d, i, t, ref, w["far"], label=f"non-finite poses, bodies_flat {flat}")
+    assert not np.any((i.reshape(4, -1)[2] >= 0) & (i.reshape(4, -1)[2] < 30))
+
+
 # ---------------------------------------------------------------------------
 # rendering parity
 # ---------------------------------------------------------------------------
@@ -285,6 +342,39 @@ def test_post_matches_oracle(s0, with_uid, hw):
     assert np.array_equal(lat, rl), "latency draws differ"
     assert np.array_equal(drop, rd), "dropout masks differ"
     assert np.max(np.abs(out - ro)) <= 1e-5
+
+
+@pytest.mark.parametrize("hw", [(29, 37), (24, 36)])
+def test_post_raw_draws_bit_exact(hw):
+    """The raw Philox4x32-10 words of every pixel's draw (rc_postprocess_words,
+    the same code that makes the outputs) equal the oracle's Philox at the
+    documented counter (pixel, camera uid, step low 32 bits, step bits 32-47
+    shifted up 16, stream 0 in the low bits) with key = seed, at steps above
+    2^40; the outputs equal rc_postprocess's.  Odd sizes take the one-pixel
+    form, sizes divisible by four the four-pixel form."""
+    m = rc()
+    H, W = hw
+    say(f"[post] raw draws, 3 envs x 2 cams {H}x{W}")
+    depth, inst = sg.synthetic_frames(3, 2, H, W, 3)
+    kw = dict(seed=0x1234_5678_9ABC, sigma_abs=0.01, sigma_rel=0.02, p_drop=0.02, near=0.05,
+              far=3.0, fill=0.0, lat_min=1, lat_max=3)
+    uid = np.arange(6, dtype=np.uint32) * 11 + 7
+    s0 = (1 << 40) + (1 << 33) + 5
+    a, b = m.Post(3, 2, H, W, 3), m.Post(3, 2, H, W, 3)
+    p = m.post_params(**kw)
+    key = np.array([kw["seed"] & 0xFFFFFFFF, kw["seed"] >> 32], np.uint32)
+    for s in range(3):
+        step = s0 + s
+        o, dr, la, words = a.process_words(dev(depth[s]), dev(inst[s]), p, step, cam_uid=dev(uid))
+        o2, dr2, la2 = b.process(dev(depth[s]), dev(inst[s]), p, step, cam_uid=dev(uid))
+        torch.cuda.synchronize()
+        assert torch.equal(o, o2) and torch.equal(dr, dr2) and torch.equal(la, la2)
+        got = words.cpu().numpy().view(np.uint32).reshape(6, H * W, 4)
+        hi = ((step >> 32) & 0xFFFF) << 16
+        for ec in range(6):
+            for pix in range(H * W):
+                want = oracle.philox([pix, uid[ec], step & 0xFFFFFFFF, hi], key)
+                assert np.array_equal(got[ec, pix], want), (s, ec, pix)
 
 
 def test_post_reset_starts_a_new_sequence():

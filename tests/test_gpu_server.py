@@ -113,3 +113,31 @@ def test_memory_admission_waits_for_space():
         srv.submit(0.0, **reqs[2])
     assert srv.stats()["rejected"] == 1
     srv.close()
+
+
+def test_injected_failure_fails_only_that_batch_and_scene_survives():
+    """rc_server_fail_next: the failed batch's requests report a device
+    error; the resident scene then serves the same request bit-identically."""
+    import paper_2602_03002_amd as m
+    print("[server] injected batch failure", flush=True)
+    w = sg.robot_scene(2, 3, 3.0, 4, 16, 12, steps=1, label="serve")
+    sc = m.Scene(dev(w["terrain"]))
+    sc.set_robot(dev(w["link_tri"]), w["link_off"].tolist())
+    reqs = requests_for(w)
+    srv = m.Server(sc, n_streams=1, out_pixels=1 << 22, scratch_bytes=1 << 27)
+    before = run(srv, reqs, [1])[1]
+    srv.fail_next(1)
+    rid = srv.submit(time.perf_counter(), **reqs[1])
+    t_end = time.time() + 60
+    res = None
+    while res is None and time.time() < t_end:
+        srv.poll(time.perf_counter())
+        res = srv.next_result()
+    assert res is not None and res["id"] == rid and res["status"] == -3
+    srv.release(rid)
+    after = run(srv, reqs, [1])[1]
+    st = srv.stats()
+    srv.close()
+    for x, y in zip(before, after):
+        assert np.array_equal(x, y)
+    assert st["completed"] == 3 and st["in_flight"] == 0

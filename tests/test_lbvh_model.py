@@ -1,6 +1,7 @@
 """Pins for the CPU LBVH model: brute-force bit interleaving, the defining
 properties of the Karras hierarchy, and box containment."""
 import numpy as np
+import pytest
 
 from oracle import lbvh
 import scenegen as sg
@@ -131,3 +132,69 @@ def test_degenerate_triangles_are_unreachable():
 def test_single_degenerate_triangle():
     m = lbvh.build(np.array([[[0, 0, 0], [1, 1, 1], [2, 2, 2]]], np.float32))
     assert np.all(m["records"][0, :12] == lbvh.FAR_POINT)
+
+
+# ---------------------------------------------------------------------------
+# top level over the link instances
+# ---------------------------------------------------------------------------
+
+def _tlas_inputs(B=30, seed=7):
+    rng = np.random.default_rng(seed)
+    lp = rng.uniform(-0.6, 0.6, (B, 3)).astype(np.float32) + np.float32([3.0, -2.0, 0.8])
+    lq = rng.normal(size=(B, 4)).astype(np.float32)
+    half = rng.uniform(0.03, 0.15, (B, 3))
+    root = np.stack([-half[:, 0], half[:, 0], -half[:, 1], half[:, 1], -half[:, 2], half[:, 2]],
+                    1).astype(np.float32)
+    return lp, lq, root
+
+
+def test_tlas_transforms_match_scipy_and_boxes_hold_the_posed_link():
+    from scipy.spatial.transform import Rotation
+    lp, lq, root = _tlas_inputs()
+    xf, rec = lbvh.tlas(lp, lq, root)
+    for b in range(len(lp)):
+        R = Rotation.from_quat(lq[b].astype(np.float64)).as_matrix()
+        assert np.max(np.abs(xf[b, :9].reshape(3, 3) - R.T)) < 1e-6
+        assert np.array_equal(xf[b, 9:], lp[b])
+        corners = np.array([[root[b, i], root[b, 2 + j], root[b, 4 + k]]
+                            for i in (0, 1) for j in (0, 1) for k in (0, 1)], np.float64)
+        world = corners @ R.T + lp[b].astype(np.float64)
+        lo, hi = lbvh.instance(lp[b], lq[b], root[b])[1][0::2], lbvh.instance(lp[b], lq[b], root[b])[1][1::2]
+        assert np.all(world >= lo) and np.all(world <= hi)
+
+
+@pytest.mark.parametrize("B", [2, 3, 30, 64])
+def test_tlas_hierarchy_properties(B):
+    lp, lq, root = _tlas_inputs(B, seed=B)
+    xf, rec = lbvh.tlas(lp, lq, root)
+    ints = rec.view(np.int32)
+    c0, c1, par, sib = ints[:, 12], ints[:, 13], ints[:, 14], ints[:, 15]
+    leaves = sorted(~c for c in np.concatenate([c0, c1]) if c < 0)
+    assert leaves == list(range(B))  # every instance exactly once
+    assert par[0] == -1
+    for i in range(B - 1):
+        for h, c in enumerate((c0[i], c1[i])):
+            other = (c1[i], c0[i])[h]
+            if c >= 0:
+                assert par[c] == i and sib[c] == other
+                child = rec[c, :12].reshape(2, 6)
+                box = rec[i, 6 * h:6 * h + 6]
+                assert np.all(child[:, 0::2] >= box[0::2]) and np.all(child[:, 1::2] <= box[1::2])
+            else:
+                box = rec[i, 6 * h:6 * h + 6]
+                assert np.array_equal(box, lbvh.instance(lp[~c], lq[~c], root[~c])[1])
+
+
+def test_tlas_absent_instances():
+    lp, lq, root = _tlas_inputs(8, seed=3)
+    lp[2, 1] = np.nan
+    lq[5] = 0.0
+    lq[6, 0] = np.inf
+    xf, rec = lbvh.tlas(lp, lq, root)
+    ints = rec.view(np.int32)
+    for b in (2, 5, 6):
+        assert np.array_equal(xf[b], np.float32([1, 0, 0, 0, 1, 0, 0, 0, 1, 1e30, 1e30, 1e30]))
+    for i in range(7):
+        for h, c in enumerate((ints[i, 12], ints[i, 13])):
+            if c < 0 and ~c in (2, 5, 6):
+                assert np.all(rec[i, 6 * h:6 * h + 6] == np.float32(1e30))

@@ -140,3 +140,30 @@ def test_latency_percentiles_nearest_rank():
     st2 = s2.stats()
     times.sort()
     assert st2["p50_s"] == pytest.approx(times[4]) and st2["p99_s"] == pytest.approx(times[9])
+
+
+def test_injected_failure_fails_only_that_batch():
+    """rc_server_fail_next: the requests of the next batch report a device
+    error; the batch's memory comes back and later batches succeed."""
+    s = server(out_pixels=4 * PX)
+    a = s.submit(0.0, 1, 2, 64, 48)
+    s.poll(0.0)                       # A starts
+    s.fail_next(1)
+    b = s.submit(1e-4, 1, 2, 64, 48)  # waits: the only stream is busy
+    t_a = LAUNCH + 2 * PX * PER_RAY
+    s.poll(t_a)                       # A completes (reported failed), B starts
+    assert b"injected" in m.lib().rc_last_error()
+    r = drain(s)
+    assert [x["id"] for x in r] == [a] and r[0]["status"] == -3
+    s.release(a)
+    s.poll(t_a + LAUNCH + 2 * PX * PER_RAY)
+    r = drain(s)
+    assert [x["id"] for x in r] == [b] and r[0]["status"] == 0
+    s.release(b)
+    c = s.submit(1.0, 2, 2, 64, 48)   # all output memory is free again
+    s.poll(1.0)
+    s.poll(1.0 + LAUNCH + 4 * PX * PER_RAY)
+    r = drain(s)
+    assert [x["id"] for x in r] == [c] and r[0]["status"] == 0
+    st = s.stats()
+    assert st["completed"] == 3 and st["in_flight"] == 0 and st["queued"] == 0
