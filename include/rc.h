@@ -173,6 +173,22 @@ rc_status rc_render_size(const rc_scene* scene, int32_t n_env, int32_t n_cam, in
 rc_status rc_render(const rc_scene* scene, const rc_render_args* args, void* ws,
                     size_t ws_bytes, rc_stream stream);
 
+/* rc_render for callers that cannot allocate device memory or hand over a
+ * workspace (code under stream capture, tight serving loops, hosts that
+ * forbid allocation).  Same arguments, results and errors as rc_render,
+ * without ws: the workspace is a static device array of the library, 32 MiB
+ * per GPU, held from the library's first use on that GPU until the process
+ * ends, and the call itself allocates nothing.  It holds the top level of up
+ * to about 8,000 environments of 30 links and an exact-pass list of 2^17
+ * rays (a render that hands more rays to the exact pass re-casts every pixel
+ * exactly: correct, slower).  A render whose workspace would exceed 32 MiB
+ * fails with RC_ERR_WORKSPACE before anything is enqueued.  The array of the
+ * current device is used (the stream must belong to it), and every call on
+ * a GPU shares it: calls that overlap on one GPU (other streams, other
+ * threads) race and must be serialised by the caller.  Each call writes all
+ * it reads, so no state carries over between calls. */
+rc_status rc_render_noalloc(const rc_scene* scene, const rc_render_args* args, rc_stream stream);
+
 /* Number of rays the last rc_render on this workspace sent to the exact pass
  * (a diagnostic), and how many of them it re-cast in full (`recast`, may be
  * NULL).  Synchronises `stream`. */

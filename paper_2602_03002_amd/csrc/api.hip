@@ -6,6 +6,7 @@
 #include <atomic>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -436,6 +437,68 @@ rc_status rc_render_counts(const rc_scene* scene, const rc_render_args* a, uint3
     L.counts = counts;
     hipError_t e = run_plain(scene, L, ws, scene->cfg(), (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "rc_render_counts: launch");
+    return RC_OK;
+}
+
+// ---- render without a caller workspace ----
+//
+// rc_render_noalloc takes its workspace from `scratch`, a device array of this
+// file that the loader allocates once per GPU with the library's code object.
+// In host code the array's name stands for a host-side shadow, not a device
+// address: its address on the current device comes from hipGetSymbolAddress,
+// taken once per device at that device's first call and kept here.
+
+constexpr size_t kNoallocBytes = (size_t)32 << 20;
+// exact-pass list of the no-allocation form: 2^17 entries (4 MiB); a render
+// that hands more rays to the exact pass re-casts every pixel exactly
+constexpr int64_t kNoallocListRays = (int64_t)16 << 17;
+constexpr int kNoallocDevices = 64;
+
+static __device__ __align__(256) unsigned char scratch[kNoallocBytes];
+
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kNoallocDevices] = {};
+
+static rc_status scratch_of_current_device(void** out, const char* who) {
+    const std::string w(who);
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, who);
+    if (dev < 0 || dev >= kNoallocDevices)
+        return fail(RC_ERR_UNSUPPORTED, w + ": device index beyond " + std::to_string(kNoallocDevices));
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, who);
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return RC_OK;
+}
+
+rc_status rc_render_noalloc(const rc_scene* scene, const rc_render_args* a, rc_stream stream) {
+    const char* who = "rc_render_noalloc";
+    if (!scene || !a) return fail(RC_ERR_INVALID_ARG, "rc_render_noalloc: NULL scene or args");
+    if (!render_dims_ok(a->n_env, a->n_cam, a->width, a->height))
+        return fail(RC_ERR_INVALID_ARG, "rc_render_noalloc: sizes must be >= 1, width and height "
+                                        "<= 65535, at most 2^32 - 1 rays");
+    const int64_t n_rays = (int64_t)a->n_env * a->n_cam * a->width * a->height;
+    const int64_t cap = n_rays < kNoallocListRays ? n_rays : kNoallocListRays;
+    const size_t need = render_layout(a->n_env, n_rays, scene->n_links, 0,
+                                      (int64_t)a->n_env * a->n_cam, cap).end;
+    if (need > kNoallocBytes)
+        return fail(RC_ERR_WORKSPACE, "rc_render_noalloc: this render needs " + std::to_string(need) +
+                                          " bytes of scratch, the static scratch holds " +
+                                          std::to_string(kNoallocBytes) + " (use rc_render)");
+    void* ws = nullptr;
+    rc_status st = scratch_of_current_device(&ws, who);
+    if (st != RC_OK) return st;
+    RenderLaunch L;
+    st = prep_plain(scene, a, ws, kNoallocBytes, L, who, cap);
+    if (st != RC_OK) return st;
+    hipError_t e = run_plain(scene, L, ws, scene->cfg(), (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "rc_render_noalloc: launch");
     return RC_OK;
 }
 

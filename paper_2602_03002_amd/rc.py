@@ -26,7 +26,7 @@ EXPORTED = [
     "rc_version", "rc_status_string", "rc_last_error",
     "rc_scene_size", "rc_scene_create", "rc_scene_destroy",
     "rc_robot_size", "rc_robot_meshes",
-    "rc_render_size", "rc_render", "rc_render_exact_count", "rc_render_counts",
+    "rc_render_size", "rc_render", "rc_render_exact_count", "rc_render_counts", "rc_render_noalloc",
     "rc_post_size", "rc_post_create", "rc_post_reset", "rc_postprocess", "rc_post_destroy",
     "rc_postprocess_words",
     "rc_downsample", "rc_heightmap",
@@ -174,6 +174,7 @@ def lib():
         L.rc_render_exact_count.argtypes = [vp, i32, i32, i32, i32, vp, ctypes.POINTER(i64),
                                             ctypes.POINTER(i64), vp]
         L.rc_render.argtypes = [vp, ctypes.POINTER(RenderArgs), vp, sz, vp]
+        L.rc_render_noalloc.argtypes = [vp, ctypes.POINTER(RenderArgs), vp]
         L.rc_render_counts.argtypes = [vp, ctypes.POINTER(RenderArgs), vp, vp, sz, vp]
         L.rc_post_size.argtypes = [i32, i32, i32, i32, i32, ctypes.POINTER(sz)]
         L.rc_post_create.argtypes = [i32, i32, i32, i32, i32, vp, sz, ctypes.POINTER(vp)]
@@ -328,7 +329,7 @@ class Scene:
         return (c.value, r.value) if recast else c.value
 
     def _plain_args(self, cam_pos, cam_quat, intr, width, height, far_plane, link_pos, link_quat,
-                    depth_mode, out, ids, timing=None, rand=None):
+                    depth_mode, out, ids, timing=None, rand=None, want_ws=True):
         E, C = cam_pos.shape[0], cam_pos.shape[1]
         _dev_f32(cam_pos, (E, C, 3), "cam_pos")
         _dev_f32(cam_quat, (E, C, 4), "cam_quat")
@@ -350,7 +351,7 @@ class Scene:
                        ctypes.pointer(rand) if rand is not None else None)
         a._ev = ev  # keep the event array and randomisation alive with the argument block
         a._rand = rand
-        return a, (depth, inst, tri), self.render_workspace(E, C, width, height)
+        return a, (depth, inst, tri), (self.render_workspace(E, C, width, height) if want_ws else None)
 
     def render(self, cam_pos, cam_quat, intr, width, height, far_plane, link_pos=None,
                link_quat=None, depth_mode=RC_DEPTH_PLANAR, out=None, ids=True, stream=None,
@@ -362,6 +363,16 @@ class Scene:
                                        link_quat, depth_mode, out, ids, timing, rand)
         check(lib().rc_render(self.handle, ctypes.byref(a), ctypes.c_void_p(ws.ptr), ws.nbytes,
                               _stream(stream)))
+        return outs
+
+    def render_noalloc(self, cam_pos, cam_quat, intr, width, height, far_plane, link_pos=None,
+                       link_quat=None, depth_mode=RC_DEPTH_PLANAR, out=None, ids=True, stream=None):
+        """rc_render_noalloc: render() without a workspace (the library's static
+        per-GPU scratch; calls on one GPU must not overlap).  Pass `out` to
+        allocate nothing here either."""
+        a, outs, _ = self._plain_args(cam_pos, cam_quat, intr, width, height, far_plane, link_pos,
+                                      link_quat, depth_mode, out, ids, want_ws=False)
+        check(lib().rc_render_noalloc(self.handle, ctypes.byref(a), _stream(stream)))
         return outs
 
     def render_counts(self, cam_pos, cam_quat, intr, width, height, far_plane, link_pos=None,
