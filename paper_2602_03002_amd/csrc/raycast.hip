@@ -482,6 +482,9 @@ __device__ __forceinline__ void traverse(const Node* __restrict__ nodes, int n_n
 }
 
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ float uni_f(float v) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
 
 // Enter link b of env e: take the ray to the link frame (o_b = R_b^T (o - t_b),
 // d_b = R_b^T d) and traverse the link's hierarchy under the current bound.
@@ -497,9 +500,14 @@ __device__ __forceinline__ void enter_link(const RenderLaunch& a, int e, int b, 
     double o64[3], d64[3], rx, ry;
     pixel_ray64(px.cam, px.x, px.y, o64, d64, rx, ry);
     const double qx = o64[0] - (double)X.t[0], qy = o64[1] - (double)X.t[1], qz = o64[2] - (double)X.t[2];
-    const float lox = (float)((double)X.m[0] * qx + (double)X.m[1] * qy + (double)X.m[2] * qz);
-    const float loy = (float)((double)X.m[3] * qx + (double)X.m[4] * qy + (double)X.m[5] * qz);
-    const float loz = (float)((double)X.m[6] * qx + (double)X.m[7] * qy + (double)X.m[8] * qz);
+    float lox = (float)((double)X.m[0] * qx + (double)X.m[1] * qy + (double)X.m[2] * qz);
+    float loy = (float)((double)X.m[3] * qx + (double)X.m[4] * qy + (double)X.m[5] * qz);
+    float loz = (float)((double)X.m[6] * qx + (double)X.m[7] * qy + (double)X.m[8] * qz);
+    if constexpr (!EXACT) {  // the fast pass's wavefront shares one camera, so one o_b
+        lox = uni_f(lox);
+        loy = uni_f(loy);
+        loz = uni_f(loz);
+    }
     const float ldx = (float)((double)X.m[0] * d64[0] + (double)X.m[1] * d64[1] + (double)X.m[2] * d64[2]);
     const float ldy = (float)((double)X.m[3] * d64[0] + (double)X.m[4] * d64[1] + (double)X.m[5] * d64[2]);
     const float ldz = (float)((double)X.m[6] * d64[0] + (double)X.m[7] * d64[1] + (double)X.m[8] * d64[2]);
@@ -564,7 +572,12 @@ __device__ __forceinline__ Hit cast_ray(const RenderLaunch& a, const CamRef& cam
                                         Cnt& cnt) {
     double o64[3], d64[3], rx, ry;
     pixel_ray64(cam, x, y, o64, d64, rx, ry);
-    const float ox = (float)o64[0], oy = (float)o64[1], oz = (float)o64[2];
+    float ox = (float)o64[0], oy = (float)o64[1], oz = (float)o64[2];
+    if constexpr (WAVE) {  // one camera per wavefront: its origin lives in scalar registers
+        ox = uni_f(ox);
+        oy = uni_f(oy);
+        oz = uni_f(oz);
+    }
     const float dx = (float)d64[0], dy = (float)d64[1], dz = (float)d64[2];
     const double scale = a.depth_mode == RC_DEPTH_RANGE ? sqrt(rx * rx + ry * ry + 1.0) : 1.0;
     Hit h;
