@@ -575,13 +575,19 @@ typedef struct {
     int64_t key_offset;    /* byte offset: uint64 [n_prim] sorted Morton keys */
     int32_t max_depth;     /* deepest internal node (root = 0) */
     int32_t reserved;
+    int64_t wide_offset;   /* byte offset: 4-wide records, 128 B each, one per node record */
 } rc_bvh_layout;
 
 /* Layout of the terrain hierarchy (which = -1) or of link `which` inside the
  * workspace given to rc_scene_create / rc_robot_meshes.  Node record:
  * float box0[6] = (lo.x, hi.x, lo.y, hi.y, lo.z, hi.z), float box1[6],
  * int32 child0, child1, parent, sibling; child >= 0 is an internal node,
- * child < 0 is leaf ~child; boxes are padded outwards for FP32 traversal. */
+ * child < 0 is leaf ~child; boxes are padded outwards for FP32 traversal.
+ * 4-wide record of node n (the fast pass's terrain walk): the children of n,
+ * each internal child replaced by its two children (2-4 slots, in the binary
+ * children's order, unused slots the far point 1e30 with child word 0), as
+ * float lo.x[4], hi.x[4], lo.y[4], hi.y[4], lo.z[4], hi.z[4], int32 child[4],
+ * then 16 bytes of zeros. */
 rc_status rc_bvh_layout_of(const rc_scene* scene, int32_t which, rc_bvh_layout* out);
 
 #ifdef __cplusplus

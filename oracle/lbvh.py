@@ -309,6 +309,34 @@ def tlas(link_pos, link_quat, root):
     return xf, rec
 
 
+def collapse4(records):
+    """4-wide records [m, 32] f32 of binary records [m, 16]: for node n, its two
+    children in order, each internal child (one whose box is not the far point)
+    replaced by that child's two children; unused slots get the far-point box
+    and child word 0.  Columns: lo.x[4], hi.x[4], lo.y[4], hi.y[4], lo.z[4],
+    hi.z[4], int32 child[4], four zero words."""
+    m = len(records)
+    ints = records.view(np.int32)
+    out = np.zeros((m, 32), np.float32)
+    oi = out.view(np.int32)
+    for n in range(m):
+        slots = []
+        for h in range(2):
+            c = int(ints[n, 12 + h])
+            bx = records[n, 6 * h:6 * h + 6]
+            if c < 0 or c >= m or bx[0] == FAR_POINT:
+                slots.append((bx, c))
+            else:
+                slots.append((records[c, 0:6], int(ints[c, 12])))
+                slots.append((records[c, 6:12], int(ints[c, 13])))
+        while len(slots) < 4:
+            slots.append((np.full(6, FAR_POINT, np.float32), 0))
+        for k, (bx, c) in enumerate(slots):
+            out[n, k:24:4] = bx
+            oi[n, 24 + k] = c
+    return out
+
+
 def _leaf_range(c0, c1, i):
     """First and last sorted leaf below internal node i."""
     lo, hi = i, i

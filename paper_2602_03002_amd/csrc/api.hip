@@ -324,6 +324,7 @@ rc_status rc_render_size(const rc_scene* scene, int32_t n_env, int32_t n_cam, in
 
 static void fill_scene(const rc_scene* scene, RenderLaunch& L) {
     L.terrain_nodes = (const Node*)(scene->ws + scene->terrain.nodes);
+    L.terrain_wide = (const float4*)(scene->ws + scene->terrain.wide);
     L.terrain_tris = (const float*)(scene->ws + scene->terrain.tris);
     L.terrain_tri_id = (const int32_t*)(scene->ws + scene->terrain.tri_id);
     L.link_nodes = (const Node*)scene->robot_ws;
@@ -1069,6 +1070,7 @@ rc_status rc_bvh_layout_of(const rc_scene* scene, int32_t which, rc_bvh_layout* 
     out->key_offset = (int64_t)L->keys;
     out->max_depth = depth;
     out->reserved = 0;
+    out->wide_offset = (int64_t)L->wide;
     return RC_OK;
 }
 

@@ -359,6 +359,41 @@ __global__ void k_single_leaf(const float* __restrict__ box, Node* __restrict__ 
 
 inline unsigned nblk(int64_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
 
+// 4-wide records, one per binary node (the layout is described with
+// kWideRec).  Every node gets one, since a walk may enter the hierarchy at any
+// node; slots keep the binary children's order (child 0's side first).
+__global__ void k_collapse4(const Node* __restrict__ nodes, int64_t n_nodes, float4* __restrict__ out) {
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= n_nodes) return;
+    const Node N = nodes[n];
+    float b[4][6];
+    int c[4];
+    int m = 0;
+    for (int h = 0; h < 2; ++h) {
+        const int ch = h ? N.c1 : N.c0;
+        const float* bx = h ? N.b1 : N.b0;
+        if (ch < 0 || ch >= n_nodes || bx[0] == kFarBox) {  // leaf, or a child no ray reaches
+            for (int k = 0; k < 6; ++k) b[m][k] = bx[k];
+            c[m++] = ch;
+        } else {
+            const Node C = nodes[ch];
+            for (int k = 0; k < 6; ++k) b[m][k] = C.b0[k];
+            c[m++] = C.c0;
+            for (int k = 0; k < 6; ++k) b[m][k] = C.b1[k];
+            c[m++] = C.c1;
+        }
+    }
+    for (; m < 4; ++m) {
+        for (int k = 0; k < 6; ++k) b[m][k] = kFarBox;
+        c[m] = 0;
+    }
+    float4* o = out + kWideRec * n;
+    for (int k = 0; k < 6; ++k) o[k] = make_float4(b[0][k], b[1][k], b[2][k], b[3][k]);
+    o[6] = make_float4(__int_as_float(c[0]), __int_as_float(c[1]), __int_as_float(c[2]),
+                       __int_as_float(c[3]));
+    o[7] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+}
+
 }  // namespace
 
 BvhLayout bvh_layout(int64_t n, size_t base) {
@@ -369,6 +404,7 @@ BvhLayout bvh_layout(int64_t n, size_t base) {
     L.n_blocks_red = (n + kThreads - 1) / kThreads;
     size_t o = align_up(base);
     L.nodes = o;     o = align_up(o + (size_t)L.n_nodes * sizeof(Node));
+    L.wide = o;      o = align_up(o + (size_t)L.n_nodes * kWideRec * sizeof(float4));
     L.tris = o;      o = align_up(o + (size_t)n * 36);
     L.tri_id = o;    o = align_up(o + (size_t)n * 4);
     L.keys = o;      o = align_up(o + (size_t)n * 8);
@@ -408,6 +444,8 @@ hipError_t launch_blas_build(const float* tri, int64_t n, char* ws, const BvhLay
         hipLaunchKernelGGL(k_drop_degenerate, dim3(1), dim3(kThreads), 0, s, tri, n, box);
         hipLaunchKernelGGL(k_single_leaf, dim3(1), dim3(1), 0, s, box, nodes, tri, tris, tri_id,
                            keys, depth);
+        hipLaunchKernelGGL(k_collapse4, dim3(1), dim3(kThreads), 0, s, nodes, (int64_t)1,
+                           (float4*)(ws + L.wide));
         return hipGetLastError();
     }
     hipLaunchKernelGGL(k_reduce_bounds, dim3(1), dim3(kThreads), 0, s, partial, L.n_blocks_red, cb);
@@ -436,6 +474,8 @@ hipError_t launch_blas_build(const float* tri, int64_t n, char* ws, const BvhLay
     hipLaunchKernelGGL(k_depth, dim3(nblk(n - 1)), dim3(kThreads), 0, s, nodes, n - 1, depth);
     hipLaunchKernelGGL(k_pad_and_gather, dim3(nblk(n)), dim3(kThreads), 0, s, nodes, n - 1, tri, vals,
                        n, tris, tri_id);
+    hipLaunchKernelGGL(k_collapse4, dim3(nblk(n - 1)), dim3(kThreads), 0, s, nodes, n - 1,
+                       (float4*)(ws + L.wide));
     return hipGetLastError();
 }
 

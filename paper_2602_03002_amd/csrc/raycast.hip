@@ -406,7 +406,7 @@ __device__ __forceinline__ void tri_test(const float* __restrict__ v,
 // checked and the loop is bounded (a valid hierarchy needs fewer than
 // 2 n_nodes + 2 steps), so a corrupt hierarchy ends the ray instead of
 // faulting or spinning.
-constexpr int kStack = 12;
+constexpr int kStack = 16;
 constexpr int kLanes = 64 * kWavesPerBlock;
 
 template <int OCT = -1, bool VERT = false, typename Cnt, typename Leaf>
@@ -481,6 +481,104 @@ __device__ __forceinline__ void traverse(const Node* __restrict__ nodes, int n_n
     }
 }
 
+// The fast pass's terrain walk, over the 4-wide records (kWideRec): per lane,
+// nearest first, with the triangle tests gathered across the wavefront.
+// A visit tests the record's four boxes at once.  Leaf slots that the ray
+// reaches are parked (the record's index and a slot mask) and the lane pauses;
+// the internal slots it reaches are ordered by entry distance, the nearest
+// entered next and the others pushed farthest first on the lane's LDS stack.
+// The wavefront tests the parked leaves of all its lanes in one pass once the
+// lanes still walking are at most a quarter of the live ones (or none), so a
+// pass of the triangle test serves many lanes rather than the few that reached
+// a leaf at the same step.  A paused lane's next record was chosen under the
+// bound it had before its leaves were tested; the children of that record are
+// tested under the tightened bound.  Every step moves a walking lane (the
+// budget bounds these) or empties the parked slots, so the loop ends.  A push
+// onto a full stack is dropped and sends the ray to the exact pass's full
+// re-cast (h.tu = 0), so no result depends on the stack's depth.
+constexpr int kGatherNum = 3, kGatherDen = 4;  // test once parked >= 3/4 of live lanes
+
+template <int OCT, typename Cnt, typename Leaf>
+__device__ __forceinline__ void traverse4(const float4* __restrict__ wide, int n_nodes, int n_prim,
+                                          const Slab& r, Hit& h, Cnt& cnt, Leaf&& leaf, int start,
+                                          uint32_t* stk) {
+    int cur = start;
+    int sp = 0;
+    int budget = 2 * n_nodes + 2;
+    int pn = 0;       // record whose leaf slots are parked
+    uint32_t pm = 0;  // parked slot mask
+    bool walk = true;
+    for (;;) {
+        if (walk && pm == 0u) {
+            if ((unsigned)cur >= (unsigned)n_nodes || --budget < 0) {
+                walk = false;
+            } else {
+                const float4* np = wide + kWideRec * (int64_t)cur;
+                const float4 xl = np[0], xh = np[1], yl = np[2], yh = np[3], zl = np[4], zh = np[5];
+                const int4 ch = *reinterpret_cast<const int4*>(np + 6);
+                cnt.node();
+                float tn[4];
+                bool hit[4];
+                hit[0] = slab<OCT>(xl.x, xh.x, yl.x, yh.x, zl.x, zh.x, r, h.tmax, tn[0]);
+                hit[1] = slab<OCT>(xl.y, xh.y, yl.y, yh.y, zl.y, zh.y, r, h.tmax, tn[1]);
+                hit[2] = slab<OCT>(xl.z, xh.z, yl.z, yh.z, zl.z, zh.z, r, h.tmax, tn[2]);
+                hit[3] = slab<OCT>(xl.w, xh.w, yl.w, yh.w, zl.w, zh.w, r, h.tmax, tn[3]);
+                const int c[4] = {ch.x, ch.y, ch.z, ch.w};
+                uint32_t lm = 0;
+                float d[4];
+                int e[4];
+                for (int k = 0; k < 4; ++k) {
+                    const bool lf = hit[k] & (c[k] < 0) & ((unsigned)~c[k] < (unsigned)n_prim);
+                    lm |= (lf ? 1u : 0u) << k;
+                    d[k] = hit[k] & (c[k] >= 0) ? tn[k] : INFINITY;
+                    e[k] = c[k];
+                }
+                pm = lm;
+                pn = cur;
+                // sorting network on (distance, child): nearest in slot 0
+                auto cx = [&](int i, int j) {
+                    const bool sw = d[j] < d[i];
+                    const float di = d[i], dj = d[j];
+                    const int ei = e[i], ej = e[j];
+                    d[i] = sw ? dj : di;
+                    d[j] = sw ? di : dj;
+                    e[i] = sw ? ej : ei;
+                    e[j] = sw ? ei : ej;
+                };
+                cx(0, 1); cx(2, 3); cx(0, 2); cx(1, 3); cx(1, 2);
+                if (d[0] < INFINITY) {
+                    for (int k = 3; k >= 1; --k) {
+                        if (d[k] < INFINITY) {
+                            if (sp < kStack) stk[kLanes * sp++] = (uint32_t)e[k];
+                            else h.tu = 0.0f;
+                        }
+                    }
+                    cur = e[0];
+                } else if (sp == 0) {
+                    walk = false;
+                } else {
+                    cur = (int)stk[kLanes * --sp];
+                }
+            }
+        }
+        const bool parked = pm != 0u;
+        const uint64_t P = __ballot(parked);
+        const uint64_t Wk = __ballot(walk && !parked);
+        if (P != 0ull &&
+            (Wk == 0ull || __popcll(P) * kGatherDen >= __popcll(P | Wk) * kGatherNum)) {
+            if (parked) {
+                const int4 ch = *reinterpret_cast<const int4*>(wide + kWideRec * (int64_t)pn + 6);
+                while (pm) {
+                    const int k = __builtin_ctz(pm);
+                    pm &= pm - 1u;
+                    leaf(~(k == 0 ? ch.x : (k == 1 ? ch.y : (k == 2 ? ch.z : ch.w))));
+                }
+            }
+        }
+        if (!walk && pm == 0u) return;
+    }
+}
+
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
 __device__ __forceinline__ float uni_f(float v) {
     return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
@@ -532,29 +630,46 @@ __device__ __forceinline__ void enter_link(const RenderLaunch& a, int e, int b, 
 constexpr int kPacketTerrain = 1;  // walk the terrain as a wavefront packet
 constexpr int kFlatBodies = 2;     // cull links against the wavefront's cone instead of the top level
 
+// Wavefront reductions by DPP lane moves (no LDS round trips; all 64 lanes
+// must be active): shifts within each row of 16 lanes leave the row's result
+// in its last lane, two row broadcasts carry those on to lane 63, whose value
+// is returned to every lane as a scalar.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_mov(float v) {
+    return __int_as_float(
+        __builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), CTRL, ROWS, 0xF, false));
+}
+template <typename Op>
+__device__ __forceinline__ float wave_reduce(float v, Op op) {
+    v = op(v, dpp_mov<0x111, 0xF>(v));  // row_shr:1
+    v = op(v, dpp_mov<0x112, 0xF>(v));  // row_shr:2
+    v = op(v, dpp_mov<0x114, 0xF>(v));  // row_shr:4
+    v = op(v, dpp_mov<0x118, 0xF>(v));  // row_shr:8
+    v = op(v, dpp_mov<0x142, 0xA>(v));  // row_bcast:15 into rows 1 and 3
+    v = op(v, dpp_mov<0x143, 0xC>(v));  // row_bcast:31 into rows 2 and 3
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
 __device__ __forceinline__ float wave_sum(float v) {
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+    return wave_reduce(v, [](float x, float y) { return x + y; });
 }
 __device__ __forceinline__ float wave_min(float v) {
-    for (int off = 32; off >= 1; off >>= 1) v = fminf(v, __shfl_xor(v, off, 64));
-    return v;
+    return wave_reduce(v, [](float x, float y) { return fminf(x, y); });
+}
+__device__ __forceinline__ float wave_max(float v) {
+    return wave_reduce(v, [](float x, float y) { return fmaxf(x, y); });
 }
 
-// World bounding sphere of link b of env e: the centre of its local (padded)
-// box under the pose, the box's half-diagonal as radius, widened by 1% + 1 mm
-// so FP32 rounding cannot cull a reachable link.
+// World bounding sphere of link b of env e, written by the top-level build:
+// the centre of its local (padded) box under the pose, the box's
+// half-diagonal as radius, widened by 1% + 1 mm so FP32 rounding cannot cull
+// a reachable link.
 __device__ __forceinline__ void link_sphere(const RenderLaunch& a, int e, int b, float& cx, float& cy,
                                             float& cz, float& rad) {
-    const InstXform X = a.xf[(int64_t)e * a.n_links + b];
-    const float* rb = a.link_meta[b].root;
-    const float lx = 0.5f * (rb[0] + rb[1]), ly = 0.5f * (rb[2] + rb[3]), lz = 0.5f * (rb[4] + rb[5]);
-    const float hx = 0.5f * (rb[1] - rb[0]), hy = 0.5f * (rb[3] - rb[2]), hz = 0.5f * (rb[5] - rb[4]);
-    rad = sqrtf(__fmaf_rn(hz, hz, __fmaf_rn(hy, hy, hx * hx))) * 1.01f + 1e-3f;
-    // centre = R c + t with X.m = R^T
-    cx = __fmaf_rn(X.m[6], lz, __fmaf_rn(X.m[3], ly, X.m[0] * lx)) + X.t[0];
-    cy = __fmaf_rn(X.m[7], lz, __fmaf_rn(X.m[4], ly, X.m[1] * lx)) + X.t[1];
-    cz = __fmaf_rn(X.m[8], lz, __fmaf_rn(X.m[5], ly, X.m[2] * lx)) + X.t[2];
+    const float4 S = *reinterpret_cast<const float4*>(a.xf[(int64_t)e * a.n_links + b].s);
+    cx = S.x;
+    cy = S.y;
+    cz = S.z;
+    rad = S.w;
 }
 
 // One pixel ray: robot bodies first, then the terrain under their bound
@@ -720,13 +835,7 @@ __device__ __forceinline__ Hit cast_ray(const RenderLaunch& a, const CamRef& cam
             const float ex = ox + h.tmax * dx, ey = oy + h.tmax * dy, ez = oz + h.tmax * dz;
             float f[6] = {fminf(ox, ex), fmaxf(ox, ex), fminf(oy, ey), fmaxf(oy, ey),
                           fminf(oz, ez), fmaxf(oz, ez)};
-            for (int off = 32; off >= 1; off >>= 1)
-                for (int k = 0; k < 6; ++k) {
-                    const float v = __shfl_xor(f[k], off, 64);
-                    f[k] = (k & 1) ? fmaxf(f[k], v) : fminf(f[k], v);
-                }
-            for (int k = 0; k < 6; ++k)
-                f[k] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(f[k])));
+            for (int k = 0; k < 6; ++k) f[k] = (k & 1) ? wave_max(f[k]) : wave_min(f[k]);
             for (int guard = 0; guard < 64; ++guard) {
                 const Node& N = a.terrain_nodes[entry];
                 cnt.node();
@@ -752,13 +861,14 @@ __device__ __forceinline__ Hit cast_ray(const RenderLaunch& a, const CamRef& cam
             };
             if (!(MODE & kPacketTerrain)) {
                 // a wavefront whose rays share one direction octant (the common
-                // case for a tile) runs the octant's specialised box tests
+                // case for a tile) runs the octant's specialised box tests on
+                // the 4-wide records; a mixed wavefront walks the binary ones
                 const int oct = slab_octant(ws);
                 const int oct0 = uni(oct);
                 if (WAVE && !EXACT && __ballot(oct != oct0) == 0ull) {
                     switch (oct0) {
 #define RC_OCT(K) \
-    case K: traverse<K>(a.terrain_nodes, n_nodes, a.n_terrain, ws, h, cnt, leaf, entry, stk); break;
+    case K: traverse4<K>(a.terrain_wide, n_nodes, a.n_terrain, ws, h, cnt, leaf, entry, stk); break;
                         RC_OCT(0) RC_OCT(1) RC_OCT(2) RC_OCT(3) RC_OCT(4) RC_OCT(5) RC_OCT(6) RC_OCT(7)
 #undef RC_OCT
                     }

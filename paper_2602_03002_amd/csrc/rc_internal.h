@@ -23,6 +23,14 @@ struct alignas(16) Node {
 };
 static_assert(sizeof(Node) == 64, "node record is one 64-byte line");
 
+// 4-wide record of binary node n (the fast pass's terrain walk): n's two
+// children, each internal one replaced by its own two children, so one record
+// spans two levels.  Slot-major float4 columns: lo.x, hi.x, lo.y, hi.y, lo.z,
+// hi.z (one lane per slot), then the four child words (>= 0 internal node,
+// < 0 leaf ~i) and one float4 of padding: 128 bytes, two cache lines.  An
+// unused slot has the far-point box.
+constexpr int kWideRec = 8;
+
 // Per-link hierarchy directory entry (device), 64 bytes.
 // Bases are element offsets from the start of the robot workspace.
 struct alignas(16) LinkMeta {
@@ -36,12 +44,14 @@ struct alignas(16) LinkMeta {
 static_assert(sizeof(LinkMeta) == 64, "link directory entry is 64 bytes");
 
 // Instance transform written by the top-level build: M = R^T (row-major),
-// t = link position; o_local = M (o - t), d_local = M d.
+// t = link position; o_local = M (o - t), d_local = M d; s = the link's world
+// bounding sphere (centre, radius) for the fast pass's cone and segment culls.
 struct alignas(16) InstXform {
     float m[9];
     float t[3];
+    float s[4];
 };
-static_assert(sizeof(InstXform) == 48, "instance transform is 48 bytes");
+static_assert(sizeof(InstXform) == 64, "instance transform is 64 bytes");
 
 // Wavefronts per block of the ray-cast kernels.  One: a block keeps its LDS and
 // its slot until its slowest wavefront ends, and the fast pass's wavefronts
@@ -62,7 +72,7 @@ inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 // Byte layout of one hierarchy inside a workspace.
 struct BvhLayout {
     int64_t n_prim = 0, n_nodes = 0;
-    size_t nodes = 0, tris = 0, tri_id = 0, keys = 0;
+    size_t nodes = 0, wide = 0, tris = 0, tri_id = 0, keys = 0;
     // build scratch
     size_t keys_alt = 0, vals = 0, vals_alt = 0, prim_box = 0, flags = 0, leaf_parent = 0,
            hist = 0, partial = 0, cbounds = 0, depth = 0, end = 0;
@@ -82,6 +92,7 @@ hipError_t launch_tlas_build(const float* link_pos, const float* link_quat, int 
 
 struct RenderLaunch {
     const Node* terrain_nodes;
+    const float4* terrain_wide;  // 4-wide records, kWideRec float4 each, indexed like terrain_nodes
     const float* terrain_tris;
     const int32_t* terrain_tri_id;
     const Node* link_nodes;
@@ -123,7 +134,7 @@ struct RenderLaunch {
 struct RenderCfg {
     int tile_w = 8, tile_h = 8;  // pixels per wavefront tile, tile_w * tile_h = 64
     int rays_per_lane = 1;       // tiles each wavefront casts, stacked vertically
-    int waves = 7;               // resident wavefronts per SIMD asked of the compiler (6, 7, 8)
+    int waves = 6;               // resident wavefronts per SIMD asked of the compiler (6, 7, 8)
     int persistent = 0;          // batched form: persistent work-queue launch (1) or flat grid (0)
     int terrain_packet = 0;      // terrain walked per lane (0) or as a wavefront packet (1)
     int bodies_flat = 1;         // links found by the top-level walk (0) or by cone culling (1)

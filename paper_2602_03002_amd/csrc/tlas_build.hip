@@ -2,8 +2,9 @@
 // rebuilt from the link poses on every render (the poses change each step).
 //
 // One 64-lane wavefront builds one environment: lane b handles instance b
-// (its world box from the link's local root box under (t_b, q_b), and the
-// transform M = R_b^T used to take rays into the link frame, Sec. 3.2.2);
+// (its world box from the link's local root box under (t_b, q_b), the
+// transform M = R_b^T used to take rays into the link frame, Sec. 3.2.2, and
+// the world bounding sphere the fast pass culls links with);
 // the wave ranks the 30-bit Morton codes of the box centres by counting
 // (keys broken by instance index), builds the Karras hierarchy from the
 // ranked keys, and boxes every internal node as the union of its leaf range.
@@ -11,11 +12,11 @@
 //
 // A link whose pose is not finite (or whose quaternion is zero) is absent from
 // its environment for this render: its transform places it at
-// the far point (identity rotation, t = 1e30) and its instance box is that
-// point, so no ray reaches it; the other links and the terrain are unaffected.
-// When the renderer culls links by their bounding spheres (the default
-// schedule) it never walks the top level, and only the transforms are
-// written.
+// the far point (identity rotation, t = 1e30) and its instance box and
+// sphere (radius 0) are that point, so no ray reaches it; the other links and
+// the terrain are unaffected.  When the renderer culls links by their
+// bounding spheres (the default schedule) it never walks the top level, and
+// only the transforms and spheres are written.
 #include "rc_internal.h"
 
 #pragma clang fp contract(off)
@@ -74,6 +75,8 @@ k_tlas(const float* __restrict__ link_pos, const float* __restrict__ link_quat, 
             InstXform X;
             for (int k = 0; k < 9; ++k) X.m[k] = (k % 4 == 0) ? 1.0f : 0.0f;
             X.t[0] = X.t[1] = X.t[2] = kFarBox;
+            X.s[0] = X.s[1] = X.s[2] = kFarBox;
+            X.s[3] = 0.0f;
             xf[eb] = X;
             for (int k = 0; k < 6; ++k) box[k] = kFarBox;
         }
@@ -102,6 +105,20 @@ k_tlas(const float* __restrict__ link_pos, const float* __restrict__ link_quat, 
         for (int r = 0; r < 3; ++r)
             for (int c = 0; c < 3; ++c) X.m[3 * r + c] = R[3 * c + r];
         X.t[0] = t[0]; X.t[1] = t[1]; X.t[2] = t[2];
+        {
+            // world bounding sphere: the local (padded) box's centre under the
+            // pose, its half-diagonal widened by 1% + 1 mm so that FP32
+            // rounding cannot cull a reachable link
+            const float* rb = meta[lane].root;
+            const float lx = 0.5f * (rb[0] + rb[1]), ly = 0.5f * (rb[2] + rb[3]),
+                        lz = 0.5f * (rb[4] + rb[5]);
+            const float hx = 0.5f * (rb[1] - rb[0]), hy = 0.5f * (rb[3] - rb[2]),
+                        hz = 0.5f * (rb[5] - rb[4]);
+            X.s[0] = __fmaf_rn(X.m[6], lz, __fmaf_rn(X.m[3], ly, X.m[0] * lx)) + X.t[0];
+            X.s[1] = __fmaf_rn(X.m[7], lz, __fmaf_rn(X.m[4], ly, X.m[1] * lx)) + X.t[1];
+            X.s[2] = __fmaf_rn(X.m[8], lz, __fmaf_rn(X.m[5], ly, X.m[2] * lx)) + X.t[2];
+            X.s[3] = sqrtf(__fmaf_rn(hz, hz, __fmaf_rn(hy, hy, hx * hx))) * 1.01f + 1e-3f;
+        }
         xf[eb] = X;
         const float* rb = meta[lane].root;
         for (int a = 0; a < 3; ++a) {

@@ -147,7 +147,8 @@ class BvhLayout(ctypes.Structure):
     _fields_ = [("n_prim", ctypes.c_int64), ("n_nodes", ctypes.c_int64),
                 ("node_offset", ctypes.c_int64), ("tri_offset", ctypes.c_int64),
                 ("tri_id_offset", ctypes.c_int64), ("key_offset", ctypes.c_int64),
-                ("max_depth", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("max_depth", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("wide_offset", ctypes.c_int64)]
 
 
 _lib = None

@@ -72,6 +72,8 @@ def check_bvh(buf, lay, tri):
         keys = buf[lay.key_offset:lay.key_offset + 8 * n].view(np.uint64)
         assert np.array_equal(keys, model["keys"]), "Morton keys differ"
     assert np.array_equal(rec.view(np.uint32), model["records"].view(np.uint32)), "node records differ"
+    wide = buf[lay.wide_offset:lay.wide_offset + 128 * m].view(np.uint32).reshape(m, 32)
+    assert np.array_equal(wide, lbvh.collapse4(model["records"]).view(np.uint32)), "4-wide records differ"
     tris = buf[lay.tri_offset:lay.tri_offset + 36 * n].view(np.float32).reshape(n, 9)
     assert np.array_equal(tris, np.asarray(tri, np.float32).reshape(-1, 9)[model["tri_id"]])
     assert lay.max_depth == model["depth"]
@@ -136,10 +138,27 @@ def test_tlas_bit_exact(bodies_flat):
     n_rec = B - 1
     nodes = buf[:E * n_rec * 64].view(np.float32).reshape(E, n_rec, 16)
     x0 = _align(E * n_rec * 64)
-    xf = buf[x0:x0 + E * B * 48].view(np.float32).reshape(E, B, 12)
+    xf = buf[x0:x0 + E * B * 64].view(np.float32).reshape(E, B, 16)
+    lo, hi = root[:, 0::2].astype(np.float64), root[:, 1::2].astype(np.float64)
+    corners = np.stack([np.where([(k >> a) & 1 for a in range(3)], hi, lo) for k in range(8)], 1)
     for e in range(E):
         mx, mrec = lbvh.tlas(lp[e], lq[e], root)
-        assert np.array_equal(xf[e].view(np.uint32), mx.view(np.uint32)), f"transforms of env {e}"
+        assert np.array_equal(xf[e, :, :12].view(np.uint32), mx.view(np.uint32)), f"transforms of env {e}"
+        # bounding spheres: an absent link's is the far point with radius 0;
+        # otherwise it holds the posed local box (corners under the model's
+        # R, t) and its radius is the half-diagonal widened by 1% + 1 mm
+        for b in range(B):
+            sph = xf[e, b, 12:16].astype(np.float64)
+            if mx[b, 9] == lbvh.FAR_POINT:
+                assert np.array_equal(xf[e, b, 12:16], np.float32([1e30, 1e30, 1e30, 0])), (e, b)
+                continue
+            R, t = mx[b, :9].astype(np.float64).reshape(3, 3).T, mx[b, 9:12].astype(np.float64)
+            w = corners[b] @ R.T + t
+            half = 0.5 * np.linalg.norm(hi[b] - lo[b])
+            assert abs(sph[3] - (half * 1.01 + 1e-3)) <= 1e-6 * sph[3], (e, b)
+            assert np.max(np.linalg.norm(w - sph[:3], axis=1)) <= sph[3], (e, b)
+            ctr = R @ (0.5 * (lo[b] + hi[b])) + t
+            assert np.max(np.abs(ctr - sph[:3])) <= 1e-6 * (1 + np.abs(t).max()), (e, b)
         if bodies_flat == 0:
             g, mm = nodes[e].view(np.uint32), mrec.view(np.uint32)
             bad = np.argwhere(g != mm)

@@ -198,3 +198,61 @@ def test_tlas_absent_instances():
         for h, c in enumerate((ints[i, 12], ints[i, 13])):
             if c < 0 and ~c in (2, 5, 6):
                 assert np.all(rec[i, 6 * h:6 * h + 6] == np.float32(1e30))
+
+
+@pytest.mark.parametrize("case", ["terrain", "degenerate", "single"])
+def test_collapse4_records_cover_every_leaf_once(case):
+    """4-wide records: walking them from the root (internal slots only)
+    reaches every leaf exactly once; every slot's box holds the triangles of
+    the leaves below it (the far point only when all of them have zero area),
+    and a record has two slots per child that it expands, one per child that
+    it keeps, far-point empty slots after them."""
+    if case == "terrain":
+        tri, n_good = sg.TileTerrain(1).triangles()[:2000], 2000
+    elif case == "degenerate":
+        tri, n_good = _with_degenerate()
+    else:
+        tri, n_good = np.array([[[0, 0, 0], [1, 0, 0], [0, 1, 0]]], np.float32), 1
+    m = lbvh.build(tri)
+    rec, ints = m["records"], m["records"].view(np.int32)
+    w = lbvh.collapse4(rec)
+    wi = w.view(np.int32)
+    assert w.shape == (rec.shape[0], 32) and np.all(wi[:, 28:32] == 0)
+    t = tri.reshape(-1, 9)[m["tri_id"]].reshape(-1, 3, 3)
+    is_deg = m["tri_id"] >= n_good
+    n = t.shape[0]
+
+    def leaves(c):
+        if c < 0:
+            return [~c]
+        return leaves(ints[c, 12]) + leaves(ints[c, 13])
+
+    far = np.full(3, lbvh.FAR_POINT, np.float32)
+    seen = []
+    stack = [0]
+    while stack:
+        r = stack.pop()
+        used = 0
+        for h in (0, 1):
+            c = ints[r, 12 + h]
+            keep = c < 0 or rec[r, 6 * h] == lbvh.FAR_POINT
+            used += 1 if keep else 2
+        for k in range(4):
+            lo, hi, c = w[r, k:24:4][0::2], w[r, k:24:4][1::2], wi[r, 24 + k]
+            if k >= used:
+                assert np.array_equal(lo, far) and np.array_equal(hi, far) and c == 0
+                continue
+            if n == 1 and k == 1:  # a one-leaf hierarchy's second child: the far point
+                assert np.array_equal(lo, far) and c == ~0
+                continue
+            good = [i for i in leaves(c) if not is_deg[i]]
+            if not good:
+                assert np.array_equal(lo, far) and np.array_equal(hi, far)
+                seen += leaves(c)
+                continue
+            assert np.all(t[good].min((0, 1)) > lo) and np.all(t[good].max((0, 1)) < hi)
+            if c < 0:
+                seen.append(~c)
+            else:
+                stack.append(c)
+    assert sorted(seen) == list(range(n)), "every leaf reached once"
