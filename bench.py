@@ -66,8 +66,9 @@ def bytes_per_ray():
 COUNTERS = os.path.join(ROOT, "profiles", "k_render_4096x2_64x48_hbm_counters.txt")
 SQ_COUNTERS = os.path.join(ROOT, "profiles", "k_render_4096x2_64x48_sq_counters.txt")
 L2_COUNTERS = os.path.join(ROOT, "profiles", "k_render_4096x2_64x48_l2_counters.txt")
+# the fast pass and the sources of the records it reads
 KERNEL_SRC = [os.path.join(ROOT, "paper_2602_03002_amd", "csrc", f)
-              for f in ("raycast.hip", "rc_internal.h")]
+              for f in ("raycast.hip", "rc_internal.h", "blas_build.hip", "tlas_build.hip")]
 
 
 def kernel_sha():
@@ -207,9 +208,11 @@ def traversal_report(sc, kw, ref):
     # one triangle per leaf and C_trav = C_tri = 1: every child box weighs 1
     sah = float((a_root + area.sum()) / a_root)
     del counts, rec, b, ext, area
+    # node records visited: the terrain walk's are 4-wide (112 bytes read of
+    # 128) but the entry descent's, the links' and the top level's binary (56)
     own = {"node": round(c[0], 3), "tri": round(c[1], 3), "inst": round(c[2], 3),
-           "link_node": round(c[3], 3)}
-    own["bytes_per_ray"] = round(12 + 56 * c[0] + 36 * c[1] + 28 * c[2], 1)
+           "link_node": round(c[3], 3), "terrain_node": round(c[0] - c[3], 3)}
+    own["bytes_per_ray_upper"] = round(12 + 112 * (c[0] - c[3]) + 56 * c[3] + 36 * c[1] + 28 * c[2], 1)
     out = {"own": own, "sah_cost_terrain_own": round(sah, 3)}
     if ref is not None:
         rc_ = ref["mean_counts"]

@@ -860,9 +860,10 @@ __device__ __forceinline__ Hit cast_ray(const RenderLaunch& a, const CamRef& cam
                                 (uint32_t)a.n_links, ox, oy, oz, wm, kTerrainKP, px.eo, h, px, -1, i);
             };
             if (!(MODE & kPacketTerrain)) {
-                // a wavefront whose rays share one direction octant (the common
-                // case for a tile) runs the octant's specialised box tests on
-                // the 4-wide records; a mixed wavefront walks the binary ones
+                // the fast pass walks the 4-wide records, with the octant's
+                // specialised box tests when the wavefront's rays share one
+                // direction octant (the common case for a tile); the exact
+                // pass's lanes walk the binary records alone
                 const int oct = slab_octant(ws);
                 const int oct0 = uni(oct);
                 if (WAVE && !EXACT && __ballot(oct != oct0) == 0ull) {
@@ -872,6 +873,8 @@ __device__ __forceinline__ Hit cast_ray(const RenderLaunch& a, const CamRef& cam
                         RC_OCT(0) RC_OCT(1) RC_OCT(2) RC_OCT(3) RC_OCT(4) RC_OCT(5) RC_OCT(6) RC_OCT(7)
 #undef RC_OCT
                     }
+                } else if (WAVE && !EXACT) {
+                    traverse4<-1>(a.terrain_wide, n_nodes, a.n_terrain, ws, h, cnt, leaf, entry, stk);
                 } else {
                     traverse(a.terrain_nodes, n_nodes, a.n_terrain, ws, h, cnt, leaf, entry, stk);
                 }
