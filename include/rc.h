@@ -28,7 +28,8 @@
  *    workspaces may run concurrently from several threads.  The one mutable
  *    part of a scene is its pair of launch schedules (rc_set_render_config,
  *    rc_autotune), each stored as one word: a render reads a whole schedule,
- *    old or new, never a mix.  rc_robot_meshes and rc_scene_destroy must not
+ *    old or new, never a mix; the walk's stack cap (rc_set_walk_stack_limit)
+ *    is one word too.  rc_robot_meshes and rc_scene_destroy must not
  *    overlap any other call on the same scene.
  *  - Frames: quaternions are (x, y, z, w) and rotate local vectors to world;
  *    they are normalised before use.  A camera's optical frame has x right,
@@ -287,6 +288,15 @@ typedef struct {
                                 the cone of the wavefront's rays, then each ray against the
                                 surviving spheres */
 } rc_render_config;
+
+/* Cap the per-lane stack of the fast pass's terrain walk at `entries`
+ * (1..16; 16 is the default).  A ray whose walk would push onto a full stack
+ * is re-cast in full by the exact pass, so results do not depend on the cap;
+ * fewer entries only make that fallback frequent, which is what tests of it
+ * use this for (the nearest-first walk of Alg. 1, Sec. 3.2.2, with its
+ * pending subtrees kept on the stack).  Read at each render's set-up, like
+ * the schedules.  Errors: INVALID_ARG (NULL scene, entries outside 1..16). */
+rc_status rc_set_walk_stack_limit(rc_scene* scene, int32_t entries);
 
 /* Schedule used by rc_render (batched = 0) or rc_render_batched (batched = 1). */
 rc_status rc_get_render_config(const rc_scene* scene, int32_t batched, rc_render_config* cfg);

@@ -23,6 +23,9 @@ struct rc_scene {
     // Fast-pass schedules of rc_render and rc_render_batched, packed into one
     // word each: rc_autotune and rc_set_render_config may replace them while
     // renders run on other threads, and each render reads one whole schedule.
+    // entries of the per-lane stack the fast pass's 4-wide terrain walk may
+    // use (rc_set_walk_stack_limit; fewer only to test the overflow path)
+    std::atomic<int32_t> wide_stack{rc::kWalkStack};
     std::atomic<uint64_t> cfg_word{rc::pack_cfg(rc::RenderCfg())};
     std::atomic<uint64_t> cfg_batched_word{rc::pack_cfg(rc::RenderCfg())};
     rc::RenderCfg cfg() const { return rc::unpack_cfg(cfg_word.load(std::memory_order_acquire)); }
@@ -325,6 +328,7 @@ rc_status rc_render_size(const rc_scene* scene, int32_t n_env, int32_t n_cam, in
 static void fill_scene(const rc_scene* scene, RenderLaunch& L) {
     L.terrain_nodes = (const Node*)(scene->ws + scene->terrain.nodes);
     L.terrain_wide = (const float4*)(scene->ws + scene->terrain.wide);
+    L.wide_stack = scene->wide_stack.load(std::memory_order_acquire);
     L.terrain_tris = (const float*)(scene->ws + scene->terrain.tris);
     L.terrain_tri_id = (const int32_t*)(scene->ws + scene->terrain.tri_id);
     L.link_nodes = (const Node*)scene->robot_ws;
@@ -657,6 +661,15 @@ static rc_render_config from_cfg(const RenderCfg& c) {
 rc_status rc_get_render_config(const rc_scene* scene, int32_t batched, rc_render_config* cfg) {
     if (!scene || !cfg) return fail(RC_ERR_INVALID_ARG, "rc_get_render_config: NULL pointer");
     *cfg = from_cfg(batched ? scene->cfg_batched() : scene->cfg());
+    return RC_OK;
+}
+
+rc_status rc_set_walk_stack_limit(rc_scene* scene, int32_t entries) {
+    if (!scene) return fail(RC_ERR_INVALID_ARG, "rc_set_walk_stack_limit: NULL scene");
+    if (entries < 1 || entries > kWalkStack)
+        return fail(RC_ERR_INVALID_ARG, "rc_set_walk_stack_limit: entries must be in [1, " +
+                                            std::to_string(kWalkStack) + "]");
+    scene->wide_stack.store(entries, std::memory_order_release);
     return RC_OK;
 }
 

@@ -406,7 +406,7 @@ __device__ __forceinline__ void tri_test(const float* __restrict__ v,
 // checked and the loop is bounded (a valid hierarchy needs fewer than
 // 2 n_nodes + 2 steps), so a corrupt hierarchy ends the ray instead of
 // faulting or spinning.
-constexpr int kStack = 16;
+constexpr int kStack = kWalkStack;
 constexpr int kLanes = 64 * kWavesPerBlock;
 
 template <int OCT = -1, bool VERT = false, typename Cnt, typename Leaf>
@@ -494,14 +494,15 @@ __device__ __forceinline__ void traverse(const Node* __restrict__ nodes, int n_n
 // bound it had before its leaves were tested; the children of that record are
 // tested under the tightened bound.  Every step moves a walking lane (the
 // budget bounds these) or empties the parked slots, so the loop ends.  A push
-// onto a full stack is dropped and sends the ray to the exact pass's full
-// re-cast (h.tu = 0), so no result depends on the stack's depth.
+// onto a full stack (cap entries, at most kStack) is dropped and sends the ray
+// to the exact pass's full re-cast (h.tu = 0), so no result depends on the
+// stack's depth.
 constexpr int kGatherNum = 3, kGatherDen = 4;  // test once parked >= 3/4 of live lanes
 
 template <int OCT, typename Cnt, typename Leaf>
 __device__ __forceinline__ void traverse4(const float4* __restrict__ wide, int n_nodes, int n_prim,
                                           const Slab& r, Hit& h, Cnt& cnt, Leaf&& leaf, int start,
-                                          uint32_t* stk) {
+                                          uint32_t* stk, int cap) {
     int cur = start;
     int sp = 0;
     int budget = 2 * n_nodes + 2;
@@ -549,7 +550,7 @@ __device__ __forceinline__ void traverse4(const float4* __restrict__ wide, int n
                 if (d[0] < INFINITY) {
                     for (int k = 3; k >= 1; --k) {
                         if (d[k] < INFINITY) {
-                            if (sp < kStack) stk[kLanes * sp++] = (uint32_t)e[k];
+                            if (sp < cap) stk[kLanes * sp++] = (uint32_t)e[k];
                             else h.tu = 0.0f;
                         }
                     }
@@ -869,12 +870,15 @@ __device__ __forceinline__ Hit cast_ray(const RenderLaunch& a, const CamRef& cam
                 if (WAVE && !EXACT && __ballot(oct != oct0) == 0ull) {
                     switch (oct0) {
 #define RC_OCT(K) \
-    case K: traverse4<K>(a.terrain_wide, n_nodes, a.n_terrain, ws, h, cnt, leaf, entry, stk); break;
+    case K:                                                                                      \
+        traverse4<K>(a.terrain_wide, n_nodes, a.n_terrain, ws, h, cnt, leaf, entry, stk, a.wide_stack); \
+        break;
                         RC_OCT(0) RC_OCT(1) RC_OCT(2) RC_OCT(3) RC_OCT(4) RC_OCT(5) RC_OCT(6) RC_OCT(7)
 #undef RC_OCT
                     }
                 } else if (WAVE && !EXACT) {
-                    traverse4<-1>(a.terrain_wide, n_nodes, a.n_terrain, ws, h, cnt, leaf, entry, stk);
+                    traverse4<-1>(a.terrain_wide, n_nodes, a.n_terrain, ws, h, cnt, leaf, entry, stk,
+                                  a.wide_stack);
                 } else {
                     traverse(a.terrain_nodes, n_nodes, a.n_terrain, ws, h, cnt, leaf, entry, stk);
                 }

@@ -31,6 +31,9 @@ static_assert(sizeof(Node) == 64, "node record is one 64-byte line");
 // unused slot has the far-point box.
 constexpr int kWideRec = 8;
 
+// Entries of the per-lane LDS stack of the hierarchy walks.
+constexpr int kWalkStack = 16;
+
 // Per-link hierarchy directory entry (device), 64 bytes.
 // Bases are element offsets from the start of the robot workspace.
 struct alignas(16) LinkMeta {
@@ -93,6 +96,7 @@ hipError_t launch_tlas_build(const float* link_pos, const float* link_quat, int 
 struct RenderLaunch {
     const Node* terrain_nodes;
     const float4* terrain_wide;  // 4-wide records, kWideRec float4 each, indexed like terrain_nodes
+    int wide_stack;              // stack entries the 4-wide walk may use (1..kWalkStack)
     const float* terrain_tris;
     const int32_t* terrain_tri_id;
     const Node* link_nodes;

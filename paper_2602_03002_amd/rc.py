@@ -32,7 +32,7 @@ EXPORTED = [
     "rc_downsample", "rc_heightmap",
     "rc_bvh_layout_of",
     "rc_render_batched_size", "rc_render_batched", "rc_render_batched_status",
-    "rc_get_render_config", "rc_set_render_config", "rc_autotune",
+    "rc_get_render_config", "rc_set_render_config", "rc_autotune", "rc_set_walk_stack_limit",
     "rc_graph_capture_batched", "rc_graph_launch", "rc_graph_destroy",
     "rc_post_size_packed", "rc_post_create_packed", "rc_postprocess_batched",
     "rc_server_arena_size", "rc_server_create", "rc_server_create_simulated", "rc_server_submit",
@@ -194,6 +194,7 @@ def lib():
                                                ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(i64), vp]
         L.rc_get_render_config.argtypes = [vp, i32, ctypes.POINTER(RenderConfig)]
         L.rc_set_render_config.argtypes = [vp, i32, ctypes.POINTER(RenderConfig)]
+        L.rc_set_walk_stack_limit.argtypes = [vp, i32]
         L.rc_autotune.argtypes = [vp, ctypes.POINTER(RenderArgs), ctypes.POINTER(BatchArgs), vp, sz,
                                   i32, vp, ctypes.POINTER(RenderConfig), ctypes.POINTER(ctypes.c_float)]
         L.rc_graph_capture_batched.argtypes = [vp, ctypes.POINTER(BatchArgs), vp, sz, vp,
@@ -443,6 +444,11 @@ class Scene:
     def set_config(self, batched=False, **kw):
         c = RenderConfig(**{**self.config(batched), **kw})
         check(lib().rc_set_render_config(self.handle, int(batched), ctypes.byref(c)))
+
+    def set_walk_stack_limit(self, entries):
+        """Cap the fast pass's per-lane terrain-walk stack (1..16) to exercise
+        its overflow path; results do not depend on it."""
+        check(lib().rc_set_walk_stack_limit(self.handle, int(entries)))
 
     def autotune(self, reps=3, stream=None, batch=None, **plain):
         """Time every schedule on one launch (plain keyword args as for render(),

@@ -571,6 +571,34 @@ def test_grid_edge_rays_decided_by_listed_triangles():
     assert n_full > 0 and n_exact - n_full > 0
 
 
+@pytest.mark.parametrize("cap", [1, 3])
+def test_walk_stack_cap_sends_rays_to_the_full_recast(cap):
+    """The fast pass's 4-wide terrain walk with its stack capped at `cap`
+    entries: a ray whose push is dropped is re-cast in full by the exact pass,
+    so the ids stay bit-identical to the uncapped render and the depths agree
+    (to the FP32 rounding of an FP64 depth) and meet the oracle's bar."""
+    say(f"[render] 4 envs x 2 cams 37x29, walk stack capped at {cap}")
+    w = sg.robot_scene(2, 2, 4.0, 2, 37, 29, steps=1, label="parity-ragged")
+    sc = make_scene(w)
+    E, C, W, H = w["E"], w["C"], w["W"], w["H"]
+    d0, i0, t0 = render(sc, w)
+    _, full0 = sc.exact_count(E, C, W, H, recast=True)
+    sc.set_walk_stack_limit(cap)
+    try:
+        d1, i1, t1 = render(sc, w)
+        _, full1 = sc.exact_count(E, C, W, H, recast=True)
+    finally:
+        sc.set_walk_stack_limit(16)
+    say(f"  full re-casts: {full0} uncapped, {full1} capped")
+    assert full1 > full0 + 100
+    assert np.array_equal(i0, i1) and np.array_equal(t0, t1)
+    assert np.max(np.abs(d0 - d1)) <= 2e-5
+    assert_parity(d1, i1, t1, oracle_render(w), w["far"], label=f"stack cap {cap}")
+    for bad in (0, 17):
+        with pytest.raises(RuntimeError):
+            sc.set_walk_stack_limit(bad)
+
+
 def test_exact_list_overflow_recasts_everything():
     """More listed rays than the exact pass's list holds (4096 entries here):
     every pixel is re-cast, with the same results."""
