@@ -498,6 +498,11 @@ __device__ __forceinline__ void traverse(const Node* __restrict__ nodes, int n_n
 // to the exact pass's full re-cast (h.tu = 0), so no result depends on the
 // stack's depth.
 constexpr int kGatherNum = 3, kGatherDen = 4;  // test once parked >= 3/4 of live lanes
+// The exact pass's full re-casts walk the 4-wide records with a stack that
+// cannot overflow: a path from the root visits at most kMaxDepth / 2 + 1
+// records and each leaves at most three slots pending.
+constexpr int kExactStack = 104;
+static_assert(kExactStack >= 3 * (kMaxDepth / 2 + 1), "exact-pass stack too short");
 
 template <int OCT, typename Cnt, typename Leaf>
 __device__ __forceinline__ void traverse4(const float4* __restrict__ wide, int n_nodes, int n_prim,
@@ -879,6 +884,9 @@ __device__ __forceinline__ Hit cast_ray(const RenderLaunch& a, const CamRef& cam
                 } else if (WAVE && !EXACT) {
                     traverse4<-1>(a.terrain_wide, n_nodes, a.n_terrain, ws, h, cnt, leaf, entry, stk,
                                   a.wide_stack);
+                } else if (EXACT && stk) {
+                    traverse4<-1>(a.terrain_wide, n_nodes, a.n_terrain, ws, h, cnt, leaf, entry, stk,
+                                  kExactStack);
                 } else {
                     traverse(a.terrain_nodes, n_nodes, a.n_terrain, ws, h, cnt, leaf, entry, stk);
                 }
@@ -1252,12 +1260,12 @@ __device__ __forceinline__ void entry_cam(const RenderLaunch& a, uint32_t cam_in
 
 // Full re-cast of one ray with FP64 decisions for undecided triangles.
 __device__ __forceinline__ void exact_one(const RenderLaunch& a, int64_t p, uint32_t cam_index, int x,
-                                          int y, float bound) {
+                                          int y, float bound, uint32_t* stk) {
     CamRef cam;
     int e;
     entry_cam(a, cam_index, cam, e);
     NoCount none;
-    const Hit h = cast_ray<true, false, 0>(a, cam, e, x, y, bound, nullptr, nullptr, none);
+    const Hit h = cast_ray<true, false, 0>(a, cam, e, x, y, bound, nullptr, stk, none);
     write_out(a, p, h, cam, x, y);
 }
 
@@ -1310,7 +1318,10 @@ __device__ __forceinline__ void resolve_one(const RenderLaunch& a, const uint4 h
 }
 
 
+static_assert(kLanes == 64, "the exact pass indexes its stack with a 64-lane stride");
 __global__ void __launch_bounds__(64) k_render_exact(RenderLaunch a, const uint32_t* tile_start) {
+    __shared__ uint32_t s_xstack[64 * kExactStack];
+    uint32_t* stk = s_xstack + threadIdx.x;
     const uint32_t n_res = a.exact_count[0], n_full = a.exact_count[1];
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1323,7 +1334,7 @@ __global__ void __launch_bounds__(64) k_render_exact(RenderLaunch a, const uint3
             for (int64_t j = gid >> 6; j < (int64_t)n_full; j += stride >> 6) {
                 const uint4 it = a.exact_list[2 * (a.exact_cap - 1 - j)];
                 exact_one(a, it.x, it.y, (int)(it.z & 0xFFFFu), (int)(it.z >> 16),
-                          __uint_as_float(it.w));
+                          __uint_as_float(it.w), stk);
             }
         }
         return;
@@ -1334,7 +1345,7 @@ __global__ void __launch_bounds__(64) k_render_exact(RenderLaunch a, const uint3
         for (int64_t p = gid; p < a.n_pixels; p += stride) {
             const int64_t ec = p / hw;
             const int pin = (int)(p - ec * hw);
-            exact_one(a, p, (uint32_t)ec, pin % a.width, pin / a.width, INFINITY);
+            exact_one(a, p, (uint32_t)ec, pin % a.width, pin / a.width, INFINITY, stk);
         }
     } else {
         for (int d = 0; d < a.n_desc; ++d) {
@@ -1343,7 +1354,7 @@ __global__ void __launch_bounds__(64) k_render_exact(RenderLaunch a, const uint3
             const int64_t np = (int64_t)D.width * D.height;
             for (int64_t q = gid; q < np; q += stride)
                 exact_one(a, (int64_t)D.out_offset + q, (uint32_t)d, (int)(q % D.width),
-                          (int)(q / D.width), INFINITY);
+                          (int)(q / D.width), INFINITY, stk);
         }
     }
 }
