@@ -289,9 +289,11 @@ typedef struct {
                                 surviving spheres */
 } rc_render_config;
 
-/* Cap the per-lane stack of the fast pass's terrain walk at `entries`
- * (1..16; 16 is the default).  A ray whose walk would push onto a full stack
- * is re-cast in full by the exact pass, so results do not depend on the cap;
+/* Cap the per-lane stack of the 4-wide terrain walks (the fast pass's, the
+ * height map's) at `entries` (1..16; 16 is the default).  A ray whose walk
+ * would push onto a full stack is re-cast in full by the exact pass (a height
+ * map column is walked again over the binary records), so results do not
+ * depend on the cap;
  * fewer entries only make that fallback frequent, which is what tests of it
  * use this for (the nearest-first walk of Alg. 1, Sec. 3.2.2, with its
  * pending subtrees kept on the stack).  Read at each render's set-up, like

@@ -1029,6 +1029,8 @@ rc_status rc_heightmap(const rc_scene* scene, const rc_heightmap_args* a, rc_str
         return fail(RC_ERR_INVALID_ARG, "rc_heightmap: dx, dy, depth must be finite and > 0, top finite");
     HeightLaunch hl;
     hl.nodes = (const Node*)(scene->ws + scene->terrain.nodes);
+    hl.wide = (const float4*)(scene->ws + scene->terrain.wide);
+    hl.wide_stack = scene->wide_stack.load(std::memory_order_acquire);
     hl.tris = (const float*)(scene->ws + scene->terrain.tris);
     hl.n_prim = (int)scene->terrain.n_prim;
     hl.base_pos = a->base_pos;

@@ -504,7 +504,7 @@ constexpr int kGatherNum = 3, kGatherDen = 4;  // test once parked >= 3/4 of liv
 constexpr int kExactStack = 104;
 static_assert(kExactStack >= 3 * (kMaxDepth / 2 + 1), "exact-pass stack too short");
 
-template <int OCT, typename Cnt, typename Leaf>
+template <int OCT, bool VERT = false, typename Cnt, typename Leaf>
 __device__ __forceinline__ void traverse4(const float4* __restrict__ wide, int n_nodes, int n_prim,
                                           const Slab& r, Hit& h, Cnt& cnt, Leaf&& leaf, int start,
                                           uint32_t* stk, int cap) {
@@ -525,10 +525,17 @@ __device__ __forceinline__ void traverse4(const float4* __restrict__ wide, int n
                 cnt.node();
                 float tn[4];
                 bool hit[4];
-                hit[0] = slab<OCT>(xl.x, xh.x, yl.x, yh.x, zl.x, zh.x, r, h.tmax, tn[0]);
-                hit[1] = slab<OCT>(xl.y, xh.y, yl.y, yh.y, zl.y, zh.y, r, h.tmax, tn[1]);
-                hit[2] = slab<OCT>(xl.z, xh.z, yl.z, yh.z, zl.z, zh.z, r, h.tmax, tn[2]);
-                hit[3] = slab<OCT>(xl.w, xh.w, yl.w, yh.w, zl.w, zh.w, r, h.tmax, tn[3]);
+                if constexpr (VERT) {  // the height map's vertical columns
+                    hit[0] = vslab(xl.x, xh.x, yl.x, yh.x, zl.x, zh.x, r, h.tmax, tn[0]);
+                    hit[1] = vslab(xl.y, xh.y, yl.y, yh.y, zl.y, zh.y, r, h.tmax, tn[1]);
+                    hit[2] = vslab(xl.z, xh.z, yl.z, yh.z, zl.z, zh.z, r, h.tmax, tn[2]);
+                    hit[3] = vslab(xl.w, xh.w, yl.w, yh.w, zl.w, zh.w, r, h.tmax, tn[3]);
+                } else {
+                    hit[0] = slab<OCT>(xl.x, xh.x, yl.x, yh.x, zl.x, zh.x, r, h.tmax, tn[0]);
+                    hit[1] = slab<OCT>(xl.y, xh.y, yl.y, yh.y, zl.y, zh.y, r, h.tmax, tn[1]);
+                    hit[2] = slab<OCT>(xl.z, xh.z, yl.z, yh.z, zl.z, zh.z, r, h.tmax, tn[2]);
+                    hit[3] = slab<OCT>(xl.w, xh.w, yl.w, yh.w, zl.w, zh.w, r, h.tmax, tn[3]);
+                }
                 const int c[4] = {ch.x, ch.y, ch.z, ch.w};
                 uint32_t lm = 0;
                 float d[4];
@@ -1361,8 +1368,9 @@ __global__ void __launch_bounds__(64) k_render_exact(RenderLaunch a, const uint3
 
 // Privileged height map (the terrain experts' local grid, Sec. 3.1): one
 // vertical ray per grid point, from base_z + top down to `depth`, against the
-// terrain hierarchy; every triangle test is the FP64 watertight test (closed
-// triangles), so a point on a shared edge or vertex finds its surface.
+// terrain hierarchy (its 4-wide records); every triangle test is the FP64
+// watertight test (closed triangles), so a point on a shared edge or vertex
+// finds its surface.
 __global__ void __launch_bounds__(kLanes) __attribute__((amdgpu_waves_per_eu(8, 8)))
 k_heightmap(HeightLaunch hl) {
     __shared__ uint32_t s_stack[kLanes * kStack];
@@ -1389,17 +1397,23 @@ k_heightmap(HeightLaunch hl) {
         h.tu = INFINITY;
         double best = INFINITY;
         NoCount none;
-        traverse<-1, true>(hl.nodes, hl.n_prim > 1 ? hl.n_prim - 1 : 1, hl.n_prim, r, h, none,
-                           [&](int leaf) {
-                               const float* v = hl.tris + 9 * (int64_t)leaf;
-                               double t;
-                               if (tri_test64(v, o64, d64, t) &&
-                                   t <= (double)hl.depth && t < best) {
-                                   best = t;
-                                   // the FP32 bound must not cut below the FP64 hit
-                                   h.tmax = nextafterf((float)t, INFINITY);
-                               }
-                           }, 0, s_stack + threadIdx.x);
+        auto leaf = [&](int leaf) {
+            const float* v = hl.tris + 9 * (int64_t)leaf;
+            double t;
+            if (tri_test64(v, o64, d64, t) && t <= (double)hl.depth && t < best) {
+                best = t;
+                // the FP32 bound must not cut below the FP64 hit
+                h.tmax = nextafterf((float)t, INFINITY);
+            }
+        };
+        const int n_int = hl.n_prim > 1 ? hl.n_prim - 1 : 1;
+        traverse4<-1, true>(hl.wide, n_int, hl.n_prim, r, h, none, leaf, 0, s_stack + threadIdx.x,
+                            hl.wide_stack);
+        // a dropped push (full stack) left subtrees unvisited: walk the binary
+        // records, whose trail has no such limit, for that column (the hits
+        // found so far stand; the bound only prunes)
+        if (h.tu == 0.0f)
+            traverse<-1, true>(hl.nodes, n_int, hl.n_prim, r, h, none, leaf, 0, s_stack + threadIdx.x);
         hl.heights[q] = best < INFINITY ? (float)((double)hl.top - best) : hl.miss;
     }
 }

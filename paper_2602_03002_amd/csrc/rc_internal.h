@@ -166,6 +166,8 @@ inline RenderCfg unpack_cfg(uint64_t v) {
 
 struct HeightLaunch {
     const Node* nodes;
+    const float4* wide;  // 4-wide records of the same hierarchy
+    int wide_stack;      // stack entries the 4-wide walk may use (1..kWalkStack)
     const float* tris;
     int n_prim;
     const float* base_pos;  // [n_env][3]

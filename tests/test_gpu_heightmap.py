@@ -69,6 +69,32 @@ def test_heightmap_tile_terrain_all_points():
     assert n_bad <= 0.01 * got.size
 
 
+@pytest.mark.parametrize("cap", [1, 2])
+def test_heightmap_stack_cap_falls_back_to_the_binary_walk(cap):
+    """With the 4-wide walk's stack capped, columns whose pushes are dropped
+    are walked again over the binary records: the map is bit-identical to the
+    uncapped one, and still agrees with the oracle."""
+    say(f"[heightmap] 2x2 tiles, 24 bases, 4-wide walk stack capped at {cap}")
+    terr = sg.TileTerrain(2, seed=sg.MASTER_SEED)
+    tri = terr.triangles()
+    rng = np.random.default_rng(5)
+    E = 24
+    xy = np.stack([rng.uniform(-4.5, 4.5, E), rng.uniform(-4.5, 4.5, E)], 1)
+    base = np.concatenate([xy, [[terr.height(x, y) + 0.6] for x, y in xy]], 1).astype(np.float32)
+    yaw = rng.uniform(0, 2 * np.pi, E).astype(np.float32)
+    kw = dict(nx=17, ny=11, dx=0.1, dy=0.1, top=1.0, depth=3.0)
+    sc = rc().Scene(dev(tri))
+    full = gpu_heightmap(sc, base, yaw, **kw)
+    sc.set_walk_stack_limit(cap)
+    try:
+        capped = gpu_heightmap(sc, base, yaw, **kw)
+    finally:
+        sc.set_walk_stack_limit(16)
+    assert np.array_equal(full.view(np.uint64), capped.view(np.uint64))
+    ref = oracle.heightmap(tri, base, yaw, **kw)
+    assert agree(capped, ref, tri, base, yaw, kw) <= 0.01 * capped.size
+
+
 def test_heightmap_grid_vertices_watertight():
     """Grid points on the vertices and edges of a triangulated tilted plane
     (yaw 0, base on a vertex): every vertical ray finds the plane."""
