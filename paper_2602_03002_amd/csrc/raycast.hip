@@ -494,9 +494,10 @@ __device__ __forceinline__ void traverse(const Node* __restrict__ nodes, int n_n
 // bound it had before its leaves were tested; the children of that record are
 // tested under the tightened bound.  Every step moves a walking lane (the
 // budget bounds these) or empties the parked slots, so the loop ends.  A push
-// onto a full stack (cap entries, at most kStack) is dropped and sends the ray
-// to the exact pass's full re-cast (h.tu = 0), so no result depends on the
-// stack's depth.
+// onto a full stack (cap entries) is dropped and marks the ray (h.tu = 0): the
+// fast pass's exact pass then re-casts it in full, and the height map walks
+// the column again over the binary records, so no result depends on the
+// stack's depth; the exact pass's own walks get a stack that cannot overflow.
 constexpr int kGatherNum = 3, kGatherDen = 4;  // test once parked >= 3/4 of live lanes
 // The exact pass's full re-casts walk the 4-wide records with a stack that
 // cannot overflow: a path from the root visits at most kMaxDepth / 2 + 1

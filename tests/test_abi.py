@@ -39,6 +39,8 @@ def test_host_validation_paths():
     assert L.rc_post_size(1, 1, 1, 1, -1, ctypes.byref(sz)) == -1
     assert L.rc_post_size(1, 2, 3, 4, 3, ctypes.byref(sz)) == 0 and sz.value >= 4 * 24 * 4
     assert L.rc_postprocess(None, None, None, None, 0, None, None, None, None, None) == -1
+    assert L.rc_set_walk_stack_limit(None, 4) == -1
+    assert b"NULL scene" in L.rc_last_error()
     assert L.rc_scene_destroy(None) == 0 and L.rc_post_destroy(None) == 0
     assert L.rc_status_string(-2) == b"workspace too small or misaligned"
     assert b"n_tri" in L.rc_last_error() or L.rc_last_error() != b""
