@@ -144,7 +144,8 @@ typedef struct {
     const float* cam_pos;   /* device [n_env][n_cam][3]: camera centre p_c (world) */
     const float* cam_quat;  /* device [n_env][n_cam][4]: optical -> world */
     const float* intr;      /* device [n_env][n_cam][4]: fx, fy, cx, cy (batched K) */
-    float far_plane;        /* d_max (m), > 0 */
+    float far_plane;        /* d_max (m), in (0, 1e20]: boxes that no ray may reach are
+                               stored as the point (1e30, 1e30, 1e30) */
     int32_t depth_mode;     /* RC_DEPTH_PLANAR or RC_DEPTH_RANGE */
     float* depth;           /* device out [n_env][n_cam][height][width] (m) */
     int32_t* inst;          /* device out, same shape, or NULL */
@@ -239,7 +240,7 @@ typedef struct {
     int64_t n_pixels;          /* pixels of the packed outputs */
     int32_t max_width;         /* no descriptor's image is wider (1..65535) */
     int32_t max_height;        /* ... or taller (1..65535) */
-    float far_plane;
+    float far_plane;           /* d_max (m), in (0, 1e20] as for rc_render */
     int32_t depth_mode;
     float* depth;              /* device out [n_pixels] */
     int32_t* inst;             /* device out [n_pixels] or NULL */

@@ -367,8 +367,8 @@ static rc_status prep_plain(const rc_scene* scene, const rc_render_args* a, void
         return fail(RC_ERR_INVALID_ARG, w + ": cam_pos, cam_quat, intr and depth are required");
     if (scene->n_links > 0 && (!a->link_pos || !a->link_quat))
         return fail(RC_ERR_INVALID_ARG, w + ": link_pos and link_quat are required with links");
-    if (!(a->far_plane > 0.0f) || !std::isfinite(a->far_plane))
-        return fail(RC_ERR_INVALID_ARG, w + ": far_plane must be finite and > 0");
+    if (!(a->far_plane > 0.0f) || !(a->far_plane <= kMaxFar))
+        return fail(RC_ERR_INVALID_ARG, w + ": far_plane must be in (0, 1e20]");
     if (a->depth_mode != RC_DEPTH_PLANAR && a->depth_mode != RC_DEPTH_RANGE)
         return fail(RC_ERR_INVALID_ARG, w + ": unknown depth_mode");
     if (!cam_rand_ok(a->cam_rand))
@@ -557,8 +557,8 @@ static rc_status prep_batched(const rc_scene* scene, const rc_batch_args* a, voi
         return fail(RC_ERR_INVALID_ARG, w + ": max_width and max_height must be in [1, 65535]");
     if (scene->n_links > 0 && (!a->link_pos || !a->link_quat))
         return fail(RC_ERR_INVALID_ARG, w + ": link_pos and link_quat are required with links");
-    if (!(a->far_plane > 0.0f) || !std::isfinite(a->far_plane))
-        return fail(RC_ERR_INVALID_ARG, w + ": far_plane must be finite and > 0");
+    if (!(a->far_plane > 0.0f) || !(a->far_plane <= kMaxFar))
+        return fail(RC_ERR_INVALID_ARG, w + ": far_plane must be in (0, 1e20]");
     if (a->depth_mode != RC_DEPTH_PLANAR && a->depth_mode != RC_DEPTH_RANGE)
         return fail(RC_ERR_INVALID_ARG, w + ": unknown depth_mode");
     if (!cam_rand_ok(a->cam_rand))

@@ -65,6 +65,7 @@ constexpr int kWavesPerBlock = 1;
 constexpr int kMaxLinks = 64;
 constexpr int kMaxDepth = 64;          // bits in the traversal trail
 constexpr float kFarBox = 1.0e30f;               // the unreachable box (a far point)
+constexpr float kMaxFar = 1.0e20f;               // largest far plane: rays end far short of kFarBox
 constexpr float kPadRel = 9.5367431640625e-07f;  // 2^-20, outward box padding
 constexpr float kPadAbs = 1.0e-5f;               // metres
 constexpr float kInstPadRel = 9.5367431640625e-07f;

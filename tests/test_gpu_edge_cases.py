@@ -191,7 +191,7 @@ def test_render_rejects_bad_arguments_and_leaves_outputs():
     bad = [dict(width=0), dict(height=0), dict(n_env=0), dict(n_cam=-1), dict(width=65536),
            dict(n_env=1 << 20, width=65535, height=65535), dict(cam_pos=None), dict(intr=None),
            dict(depth=None), dict(link_pos=None), dict(far_plane=0.0), dict(far_plane=float("nan")),
-           dict(far_plane=float("inf")), dict(depth_mode=2)]
+           dict(far_plane=float("inf")), dict(far_plane=1e21), dict(depth_mode=2)]
     for ch in bad:
         assert call(**ch) == -1, ch
     assert L.rc_render(sc.handle, ctypes.byref(a), ctypes.c_void_p(ws.ptr), 64, None) == -2
