@@ -181,8 +181,8 @@ rc_status rc_render(const rc_scene* scene, const rc_render_args* args, void* ws,
  * without ws: the workspace is a static device array of the library, 32 MiB
  * per GPU, held from the library's first use on that GPU until the process
  * ends, and the call itself allocates nothing.  It holds the top level of up
- * to about 8,000 environments of 30 links and an exact-pass list of 2^17
- * rays (a render that hands more rays to the exact pass re-casts every pixel
+ * to about 7,200 environments of 30 links and two cameras and an exact-pass
+ * list of 2^17 rays (a render that hands more rays to the exact pass re-casts every pixel
  * exactly: correct, slower).  A render whose workspace would exceed 32 MiB
  * fails with RC_ERR_WORKSPACE before anything is enqueued.  The array of the
  * current device is used (the stream must belong to it), and every call on
