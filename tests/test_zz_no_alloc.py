@@ -46,7 +46,7 @@ def test_noalloc_rejects_renders_beyond_its_scratch():
     w = sg.robot_scene(1, 1, 4.0, 1, 16, 12, steps=1, label="noalloc-limit")
     sc = m.Scene(dev(w["terrain"]))
     sc.set_robot(dev(w["link_tri"]), w["link_off"].tolist())
-    E = 16384  # 16,384 top levels of 30 links need about 54 MB
+    E = 16384  # 16,384 top levels of 30 links need about 62 MB
     cam = dev(np.broadcast_to(w["cam_pos"], (E, 1, 3)))
     q = dev(np.broadcast_to(w["cam_quat"], (E, 1, 4)))
     K = dev(np.broadcast_to(w["intr"], (E, 1, 4)))
