@@ -869,7 +869,7 @@ def main():
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "4096 envs x 2 cams x 64x48, 30-link robots (15,360 link tris), "
-                               f"20x20-tile terrain ({w['terrain'].shape[0]} tris), "
+                               f"20x20-tile terrain ({w['terrain'].shape[0]} tris, binned-SAH hierarchy), "
                                "per-step pose rebuild + noise/dropout/latency",
                    "rays_per_step": rays, "wall_s": round(wall, 3),
                    "fast_pass_ms_median": round(statistics.median(fast_ms), 4),

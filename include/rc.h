@@ -29,8 +29,8 @@
  *    part of a scene is its pair of launch schedules (rc_set_render_config,
  *    rc_autotune), each stored as one word: a render reads a whole schedule,
  *    old or new, never a mix; the walk's stack cap (rc_set_walk_stack_limit)
- *    is one word too.  rc_robot_meshes and rc_scene_destroy must not
- *    overlap any other call on the same scene.
+ *    is one word too.  rc_robot_meshes, rc_scene_rebuild_sah and
+ *    rc_scene_destroy must not overlap any other call on the same scene.
  *  - Frames: quaternions are (x, y, z, w) and rotate local vectors to world;
  *    they are normalised before use.  A camera's optical frame has x right,
  *    y down, z forward.  Intrinsics are (fx, fy, cx, cy) in pixels; pixel
@@ -87,6 +87,31 @@ rc_status rc_scene_size(int64_t n_tri, size_t* ws_bytes);
  * UNSUPPORTED (a hierarchy deeper than 64 levels), DEVICE. */
 rc_status rc_scene_create(const float* tri, int64_t n_tri, void* ws, size_t ws_bytes,
                           rc_stream stream, rc_scene** out);
+
+/* Rebuild the terrain's hierarchy in place with a top-down binned
+ * surface-area-heuristic split (MacDonald and Booth 1990; 32 bins per axis
+ * over the centroid bounds, as in Wald 2007; one triangle per leaf), on the
+ * host: the static terrain of Sec. 3.2.2 is built once, so a build of higher
+ * quality than the Morton one pays for itself in every later ray.  The
+ * workspace layout, the triangles' ids and every render's results are the
+ * same; walks visit fewer records.  The Morton keys in the workspace then no
+ * longer follow the leaf order.  Reads the mesh back from the workspace,
+ * builds on the calling thread (about 1.6 s for 2M triangles), uploads the
+ * records, the leaf-order triangles and ids and rebuilds the 4-wide records
+ * on `stream`, and synchronises it.  Must not overlap any other call on the
+ * scene.  Errors: INVALID_ARG (NULL scene), UNSUPPORTED (the new hierarchy
+ * would be deeper than 64 levels; the scene is unchanged), DEVICE (after
+ * which the scene must be destroyed). */
+rc_status rc_scene_rebuild_sah(rc_scene* scene, rc_stream stream);
+
+/* The same builder on host arrays, for tests and offline use: n_tri >= 1
+ * triangles tri (host float [n_tri][3][3]) -> records (host float
+ * [max(n_tri - 1, 1)][16], the node record layout of rc_bvh_layout_of),
+ * tris_out (host float [n_tri][9], leaf order; must not alias tri), ids_out
+ * (host int32 [n_tri], input index of each leaf), depth (deepest record,
+ * root 0).  No device work.  Errors: INVALID_ARG. */
+rc_status rc_sah_build_host(const float* tri, int64_t n_tri, float* records, float* tris_out,
+                            int32_t* ids_out, int32_t* depth);
 
 /* Release the handle (not the caller's workspaces). NULL is a no-op. */
 rc_status rc_scene_destroy(rc_scene* scene);
@@ -585,7 +610,8 @@ typedef struct {
     int64_t node_offset;   /* byte offset in the workspace: node records, 64 B each */
     int64_t tri_offset;    /* byte offset: float [n_prim][9] triangles in leaf order */
     int64_t tri_id_offset; /* byte offset: int32 [n_prim] input index of each leaf */
-    int64_t key_offset;    /* byte offset: uint64 [n_prim] sorted Morton keys */
+    int64_t key_offset;    /* byte offset: uint64 [n_prim] sorted Morton keys (of the Morton
+                              build; not in leaf order after rc_scene_rebuild_sah) */
     int32_t max_depth;     /* deepest internal node (root = 0) */
     int32_t reserved;
     int64_t wide_offset;   /* byte offset: 4-wide records, 128 B each, one per node record */

@@ -12,7 +12,8 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librc.so")
-SOURCES = ["api.hip", "blas_build.hip", "tlas_build.hip", "raycast.hip", "post.hip", "server.hip"]
+SOURCES = ["api.hip", "blas_build.hip", "sah_build.hip", "tlas_build.hip", "raycast.hip", "post.hip",
+           "server.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

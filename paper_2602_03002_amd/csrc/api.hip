@@ -177,6 +177,49 @@ rc_status rc_scene_create(const float* tri, int64_t n_tri, void* ws, size_t ws_b
     return RC_OK;
 }
 
+rc_status rc_scene_rebuild_sah(rc_scene* scene, rc_stream stream) {
+    if (!scene) return fail(RC_ERR_INVALID_ARG, "rc_scene_rebuild_sah: NULL scene");
+    const BvhLayout& L = scene->terrain;
+    const int64_t n = L.n_prim, m = L.n_nodes;
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<float> tri((size_t)n * 9), tri_out((size_t)n * 9), rec((size_t)m * 16);
+    std::vector<int32_t> ids((size_t)n), ids_out((size_t)n);
+    // the leaf-order triangles and their input ids hold the whole mesh
+    hipError_t e = hipMemcpyAsync(tri.data(), scene->ws + L.tris, (size_t)n * 36, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(ids.data(), scene->ws + L.tri_id, (size_t)n * 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "rc_scene_rebuild_sah: read back");
+    const int32_t depth = sah_build_host(tri.data(), n, ids.data(), rec.data(), tri_out.data(),
+                                         ids_out.data());
+    if (depth < 0) return fail(RC_ERR_STATE, "rc_scene_rebuild_sah: empty terrain");
+    if (depth > kMaxDepth)
+        return fail(RC_ERR_UNSUPPORTED, "rc_scene_rebuild_sah: hierarchy depth " + std::to_string(depth) +
+                                            " exceeds 64 (scene unchanged)");
+    e = hipMemcpyAsync(scene->ws + L.nodes, rec.data(), (size_t)m * 64, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(scene->ws + L.tris, tri_out.data(), (size_t)n * 36, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(scene->ws + L.tri_id, ids_out.data(), (size_t)n * 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = launch_collapse4((const Node*)(scene->ws + L.nodes), m, (float4*)(scene->ws + L.wide), s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);  // the host arrays end with this call
+    if (e != hipSuccess) return hip_fail(e, "rc_scene_rebuild_sah: upload");
+    scene->terrain_depth = depth;
+    return RC_OK;
+}
+
+rc_status rc_sah_build_host(const float* tri, int64_t n_tri, float* records, float* tris_out,
+                            int32_t* ids_out, int32_t* depth) {
+    if (!tri || !records || !tris_out || !ids_out || !depth)
+        return fail(RC_ERR_INVALID_ARG, "rc_sah_build_host: NULL pointer");
+    if (n_tri < 1 || n_tri > (int64_t)0x7FFFFFFE)
+        return fail(RC_ERR_INVALID_ARG, "rc_sah_build_host: n_tri must be in [1, 2^31 - 2]");
+    if (tri == tris_out) return fail(RC_ERR_INVALID_ARG, "rc_sah_build_host: tris_out aliases tri");
+    *depth = sah_build_host(tri, n_tri, nullptr, records, tris_out, ids_out);
+    return RC_OK;
+}
+
 rc_status rc_scene_destroy(rc_scene* scene) {
     delete scene;
     return RC_OK;

@@ -396,6 +396,11 @@ __global__ void k_collapse4(const Node* __restrict__ nodes, int64_t n_nodes, flo
 
 }  // namespace
 
+hipError_t launch_collapse4(const Node* nodes, int64_t n_nodes, float4* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_collapse4, dim3(nblk(n_nodes)), dim3(kThreads), 0, s, nodes, n_nodes, out);
+    return hipGetLastError();
+}
+
 BvhLayout bvh_layout(int64_t n, size_t base) {
     BvhLayout L;
     L.n_prim = n;

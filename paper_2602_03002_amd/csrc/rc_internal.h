@@ -85,6 +85,15 @@ struct BvhLayout {
 
 BvhLayout bvh_layout(int64_t n, size_t base);
 
+// Binned-SAH binary hierarchy over n host triangles (sah_build.hip): writes
+// max(n - 1, 1) records (16 words each), the triangles in leaf order and
+// their ids (ids_in[p], or p when ids_in is NULL); returns the depth of the
+// deepest record (root 0), or -1 for n < 1.  tris_out must not alias tri.
+int32_t sah_build_host(const float* tri, int64_t n, const int32_t* ids_in, float* rec, float* tris_out,
+                       int32_t* ids_out);
+// 4-wide records of a built binary hierarchy (as the builders write them).
+hipError_t launch_collapse4(const Node* nodes, int64_t n_nodes, float4* out, hipStream_t s);
+
 // Host-side launchers (each returns a hipError_t of its enqueue).
 hipError_t launch_blas_build(const float* tri, int64_t n, char* ws, const BvhLayout& L,
                              hipStream_t s);

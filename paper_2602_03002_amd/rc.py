@@ -30,7 +30,7 @@ EXPORTED = [
     "rc_post_size", "rc_post_create", "rc_post_reset", "rc_postprocess", "rc_post_destroy",
     "rc_postprocess_words",
     "rc_downsample", "rc_heightmap",
-    "rc_bvh_layout_of",
+    "rc_bvh_layout_of", "rc_scene_rebuild_sah", "rc_sah_build_host",
     "rc_render_batched_size", "rc_render_batched", "rc_render_batched_status",
     "rc_get_render_config", "rc_set_render_config", "rc_autotune", "rc_set_walk_stack_limit",
     "rc_graph_capture_batched", "rc_graph_launch", "rc_graph_destroy",
@@ -188,6 +188,8 @@ def lib():
                                      vp, vp, vp, vp, vp]
         L.rc_post_destroy.argtypes = [vp]
         L.rc_bvh_layout_of.argtypes = [vp, i32, ctypes.POINTER(BvhLayout)]
+        L.rc_scene_rebuild_sah.argtypes = [vp, vp]
+        L.rc_sah_build_host.argtypes = [vp, i64, vp, vp, vp, ctypes.POINTER(i32)]
         L.rc_render_batched_size.argtypes = [vp, i32, i32, i64, ctypes.POINTER(sz)]
         L.rc_render_batched.argtypes = [vp, ctypes.POINTER(BatchArgs), vp, sz, vp]
         L.rc_render_batched_status.argtypes = [vp, ctypes.POINTER(BatchArgs), vp,
@@ -272,10 +274,28 @@ class Workspace:
         return self.buf[self.offset:self.offset + self.nbytes]
 
 
+def sah_build_host(tri):
+    """rc_sah_build_host on a host array [n][3][3] float32: (records [m][16]
+    float32 with int32 child/parent/sibling words, leaf-order triangles
+    [n][9], input ids [n], depth)."""
+    import numpy as np
+    t = np.ascontiguousarray(tri, np.float32).reshape(-1, 9)
+    n = t.shape[0]
+    rec = np.zeros((max(n - 1, 1), 16), np.float32)
+    tris = np.zeros((n, 9), np.float32)
+    ids = np.zeros(n, np.int32)
+    d = ctypes.c_int32()
+    p = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    check(lib().rc_sah_build_host(p(t), n, p(rec), p(tris), p(ids), ctypes.byref(d)))
+    return rec, tris, ids, d.value
+
+
 class Scene:
     """Terrain hierarchy (+ optional robot link hierarchies) resident on the device."""
 
-    def __init__(self, terrain, stream=None):
+    def __init__(self, terrain, stream=None, sah=True):
+        """sah: rebuild the terrain hierarchy with the binned SAH after the
+        Morton build (rc_scene_rebuild_sah); False keeps the Morton one."""
         terrain = _dev_f32(terrain, (terrain.shape[0], 3, 3), "terrain")
         L = lib()
         self.device = terrain.device
@@ -290,6 +310,8 @@ class Scene:
         self.n_links = 0
         self.robot_ws = None
         self._render_ws = {}
+        if sah:
+            check(L.rc_scene_rebuild_sah(h, _stream(stream)))
 
     def set_robot(self, link_tri, tri_offset, stream=None):
         L = lib()

@@ -28,9 +28,9 @@ def say(msg):
     print(msg, flush=True)
 
 
-def make_scene(w, step=0):
+def make_scene(w, step=0, sah=True):
     m = rc()
-    sc = m.Scene(dev(w["terrain"]))
+    sc = m.Scene(dev(w["terrain"]), sah=sah)
     B = int(w["link_off"].shape[0] - 1)
     if B > 0:
         sc.set_robot(dev(w["link_tri"]), w["link_off"].tolist())
@@ -96,8 +96,41 @@ def test_terrain_bvh_bit_exact(which):
         tri = np.array([[[0, 0, 0], [1, 1, 1], [2, 2, 2]]], np.float32)
     else:
         tri = np.array([[[0, 0, 0], [1, 0, 0], [0, 1, 0]]], np.float32)
-    sc = rc().Scene(dev(tri))
+    sc = rc().Scene(dev(tri), sah=False)
     check_bvh(ws_bytes(sc.ws), sc.bvh_layout(-1), tri)
+
+
+@pytest.mark.parametrize("which", ["tiles2", "single", "degenerate"])
+def test_sah_rebuild_matches_the_host_builder(which):
+    """rc_scene_rebuild_sah: the terrain's records, leaf-order triangles, ids
+    and 4-wide records equal the host builder's output over the Morton
+    build's leaf order (ids mapped through it), bit for bit."""
+    say(f"[bvh] SAH rebuild {which}")
+    if which == "tiles2":
+        tri = sg.TileTerrain(2).triangles()
+    elif which == "degenerate":
+        t = sg.TileTerrain(1).triangles()[:5000]
+        p = t[::97, 0]
+        tri = np.concatenate([t, np.stack([p, p, p], 1)], 0).astype(np.float32)
+    else:
+        tri = np.array([[[0, 0, 0], [1, 0, 0], [0, 1, 0]]], np.float32)
+    m = rc()
+    s0 = m.Scene(dev(tri), sah=False)
+    b0, l0 = ws_bytes(s0.ws), s0.bvh_layout(-1)
+    n, nn = l0.n_prim, l0.n_nodes
+    t0 = b0[l0.tri_offset:l0.tri_offset + 36 * n].view(np.float32).reshape(n, 9)
+    i0 = b0[l0.tri_id_offset:l0.tri_id_offset + 4 * n].view(np.int32)
+    rec, tris, ids, depth = m.sah_build_host(t0.reshape(n, 3, 3))
+    s1 = m.Scene(dev(tri))
+    b1, l1 = ws_bytes(s1.ws), s1.bvh_layout(-1)
+    assert (l1.node_offset, l1.wide_offset, l1.tri_offset) == (l0.node_offset, l0.wide_offset, l0.tri_offset)
+    got = b1[l1.node_offset:l1.node_offset + 64 * nn].view(np.uint32).reshape(nn, 16)
+    assert np.array_equal(got, rec.view(np.uint32)), "records"
+    assert np.array_equal(b1[l1.tri_offset:l1.tri_offset + 36 * n].view(np.float32).reshape(n, 9), tris)
+    assert np.array_equal(b1[l1.tri_id_offset:l1.tri_id_offset + 4 * n].view(np.int32), i0[ids])
+    wide = b1[l1.wide_offset:l1.wide_offset + 128 * nn].view(np.uint32).reshape(nn, 32)
+    assert np.array_equal(wide, lbvh.collapse4(rec).view(np.uint32)), "4-wide records"
+    assert l1.max_depth == depth
 
 
 def test_link_bvh_bit_exact():
@@ -199,11 +232,12 @@ def test_small_plain_case_full_frame():
     assert np.all(i == 0)
 
 
-@pytest.mark.parametrize("depth_mode", [0, 1])
-def test_robot_scene_full_frame_ragged(depth_mode):
-    say(f"[render] 4 envs x 2 cams 37x29 (ragged tiles), 2x2 tiles, 30 links, mode {depth_mode}")
+@pytest.mark.parametrize("depth_mode,sah", [(0, True), (1, True), (0, False)])
+def test_robot_scene_full_frame_ragged(depth_mode, sah):
+    say(f"[render] 4 envs x 2 cams 37x29 (ragged tiles), 2x2 tiles, 30 links, mode {depth_mode}, "
+        f"{'SAH' if sah else 'Morton'} terrain hierarchy")
     w = sg.robot_scene(2, 2, 4.0, 2, 37, 29, steps=2, label="parity-ragged")
-    sc = make_scene(w)
+    sc = make_scene(w, sah=sah)
     for step in (0, 1):
         d, i, t = render(sc, w, step, depth_mode)
         ref = oracle_render(w, step, depth_mode)
