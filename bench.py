@@ -68,7 +68,7 @@ SQ_COUNTERS = os.path.join(ROOT, "profiles", "k_render_4096x2_64x48_sq_counters.
 L2_COUNTERS = os.path.join(ROOT, "profiles", "k_render_4096x2_64x48_l2_counters.txt")
 # the fast pass and the sources of the records it reads
 KERNEL_SRC = [os.path.join(ROOT, "paper_2602_03002_amd", "csrc", f)
-              for f in ("raycast.hip", "rc_internal.h", "blas_build.hip", "tlas_build.hip")]
+              for f in ("raycast.hip", "rc_internal.h", "blas_build.hip", "sah_build.hip", "tlas_build.hip")]
 
 
 def kernel_sha():

@@ -88,21 +88,23 @@ rc_status rc_scene_size(int64_t n_tri, size_t* ws_bytes);
 rc_status rc_scene_create(const float* tri, int64_t n_tri, void* ws, size_t ws_bytes,
                           rc_stream stream, rc_scene** out);
 
-/* Rebuild the terrain's hierarchy in place with a top-down binned
+/* Rebuild hierarchies of the scene in place with a top-down binned
  * surface-area-heuristic split (MacDonald and Booth 1990; 32 bins per axis
  * over the centroid bounds, as in Wald 2007; one triangle per leaf), on the
- * host: the static terrain of Sec. 3.2.2 is built once, so a build of higher
- * quality than the Morton one pays for itself in every later ray.  The
- * workspace layout, the triangles' ids and every render's results are the
- * same; walks visit fewer records.  The Morton keys in the workspace then no
- * longer follow the leaf order.  Reads the mesh back from the workspace,
- * builds on the calling thread (about 1.6 s for 2M triangles), uploads the
- * records, the leaf-order triangles and ids and rebuilds the 4-wide records
- * on `stream`, and synchronises it.  Must not overlap any other call on the
- * scene.  Errors: INVALID_ARG (NULL scene), UNSUPPORTED (the new hierarchy
- * would be deeper than 64 levels; the scene is unchanged), DEVICE (after
- * which the scene must be destroyed). */
-rc_status rc_scene_rebuild_sah(rc_scene* scene, rc_stream stream);
+ * host: the terrain (which & 1) and the link meshes present (which & 2).
+ * Both are static (Sec. 3.2.2: built once, the links in their local frames),
+ * so a build of higher quality than the Morton one pays for itself in every
+ * later ray.  The workspace layout, the triangles' ids and every render's
+ * results are the same; walks visit fewer records.  The Morton keys in the
+ * workspace then no longer follow the leaf order, and a link's directory box
+ * stays the Morton root's (a bound of the same mesh).  Reads each mesh back
+ * from its workspace, builds on the calling thread (about 1.6 s for 2M
+ * triangles), uploads the records, leaf-order triangles and ids and rebuilds
+ * the 4-wide records on `stream`, and synchronises it.  Must not overlap any
+ * other call on the scene.  Errors: INVALID_ARG (NULL scene, which not in
+ * 1..3), UNSUPPORTED (a hierarchy would be deeper than 64 levels; that one
+ * is unchanged), DEVICE (after which the scene must be destroyed). */
+rc_status rc_scene_rebuild_sah(rc_scene* scene, int32_t which, rc_stream stream);
 
 /* The same builder on host arrays, for tests and offline use: n_tri >= 1
  * triangles tri (host float [n_tri][3][3]) -> records (host float

@@ -177,35 +177,56 @@ rc_status rc_scene_create(const float* tri, int64_t n_tri, void* ws, size_t ws_b
     return RC_OK;
 }
 
-rc_status rc_scene_rebuild_sah(rc_scene* scene, rc_stream stream) {
-    if (!scene) return fail(RC_ERR_INVALID_ARG, "rc_scene_rebuild_sah: NULL scene");
-    const BvhLayout& L = scene->terrain;
+// Binned-SAH rebuild of one hierarchy whose arrays start at `base` (layout L).
+static rc_status rebuild_sah_one(char* base, const BvhLayout& L, int32_t* depth_out, hipStream_t s,
+                                 const char* who) {
     const int64_t n = L.n_prim, m = L.n_nodes;
-    hipStream_t s = (hipStream_t)stream;
     std::vector<float> tri((size_t)n * 9), tri_out((size_t)n * 9), rec((size_t)m * 16);
     std::vector<int32_t> ids((size_t)n), ids_out((size_t)n);
     // the leaf-order triangles and their input ids hold the whole mesh
-    hipError_t e = hipMemcpyAsync(tri.data(), scene->ws + L.tris, (size_t)n * 36, hipMemcpyDeviceToHost, s);
+    hipError_t e = hipMemcpyAsync(tri.data(), base + L.tris, (size_t)n * 36, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(ids.data(), scene->ws + L.tri_id, (size_t)n * 4, hipMemcpyDeviceToHost, s);
+        e = hipMemcpyAsync(ids.data(), base + L.tri_id, (size_t)n * 4, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return hip_fail(e, "rc_scene_rebuild_sah: read back");
+    if (e != hipSuccess) return hip_fail(e, (std::string(who) + ": read back").c_str());
     const int32_t depth = sah_build_host(tri.data(), n, ids.data(), rec.data(), tri_out.data(),
                                          ids_out.data());
-    if (depth < 0) return fail(RC_ERR_STATE, "rc_scene_rebuild_sah: empty terrain");
+    if (depth < 0) return fail(RC_ERR_STATE, std::string(who) + ": empty hierarchy");
     if (depth > kMaxDepth)
-        return fail(RC_ERR_UNSUPPORTED, "rc_scene_rebuild_sah: hierarchy depth " + std::to_string(depth) +
-                                            " exceeds 64 (scene unchanged)");
-    e = hipMemcpyAsync(scene->ws + L.nodes, rec.data(), (size_t)m * 64, hipMemcpyHostToDevice, s);
+        return fail(RC_ERR_UNSUPPORTED, std::string(who) + ": hierarchy depth " + std::to_string(depth) +
+                                            " exceeds 64 (hierarchy unchanged)");
+    e = hipMemcpyAsync(base + L.nodes, rec.data(), (size_t)m * 64, hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(scene->ws + L.tris, tri_out.data(), (size_t)n * 36, hipMemcpyHostToDevice, s);
+        e = hipMemcpyAsync(base + L.tris, tri_out.data(), (size_t)n * 36, hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(scene->ws + L.tri_id, ids_out.data(), (size_t)n * 4, hipMemcpyHostToDevice, s);
+        e = hipMemcpyAsync(base + L.tri_id, ids_out.data(), (size_t)n * 4, hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
-        e = launch_collapse4((const Node*)(scene->ws + L.nodes), m, (float4*)(scene->ws + L.wide), s);
+        e = launch_collapse4((const Node*)(base + L.nodes), m, (float4*)(base + L.wide), s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);  // the host arrays end with this call
-    if (e != hipSuccess) return hip_fail(e, "rc_scene_rebuild_sah: upload");
-    scene->terrain_depth = depth;
+    if (e != hipSuccess) return hip_fail(e, (std::string(who) + ": upload").c_str());
+    *depth_out = depth;
+    return RC_OK;
+}
+
+rc_status rc_scene_rebuild_sah(rc_scene* scene, int32_t which, rc_stream stream) {
+    if (!scene) return fail(RC_ERR_INVALID_ARG, "rc_scene_rebuild_sah: NULL scene");
+    if (which < 1 || which > 3) return fail(RC_ERR_INVALID_ARG, "rc_scene_rebuild_sah: which must be 1, 2 or 3");
+    hipStream_t s = (hipStream_t)stream;
+    if (which & 1) {
+        int32_t d = 0;
+        const rc_status st = rebuild_sah_one(scene->ws, scene->terrain, &d, s, "rc_scene_rebuild_sah (terrain)");
+        if (st != RC_OK) return st;
+        scene->terrain_depth = d;
+    }
+    if (which & 2) {
+        for (int32_t b = 0; b < scene->n_links; ++b) {
+            int32_t d = 0;
+            const rc_status st = rebuild_sah_one(scene->robot_ws, scene->links[b], &d, s,
+                                                 "rc_scene_rebuild_sah (link)");
+            if (st != RC_OK) return st;
+            scene->link_depth[b] = d;
+        }
+    }
     return RC_OK;
 }
 

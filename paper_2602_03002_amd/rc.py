@@ -188,7 +188,7 @@ def lib():
                                      vp, vp, vp, vp, vp]
         L.rc_post_destroy.argtypes = [vp]
         L.rc_bvh_layout_of.argtypes = [vp, i32, ctypes.POINTER(BvhLayout)]
-        L.rc_scene_rebuild_sah.argtypes = [vp, vp]
+        L.rc_scene_rebuild_sah.argtypes = [vp, i32, vp]
         L.rc_sah_build_host.argtypes = [vp, i64, vp, vp, vp, ctypes.POINTER(i32)]
         L.rc_render_batched_size.argtypes = [vp, i32, i32, i64, ctypes.POINTER(sz)]
         L.rc_render_batched.argtypes = [vp, ctypes.POINTER(BatchArgs), vp, sz, vp]
@@ -294,8 +294,9 @@ class Scene:
     """Terrain hierarchy (+ optional robot link hierarchies) resident on the device."""
 
     def __init__(self, terrain, stream=None, sah=True):
-        """sah: rebuild the terrain hierarchy with the binned SAH after the
-        Morton build (rc_scene_rebuild_sah); False keeps the Morton one."""
+        """sah: rebuild the terrain's (and later the links') hierarchies with
+        the binned SAH after the Morton build (rc_scene_rebuild_sah); False
+        keeps the Morton ones."""
         terrain = _dev_f32(terrain, (terrain.shape[0], 3, 3), "terrain")
         L = lib()
         self.device = terrain.device
@@ -310,8 +311,9 @@ class Scene:
         self.n_links = 0
         self.robot_ws = None
         self._render_ws = {}
+        self.sah = sah
         if sah:
-            check(L.rc_scene_rebuild_sah(h, _stream(stream)))
+            check(L.rc_scene_rebuild_sah(h, 1, _stream(stream)))
 
     def set_robot(self, link_tri, tri_offset, stream=None):
         L = lib()
@@ -325,6 +327,8 @@ class Scene:
             check(L.rc_robot_meshes(self.handle, _ptr(link_tri), off, nb,
                                     ctypes.c_void_p(self.robot_ws.ptr), size.value,
                                     _stream(stream)))
+            if self.sah:
+                check(L.rc_scene_rebuild_sah(self.handle, 2, _stream(stream)))
         else:
             check(L.rc_robot_meshes(self.handle, None, off, 0, None, 0, _stream(stream)))
             self.robot_ws = None

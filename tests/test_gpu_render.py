@@ -137,11 +137,38 @@ def test_link_bvh_bit_exact():
     say("[bvh] 30 link meshes")
     rob = sg.Robot()
     lt, off = rob.link_triangles()
-    sc = rc().Scene(dev(sg.small_plain_case()["terrain"]))
+    sc = rc().Scene(dev(sg.small_plain_case()["terrain"]), sah=False)
     sc.set_robot(dev(lt), off.tolist())
     buf = ws_bytes(sc.robot_ws)
     for b in (0, 13, 29):
         check_bvh(buf, sc.bvh_layout(b), lt[off[b]:off[b + 1]])
+
+
+def test_link_sah_rebuild_matches_the_host_builder():
+    """The link meshes' hierarchies after rc_scene_rebuild_sah (which = 2, as
+    Scene.set_robot does with sah=True) against the host builder over the
+    Morton build's leaf order, bit for bit."""
+    say("[bvh] SAH rebuild of 30 link meshes")
+    rob = sg.Robot()
+    lt, off = rob.link_triangles()
+    terr = dev(sg.small_plain_case()["terrain"])
+    m = rc()
+    s0 = m.Scene(terr, sah=False)
+    s0.set_robot(dev(lt), off.tolist())
+    s1 = m.Scene(terr)
+    s1.set_robot(dev(lt), off.tolist())
+    b0, b1 = ws_bytes(s0.robot_ws), ws_bytes(s1.robot_ws)
+    for b in (0, 13, 29):
+        l0, l1 = s0.bvh_layout(b), s1.bvh_layout(b)
+        n, nn = l0.n_prim, l0.n_nodes
+        t0 = b0[l0.tri_offset:l0.tri_offset + 36 * n].view(np.float32).reshape(n, 3, 3)
+        i0 = b0[l0.tri_id_offset:l0.tri_id_offset + 4 * n].view(np.int32)
+        rec, tris, ids, depth = m.sah_build_host(t0)
+        assert np.array_equal(b1[l1.node_offset:l1.node_offset + 64 * nn].view(np.uint32).reshape(nn, 16),
+                              rec.view(np.uint32)), f"link {b} records"
+        assert np.array_equal(b1[l1.tri_offset:l1.tri_offset + 36 * n].view(np.float32).reshape(n, 9), tris)
+        assert np.array_equal(b1[l1.tri_id_offset:l1.tri_id_offset + 4 * n].view(np.int32), i0[ids])
+        assert l1.max_depth == depth
 
 
 def _align(x, a=256):

@@ -115,4 +115,4 @@ def test_rejects_bad_arguments():
     assert L.rc_sah_build_host(p, 0, p, p, p, ctypes.byref(d)) == -1
     assert L.rc_sah_build_host(None, 1, p, p, p, ctypes.byref(d)) == -1
     assert L.rc_sah_build_host(p, 1, p, p, p, ctypes.byref(d)) == -1  # tris_out aliases tri
-    assert L.rc_scene_rebuild_sah(None, None) == -1
+    assert L.rc_scene_rebuild_sah(None, 1, None) == -1
