@@ -58,11 +58,18 @@ void put_box(float* dst, const HBox& b) {
     }
 }
 
+// Bin of a centroid coordinate; a non-finite coordinate (NaN, or an infinite
+// extent) falls into bin 0 instead of an undefined conversion.
+int bin_of(float c, float lo, float scale) {
+    const float f = (c - lo) * scale;
+    if (!(f >= 0.0f)) return 0;
+    return f >= (float)kBins ? kBins - 1 : (int)f;
+}
+
 struct Task {
     int64_t b, e;  // range of the index array
     int32_t node;  // its record
     int32_t depth;
-    HBox box;      // union of its triangles' boxes
 };
 
 }  // namespace
@@ -99,13 +106,10 @@ int32_t sah_build_host(const float* tri, int64_t n, const int32_t* ids_in, float
         ri[14] = -1;
         ri[15] = -1;
     } else {
-        HBox all;
-        for (const HBox& b : pb) all.grow(b);
         std::vector<Task> stack;
-        stack.push_back({0, n, 0, 0, all});
+        stack.push_back({0, n, 0, 0});
         ri[14] = -1;
         ri[15] = -1;
-        std::vector<int32_t> scratch;
         while (!stack.empty()) {
             const Task t = stack.back();
             stack.pop_back();
@@ -130,7 +134,7 @@ int32_t sah_build_host(const float* tri, int64_t n, const int32_t* ids_in, float
                 int64_t cnt[kBins] = {};
                 for (int64_t k = t.b; k < t.e; ++k) {
                     const int32_t p = idx[(size_t)k];
-                    const int j = std::min((int)((cen[3 * (size_t)p + a] - cb.lo[a]) * scale), kBins - 1);
+                    const int j = bin_of(cen[3 * (size_t)p + a], cb.lo[a], scale);
                     bin[j].grow(pb[(size_t)p]);
                     ++cnt[j];
                 }
@@ -164,9 +168,7 @@ int32_t sah_build_host(const float* tri, int64_t n, const int32_t* ids_in, float
             if (best_axis >= 0) {
                 const int a = best_axis;
                 const float scale = (float)kBins / (cb.hi[a] - cb.lo[a]);
-                auto left = [&](int32_t p) {
-                    return std::min((int)((cen[3 * (size_t)p + a] - cb.lo[a]) * scale), kBins - 1) <= best_bin;
-                };
+                auto left = [&](int32_t p) { return bin_of(cen[3 * (size_t)p + a], cb.lo[a], scale) <= best_bin; };
                 m = std::stable_partition(idx.begin() + t.b, idx.begin() + t.e, left) - idx.begin();
             } else {  // every centroid coincides: halve the range
                 m = t.b + s / 2;
@@ -192,8 +194,8 @@ int32_t sah_build_host(const float* tri, int64_t n, const int32_t* ids_in, float
                 ri[16 * (int64_t)c1 + 15] = c0;
             }
             // right first, so the left subtree is finished first (any order works)
-            if (c1 >= 0) stack.push_back({m, t.e, c1, t.depth + 1, best_r});
-            if (c0 >= 0) stack.push_back({t.b, m, c0, t.depth + 1, best_l});
+            if (c1 >= 0) stack.push_back({m, t.e, c1, t.depth + 1});
+            if (c0 >= 0) stack.push_back({t.b, m, c0, t.depth + 1});
         }
     }
     for (int64_t k = 0; k < n; ++k) {

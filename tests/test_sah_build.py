@@ -116,3 +116,26 @@ def test_rejects_bad_arguments():
     assert L.rc_sah_build_host(None, 1, p, p, p, ctypes.byref(d)) == -1
     assert L.rc_sah_build_host(p, 1, p, p, p, ctypes.byref(d)) == -1  # tris_out aliases tri
     assert L.rc_scene_rebuild_sah(None, 1, None) == -1
+
+
+def test_non_finite_coordinates_do_not_break_the_build():
+    """A vertex that is NaN or infinite must not derail the binning: the
+    build still places every triangle once and boxes the finite ones."""
+    tri = sg.TileTerrain(1).triangles()[:500].copy()
+    tri[7, 1, 0] = np.nan
+    tri[11, 2, 2] = np.inf
+    tri[13, 0, 1] = -np.inf
+    rec, tris, ids, depth = m.sah_build_host(tri)
+    assert np.array_equal(np.sort(ids), np.arange(500)) and 0 < depth < 64
+    order, below = walk(rec)
+    assert order == list(range(500))
+    ri = rec.view(np.int32)
+    finite = np.isfinite(tris.reshape(-1, 9)).all(1)
+    v = tris.reshape(-1, 3, 3)
+    for i in range(499):
+        for h in (0, 1):
+            c = ri[i, 12 + h]
+            ks = [k for k in (below[c][0] + below[c][1] if c >= 0 else [~c]) if finite[k]]
+            if ks and np.all(np.isfinite(rec[i, 6 * h:6 * h + 6])) and rec[i, 6 * h] != FAR:
+                lo, hi = rec[i, 6 * h:6 * h + 6:2], rec[i, 6 * h + 1:6 * h + 6:2]
+                assert np.all(v[ks].min((0, 1)) > lo) and np.all(v[ks].max((0, 1)) < hi), (i, h)
