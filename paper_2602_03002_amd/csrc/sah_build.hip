@@ -16,10 +16,13 @@
 // at 0: a node over s leaves heads s - 1 internal nodes, so the right child
 // of node i over [b, e) split at m is i + (m - b) without any ordering pass,
 // and leaves are numbered by their final position.  Deterministic: stable
-// partitions, first minimum in (axis, bin) order.
+// partitions, first minimum in (axis, bin) order; below the top levels the
+// subtrees are built on up to 16 threads, each in its own index range and
+// records, so the result does not depend on the threads.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <thread>
 #include <vector>
 
 #include "rc_internal.h"
@@ -106,14 +109,12 @@ int32_t sah_build_host(const float* tri, int64_t n, const int32_t* ids_in, float
         ri[14] = -1;
         ri[15] = -1;
     } else {
-        std::vector<Task> stack;
-        stack.push_back({0, n, 0, 0});
         ri[14] = -1;
         ri[15] = -1;
-        while (!stack.empty()) {
-            const Task t = stack.back();
-            stack.pop_back();
-            max_depth = std::max(max_depth, t.depth);
+        // One task: split its range, write its record, hand its internal
+        // children on.  Tasks touch disjoint ranges and records, so subtrees
+        // can be built on separate threads with the same result.
+        auto split = [&](const Task& t, std::vector<Task>& out) {
             const int64_t s = t.e - t.b;
             HBox cb;
             for (int64_t k = t.b; k < t.e; ++k) {
@@ -194,9 +195,50 @@ int32_t sah_build_host(const float* tri, int64_t n, const int32_t* ids_in, float
                 ri[16 * (int64_t)c1 + 15] = c0;
             }
             // right first, so the left subtree is finished first (any order works)
-            if (c1 >= 0) stack.push_back({m, t.e, c1, t.depth + 1});
-            if (c0 >= 0) stack.push_back({t.b, m, c0, t.depth + 1});
+            if (c1 >= 0) out.push_back({m, t.e, c1, t.depth + 1});
+            if (c0 >= 0) out.push_back({t.b, m, c0, t.depth + 1});
+        };
+        auto run = [&](std::vector<Task> stack, int32_t* depth) {
+            while (!stack.empty()) {
+                const Task t = stack.back();
+                stack.pop_back();
+                *depth = std::max(*depth, t.depth);
+                split(t, stack);
+            }
+        };
+        // the top of the hierarchy on this thread, until the pending
+        // subtrees are small enough to share out
+        const int64_t grain = std::max<int64_t>(n / 64, 4096);
+        std::vector<Task> pending{{0, n, 0, 0}}, big;
+        for (;;) {
+            std::vector<Task> next;
+            bool any = false;
+            for (const Task& t : pending) {
+                if (t.e - t.b > grain) {
+                    max_depth = std::max(max_depth, t.depth);
+                    split(t, next);
+                    any = true;
+                } else {
+                    next.push_back(t);
+                }
+            }
+            pending.swap(next);
+            if (!any) break;
         }
+        const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+        const unsigned nt = (unsigned)std::min<size_t>(hw, pending.size());
+        std::vector<std::vector<Task>> share(nt);
+        for (size_t k = 0; k < pending.size(); ++k) share[k % nt].push_back(pending[k]);
+        std::vector<int32_t> depth(nt, 0);
+        std::vector<std::thread> pool;
+        try {
+            for (unsigned k = 1; k < nt; ++k) pool.emplace_back(run, share[k], &depth[k]);
+        } catch (...) {  // no threads to be had: the rest on this one
+            for (unsigned k = (unsigned)pool.size() + 1; k < nt; ++k) run(share[k], &depth[k]);
+        }
+        if (nt > 0) run(share[0], &depth[0]);
+        for (std::thread& th : pool) th.join();
+        for (int32_t d : depth) max_depth = std::max(max_depth, d);
     }
     for (int64_t k = 0; k < n; ++k) {
         const int32_t p = idx[(size_t)k];
