@@ -124,7 +124,7 @@ using namespace rc;
 
 extern "C" {
 
-int32_t rc_version(void) { return 10000; }
+int32_t rc_version(void) { return 10100; }
 
 const char* rc_status_string(rc_status st) {
     switch (st) {
